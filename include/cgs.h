@@ -1,0 +1,232 @@
+/*
+ * cgs.h -- C-ABI of libcgs, the MI355X (gfx950) hot path of codebook-indexed,
+ * differentiable tile-based 3D Gaussian splatting.
+ *
+ * Problem statement (paper Sec. 4.1-4.4): the state is S = {G, C}; every
+ * Gaussian g_i holds a mean p_i and integer indices into the codebooks C
+ * (SR: scale + quaternion rows, SH: spherical-harmonic colour rows; Sec. 4.1,
+ * Fig. 4).  One training step renders I_P(G, C) for a camera pose P (Sec. 4.2,
+ * posterior) and needs the gradient of the loss with respect to every
+ * differentiable parameter S_diff -- all parameters except the indices
+ * (Sec. 4.4, parameter update).  The render is Eq. 1-3 of Sec. 2.1.
+ *
+ * Conventions for every call:
+ *  - Pointers documented "device" are HIP device memory owned by the caller;
+ *    the library never allocates, frees or retains device memory.  Structs
+ *    passed by pointer (cgs_batch, cgs_scene, cgs_camera, cgs_scene_grads)
+ *    live in host memory and are read during the call only.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
+ *    the call returns without synchronising.  No host<->device copies are
+ *    made, so calls may be captured into a HIP graph.
+ *  - The return value covers host-side validation only (null pointers,
+ *    negative sizes, unsupported options, workspace too small, launch
+ *    failure).  Conditions found on the device are written to the caller's
+ *    device array `d_info` (int64[4]): d_info[0] = status (CGS_OK or
+ *    CGS_ECAPACITY), d_info[1] = number of (tile, Gaussian) instances the
+ *    view batch needed.  Read it when convenient.
+ *  - Gradients are overwritten, never accumulated.
+ *  - Floating-point results are FP32; codebooks may be stored in FP32 or BF16.
+ *  - All entry points are thread-compatible: concurrent calls must use
+ *    different workspaces.
+ */
+#ifndef CGS_H
+#define CGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CGS_OK = 0,
+    CGS_EINVAL = -1,        /* bad argument (null pointer, negative size, bad stride, ...) */
+    CGS_EUNSUPPORTED = -2,  /* valid but not supported by this build (e.g. sh_degree > 3) */
+    CGS_ECAPACITY = -3,     /* instance capacity too small (device-side, via d_info) */
+    CGS_EHIP = -4,          /* a HIP launch failed */
+    CGS_EWORKSPACE = -5     /* workspace too small */
+} cgs_status;
+
+typedef enum { CGS_F32 = 0, CGS_BF16 = 1 } cgs_dtype;
+
+enum { CGS_MAX_VIEWS = 64, CGS_MAX_SCENES = 64, CGS_TILE = 16 };
+
+/* Pinhole camera (the "camera pose P" of Sec. 2.1 / 4.2).  OpenCV axes:
+ * x right, y down, z forward.  Pixel (x, y) samples image-plane point (x, y).
+ * Rt: world->camera rotation and translation, row-major 3x4 [R | t].
+ * campos: camera centre in world space (direction of view-dependent colour).
+ * bg: background colour added with the final transmittance. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float Rt[12];
+    float campos[3];
+    float bg[3];
+} cgs_camera;
+
+/* A column window into a codebook (device memory, row-major).  Element (r, c)
+ * of the window is ptr[r * row_stride + col0 + c] of type dtype. */
+typedef struct {
+    const void* ptr;
+    int32_t dtype;       /* cgs_dtype */
+    int32_t row_stride;  /* elements between consecutive rows */
+    int64_t rows;        /* codebook size |SR| or |SH| */
+    int32_t col0;
+    int32_t pad_;
+} cgs_cb_view;
+
+/* One scene S = {G, C} (Sec. 4.1).
+ * SR window columns: log-scale[3], quaternion (w,x,y,z)[4]; with
+ *   opacity_mode == 1 column 7 of the SR window is the opacity logit.
+ * SH window columns: 3 (sh_degree+1)^2 coefficients, coefficient-major and
+ *   RGB-minor (c[j*3 + ch], j = l*l + l + m, real orthonormal harmonics with
+ *   the Condon-Shortley phase).
+ * Fused single-codebook layout [ls3 q4 logit1 sh...] with one index: idx_sr ==
+ *   idx_sh, both windows on the same array, sr.col0 = 0, sh.col0 = 8,
+ *   opacity_mode = 1.  The paper's two-codebook layout: separate windows and
+ *   index arrays, per-Gaussian opacity (opacity_mode = 0). */
+typedef struct {
+    int64_t n;                    /* number of Gaussians (>= 0) */
+    int32_t sh_degree;            /* 0..3, the same for every scene of a batch */
+    int32_t opacity_mode;         /* 0: opacity_logit array, 1: SR window column 7 */
+    const float* means;           /* device [n,3] */
+    const int32_t* idx_sr;        /* device [n], values in [0, sr.rows) */
+    const int32_t* idx_sh;        /* device [n], values in [0, sh.rows) */
+    cgs_cb_view sr;
+    cgs_cb_view sh;
+    const float* opacity_logit;   /* device [n] when opacity_mode == 0, else NULL */
+} cgs_scene;
+
+/* Gradient outputs of one scene (device memory, FP32, overwritten).
+ * sr / sh use the same window geometry as the scene's codebook windows
+ * (rows x row_stride arrays, the window's columns written, others untouched).
+ * opacity: [n] when opacity_mode == 0 (else unused). */
+typedef struct {
+    float* means;                 /* [n,3] */
+    float* sr; int32_t sr_stride; int32_t sr_col0;
+    float* sh; int32_t sh_stride; int32_t sh_col0;
+    float* opacity;
+} cgs_scene_grads;
+
+/* Launch schedule knobs; zero-initialised fields take the defaults. */
+typedef struct {
+    int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup; default 4 */
+    int32_t tile_order;              /* 0: row-major tiles, 1: XCD-grouped order */
+    int32_t reserved[6];
+} cgs_schedule;
+
+/* A batch of views over one or more scenes, rendered by one call. */
+typedef struct {
+    const cgs_scene* scenes;      /* host array [n_scenes] */
+    int32_t n_scenes;             /* 1..CGS_MAX_SCENES */
+    int32_t n_views;              /* 1..CGS_MAX_VIEWS */
+    const cgs_camera* cameras;    /* host array [n_views] */
+    const int32_t* view_scene;    /* host array [n_views]: scene rendered by each view */
+    int64_t instance_capacity;    /* max (tile, Gaussian) instances over the batch */
+    const cgs_schedule* schedule; /* may be NULL */
+} cgs_batch;
+
+/* Images of a batch are stored view after view: view v occupies
+ * [pix_off(v), pix_off(v) + H_v W_v) pixels, pix_off(v) = sum of earlier
+ * views' H W; colour arrays are [pixels, 3] (RGB innermost). */
+
+/* Workspace bytes needed by render_forward/render_backward for this batch
+ * (the forward's binning results live in it until the backward).  Returns 0
+ * for an invalid batch. */
+size_t cgs_workspace_bytes(const cgs_batch* batch);
+
+/* Forward render (Sec. 2.1 Eq. 1-3 over codebook-decoded Gaussians,
+ * Sec. 4.2's I_P(G, C)).  For every Gaussian and view: gather its codebook
+ * rows, scale = exp(log-scale), unit quaternion, opacity = sigmoid(logit);
+ * project mean and covariance Sigma = R S S^T R^T (Eq. 2) with the
+ * perspective Jacobian (Sigma2D = J W Sigma W^T J^T + 0.3 I); evaluate the
+ * view-dependent SH colour max(0, sum Y_lm k_lm + 1/2); bin into 16x16 tiles
+ * by (tile, depth, index); composite front to back per pixel (Eq. 3) with
+ * alpha = min(0.99, o exp(power)), alpha < 1/255 skipped, stop before the
+ * Gaussian that would take transmittance below 1e-4.
+ * Outputs (device): image [P,3], T_final [P] (transmittance left after the
+ * last blended Gaussian), n_last [P] (list position of the last blended
+ * Gaussian + 1 in the pixel's tile list).  Workspace: >= cgs_workspace_bytes. */
+cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_final, int32_t* n_last,
+                              void* ws, size_t ws_bytes, int64_t* d_info, void* stream);
+
+/* Backward of the forward render for dL/dimage = grad_image [P,3] (device).
+ * Must follow cgs_render_forward on the same batch, workspace and outputs
+ * (T_final, n_last as the forward wrote them; the per-pixel transmittance of
+ * every blended Gaussian is recomputed from T_final by division, not stored).
+ * Writes, per scene, dL/dmeans and dL/dcodebook: the per-Gaussian parameter
+ * gradients summed over Gaussians sharing a codebook row (the gradient of
+ * S_diff needed by the update step, Sec. 4.4).  Deterministic for the
+ * codebook rows (fixed-order segmented sums); the means gradients use
+ * floating-point atomics over tiles.  grads: host array [n_scenes]. */
+cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image,
+                               const float* T_final, const int32_t* n_last,
+                               const cgs_scene_grads* grads,
+                               void* ws, size_t ws_bytes, int64_t* d_info, void* stream);
+
+/* Codebook gradient reduction (Sec. 2.2 / 4.1: a Gaussian's parameters are
+ * its codebook row, so a row's gradient is the sum over the Gaussians mapped
+ * to it): grad_cb[k, c] = sum_{i : idx[i] == k} g[i * ld + c], c < d.
+ * g: device [n, ld] FP32; idx: device [n] in [0, k); perm: device [n]
+ * Gaussian indices stably sorted by idx (cached by the caller while the
+ * indices do not change) or NULL to sort here; grad_cb: device [k, ld_out],
+ * columns [0, d) overwritten (rows with no Gaussian get 0).  Order-fixed and
+ * deterministic.  Workspace: cgs_codebook_grad_reduce_workspace_bytes. */
+size_t cgs_codebook_grad_reduce_workspace_bytes(int64_t n, int64_t k, int32_t d);
+cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* idx, const int32_t* perm,
+                                    int64_t n, int64_t k, int32_t d, float* grad_cb, int64_t ld_out,
+                                    void* ws, size_t ws_bytes, void* stream);
+
+/* Tile binning of the 3DGS tile renderer the paper builds on (Sec. 2.1):
+ * every (Gaussian i, tile t in its rectangle) instance gets the key
+ * ((view_of[i] * tiles_y + ty) * tiles_x + tx) << 32 | depth_key[i]; instances
+ * are emitted in Gaussian order (tiles row-major) and stably sorted by key.
+ * depth_key: device [n] (IEEE bits of positive view depths); trect: device
+ * [n,4] uint16 half-open tile rectangle x0,y0,x1,y1 (empty = no instance);
+ * view_of: device [n] or NULL (all view 0).  Outputs (device): sorted_key
+ * [capacity] (may be NULL), sorted_gid [capacity], tile_range
+ * [n_views*tiles_y*tiles_x, 2] = half-open [start, end) of each tile (start =
+ * end for an empty tile).  If the instance count exceeds capacity nothing is
+ * sorted and d_info[0] = CGS_ECAPACITY; d_info[1] = instance count. */
+size_t cgs_bin_tiles_workspace_bytes(int64_t n, int32_t tiles_x, int32_t tiles_y, int32_t n_views,
+                                     int64_t capacity);
+cgs_status cgs_bin_tiles(const uint32_t* depth_key, const uint16_t* trect, const int32_t* view_of,
+                         int64_t n, int32_t tiles_x, int32_t tiles_y, int32_t n_views,
+                         uint64_t* sorted_key, uint32_t* sorted_gid, uint32_t* tile_range,
+                         int64_t capacity, int64_t* d_info, void* ws, size_t ws_bytes, void* stream);
+
+/* L1 part of the reconstruction loss (Sec. 2.1 Eq. 4 with the SSIM weight 0):
+ * loss = mean |image - target| over n values, grad = sign(image - target) / n
+ * (sign(0) = 0).  image, target, grad: device [n]; loss: device float[1]
+ * (written, not accumulated).  Workspace: cgs_loss_l1_workspace_bytes(n). */
+size_t cgs_loss_l1_workspace_bytes(int64_t n);
+cgs_status cgs_loss_l1(const float* image, const float* target, int64_t n, float* grad, float* loss,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Offsets (bytes from the workspace base) of the forward's intermediate
+ * arrays for a batch, for inspection and tests.  Any pointer may be NULL.
+ * records: R = sum over views of the view's scene size, record r of view v is
+ *   Gaussian r - rec_off(v) of that scene; rec_geom float4 [R] (u, v, -A/2,
+ *   -B) and rec_col float4 [R] (-C/2, opacity, r, g), rec_blue float [R]
+ *   (A, B, C the conic, inverse of Sigma2D); depth_key uint32 [R] (0x7f800000
+ *   when culled); tile_rect uint32[R][2] ((x0 | y0 << 16), (x1 | y1 << 16));
+ * inst_rec uint32 [capacity] record of each sorted instance; tile_range
+ *   uint32 [tiles][2]. */
+typedef struct {
+    size_t rec_geom, rec_col, rec_blue, depth_key, tile_rect, inst_rec, tile_range;
+    int64_t n_records, n_tiles;
+} cgs_ws_layout;
+cgs_status cgs_workspace_layout(const cgs_batch* batch, cgs_ws_layout* out);
+
+/* Human-readable name of a status code (static string). */
+const char* cgs_status_str(int32_t status);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int32_t cgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGS_H */

@@ -1,0 +1,169 @@
+"""ctypes binding of libcgs (include/cgs.h).  Argument marshalling only: every
+step of the render runs in the HIP library.  Loading fails loudly when the
+library has not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_int64, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcgs.so")
+
+CGS_OK, CGS_EINVAL, CGS_EUNSUPPORTED, CGS_ECAPACITY, CGS_EHIP, CGS_EWORKSPACE = 0, -1, -2, -3, -4, -5
+CGS_F32, CGS_BF16 = 0, 1
+MAX_VIEWS = MAX_SCENES = 64
+
+EXPORTS = ("cgs_workspace_bytes", "cgs_render_forward", "cgs_render_backward",
+           "cgs_codebook_grad_reduce_workspace_bytes", "cgs_codebook_grad_reduce",
+           "cgs_bin_tiles_workspace_bytes", "cgs_bin_tiles", "cgs_loss_l1_workspace_bytes",
+           "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version")
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("height", c_int32), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("Rt", c_float * 12), ("campos", c_float * 3),
+                ("bg", c_float * 3)]
+
+
+class CbView(ctypes.Structure):
+    _fields_ = [("ptr", c_void_p), ("dtype", c_int32), ("row_stride", c_int32), ("rows", c_int64),
+                ("col0", c_int32), ("pad_", c_int32)]
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("sh_degree", c_int32), ("opacity_mode", c_int32),
+                ("means", c_void_p), ("idx_sr", c_void_p), ("idx_sh", c_void_p),
+                ("sr", CbView), ("sh", CbView), ("opacity_logit", c_void_p)]
+
+
+class SceneGrads(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("sr", c_void_p), ("sr_stride", c_int32), ("sr_col0", c_int32),
+                ("sh", c_void_p), ("sh_stride", c_int32), ("sh_col0", c_int32), ("opacity", c_void_p)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("blend_waves_per_block", c_int32), ("tile_order", c_int32), ("reserved", c_int32 * 6)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("scenes", POINTER(Scene)), ("n_scenes", c_int32), ("n_views", c_int32),
+                ("cameras", POINTER(Camera)), ("view_scene", POINTER(c_int32)),
+                ("instance_capacity", c_int64), ("schedule", POINTER(Schedule))]
+
+
+class WsLayout(ctypes.Structure):
+    _fields_ = [("rec_geom", c_size_t), ("rec_col", c_size_t), ("rec_blue", c_size_t),
+                ("depth_key", c_size_t), ("tile_rect", c_size_t), ("inst_rec", c_size_t),
+                ("tile_range", c_size_t), ("n_records", c_int64), ("n_tiles", c_int64)]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libcgs.so; raises if it is missing (build it with build.py)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcgs not built: {path} is missing (run paper_2509_03775_amd/build.py)")
+    L = ctypes.CDLL(path)
+    pb = POINTER(Batch)
+    L.cgs_workspace_bytes.argtypes = [pb]
+    L.cgs_workspace_bytes.restype = c_size_t
+    L.cgs_render_forward.argtypes = [pb, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
+    L.cgs_render_forward.restype = c_int32
+    L.cgs_render_backward.argtypes = [pb, c_void_p, c_void_p, c_void_p, POINTER(SceneGrads), c_void_p, c_size_t,
+                                      c_void_p, c_void_p]
+    L.cgs_render_backward.restype = c_int32
+    L.cgs_codebook_grad_reduce_workspace_bytes.argtypes = [c_int64, c_int64, c_int32]
+    L.cgs_codebook_grad_reduce_workspace_bytes.restype = c_size_t
+    L.cgs_codebook_grad_reduce.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int64, c_int32,
+                                           c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
+    L.cgs_codebook_grad_reduce.restype = c_int32
+    L.cgs_bin_tiles_workspace_bytes.argtypes = [c_int64, c_int32, c_int32, c_int32, c_int64]
+    L.cgs_bin_tiles_workspace_bytes.restype = c_size_t
+    L.cgs_bin_tiles.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p,
+                                c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.cgs_bin_tiles.restype = c_int32
+    L.cgs_loss_l1_workspace_bytes.argtypes = [c_int64]
+    L.cgs_loss_l1_workspace_bytes.restype = c_size_t
+    L.cgs_loss_l1.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.cgs_loss_l1.restype = c_int32
+    L.cgs_workspace_layout.argtypes = [pb, POINTER(WsLayout)]
+    L.cgs_workspace_layout.restype = c_int32
+    L.cgs_status_str.argtypes = [c_int32]
+    L.cgs_status_str.restype = ctypes.c_char_p
+    L.cgs_version.argtypes = []
+    L.cgs_version.restype = c_int32
+    _LIB = L
+    return L
+
+
+class CgsError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = load().cgs_status_str(status).decode()
+        super().__init__(f"{fn} failed: {msg} ({status})")
+        self.status = status
+
+
+def check(fn: str, status: int) -> None:
+    if status != CGS_OK:
+        raise CgsError(fn, status)
+
+
+def ptr(t) -> int | None:
+    """Device (or host) address of a tensor, None for None."""
+    return None if t is None else t.data_ptr()
+
+
+# --- thin wrappers with the C names (pointers are raw integers) -------------
+
+def workspace_bytes(batch: Batch) -> int:
+    return load().cgs_workspace_bytes(ctypes.byref(batch))
+
+
+def render_forward(batch: Batch, image, T_final, n_last, ws, ws_bytes, d_info, stream) -> None:
+    check("cgs_render_forward", load().cgs_render_forward(ctypes.byref(batch), image, T_final, n_last, ws,
+                                                          ws_bytes, d_info, stream))
+
+
+def render_backward(batch: Batch, grad_image, T_final, n_last, grads, ws, ws_bytes, d_info, stream) -> None:
+    check("cgs_render_backward", load().cgs_render_backward(ctypes.byref(batch), grad_image, T_final, n_last,
+                                                            grads, ws, ws_bytes, d_info, stream))
+
+
+def codebook_grad_reduce_workspace_bytes(n: int, k: int, d: int) -> int:
+    return load().cgs_codebook_grad_reduce_workspace_bytes(n, k, d)
+
+
+def codebook_grad_reduce(g, ld, idx, perm, n, k, d, grad_cb, ld_out, ws, ws_bytes, stream) -> None:
+    check("cgs_codebook_grad_reduce", load().cgs_codebook_grad_reduce(g, ld, idx, perm, n, k, d, grad_cb, ld_out,
+                                                                      ws, ws_bytes, stream))
+
+
+def bin_tiles_workspace_bytes(n, tiles_x, tiles_y, n_views, capacity) -> int:
+    return load().cgs_bin_tiles_workspace_bytes(n, tiles_x, tiles_y, n_views, capacity)
+
+
+def bin_tiles(depth_key, trect, view_of, n, tiles_x, tiles_y, n_views, sorted_key, sorted_gid, tile_range,
+              capacity, d_info, ws, ws_bytes, stream) -> None:
+    check("cgs_bin_tiles", load().cgs_bin_tiles(depth_key, trect, view_of, n, tiles_x, tiles_y, n_views,
+                                                sorted_key, sorted_gid, tile_range, capacity, d_info, ws,
+                                                ws_bytes, stream))
+
+
+def loss_l1_workspace_bytes(n: int) -> int:
+    return load().cgs_loss_l1_workspace_bytes(n)
+
+
+def loss_l1(image, target, n, grad, loss, ws, ws_bytes, stream) -> None:
+    check("cgs_loss_l1", load().cgs_loss_l1(image, target, n, grad, loss, ws, ws_bytes, stream))
+
+
+def workspace_layout(batch: Batch) -> WsLayout:
+    out = WsLayout()
+    check("cgs_workspace_layout", load().cgs_workspace_layout(ctypes.byref(batch), ctypes.byref(out)))
+    return out

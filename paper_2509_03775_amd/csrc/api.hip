@@ -1,0 +1,521 @@
+// C-ABI entry points of libcgs: host-side validation, workspace planning and
+// the launch sequences of the forward and backward render, the standalone
+// binning and codebook-reduction calls, and the L1 loss.  Nothing here
+// allocates device memory or synchronises; every launch goes to the caller's
+// stream.
+#include <string.h>
+
+#include <algorithm>
+
+#include "cgs_internal.h"
+
+namespace cgs {
+
+// launchers defined in the other translation units
+hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, float4*, float*, uint32_t*, uint2*,
+                             uint32_t*, hipStream_t);
+hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
+hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const DevCounters*,
+                       uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
+hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, const uint32_t*, int64_t, int32_t,
+                             int32_t, const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_plain_keys(const uint32_t*, const uint32_t*, const uint32_t*, const DevCounters*, int64_t,
+                             uint64_t*, uint32_t*, hipStream_t);
+hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
+                            const float4*, const float*, float*, float*, int32_t*, hipStream_t);
+hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
+                            const float4*, const float*, const float*, const float*, const int32_t*, float*,
+                            hipStream_t);
+hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, float*, hipStream_t);
+hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
+hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
+                         const uint32_t*, int64_t, int64_t, const uint32_t*, float*, hipStream_t);
+hipError_t launch_gather_keys(const int32_t*, const int32_t*, int64_t, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_copy_keys(const int32_t*, int64_t, uint32_t*, hipStream_t);
+hipError_t launch_l1(const float*, const float*, int64_t, float*, float*, float*, int, hipStream_t);
+
+namespace {
+
+int bits_for(int64_t n) {   // bits needed for values in [0, n)
+    int b = 1;
+    while (b < 40 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+int passes_for(int nbits) { return (nbits + kRadixBits - 1) / kRadixBits; }
+
+template <typename T>
+T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+struct Host {
+    BatchDesc d;
+    WsPlan p;
+    int wpb;
+    int inst_buf;          // buffer pair holding the tile-sorted instances
+    int dsort_buf;         // buffer pair holding the depth-sorted records
+    int tile_bits;
+    bool fused;            // every scene uses the single-codebook layout
+    int opacity_mode;
+    int64_t rows_total;    // rows of the reduction key space (max of both parts)
+};
+
+size_t scan_bsum_count(int64_t n) { return (size_t)((n + kSortTile - 1) / kSortTile) + 16; }
+
+cgs_status plan_batch(const cgs_batch* b, Host* h) {
+    if (!b || !b->scenes || !b->cameras || !b->view_scene) return CGS_EINVAL;
+    if (b->n_scenes < 1 || b->n_scenes > CGS_MAX_SCENES || b->n_views < 1 || b->n_views > CGS_MAX_VIEWS)
+        return CGS_EINVAL;
+    if (b->instance_capacity < 0 || b->instance_capacity >= ((int64_t)1 << 32)) return CGS_EINVAL;
+    memset(&h->d, 0, sizeof(h->d));
+    BatchDesc& d = h->d;
+    d.n_views = b->n_views;
+    d.n_scenes = b->n_scenes;
+    d.capacity = b->instance_capacity;
+    const cgs_scene& s0 = b->scenes[0];
+    d.sh_degree = s0.sh_degree;
+    d.dtype = s0.sr.dtype;
+    if (s0.sh_degree < 0) return CGS_EINVAL;
+    if (s0.sh_degree > 3) return CGS_EUNSUPPORTED;
+    const int nco = (s0.sh_degree + 1) * (s0.sh_degree + 1);
+    d.row_width = 8 + 3 * nco;
+    h->opacity_mode = s0.opacity_mode;
+    h->fused = true;
+    int64_t goff = 0, sroff = 0, shoff = 0;
+    for (int s = 0; s < b->n_scenes; ++s) {
+        const cgs_scene& sc = b->scenes[s];
+        if (sc.n < 0) return CGS_EINVAL;
+        if (sc.sh_degree != s0.sh_degree) return CGS_EINVAL;
+        if (sc.sr.dtype != d.dtype || sc.sh.dtype != d.dtype) return CGS_EINVAL;
+        if (d.dtype != CGS_F32 && d.dtype != CGS_BF16) return CGS_EINVAL;
+        if (sc.opacity_mode != 0 && sc.opacity_mode != 1) return CGS_EINVAL;
+        if (sc.opacity_mode != h->opacity_mode) return CGS_EINVAL;
+        if (sc.sr.rows <= 0 || sc.sh.rows <= 0) return CGS_EINVAL;
+        if (!sc.sr.ptr || !sc.sh.ptr) return CGS_EINVAL;
+        const int srcols = sc.opacity_mode ? 8 : 7;
+        if (sc.sr.col0 < 0 || sc.sh.col0 < 0 || sc.sr.row_stride < sc.sr.col0 + srcols ||
+            sc.sh.row_stride < sc.sh.col0 + 3 * nco)
+            return CGS_EINVAL;
+        if (sc.n > 0 && (!sc.means || !sc.idx_sr || !sc.idx_sh)) return CGS_EINVAL;
+        if (sc.n > 0 && sc.opacity_mode == 0 && !sc.opacity_logit) return CGS_EINVAL;
+        SceneDesc& sd = d.scenes[s];
+        sd.n = sc.n;
+        sd.g_off = goff;
+        sd.sr_rows = sc.sr.rows;
+        sd.sh_rows = sc.sh.rows;
+        sd.sr_row_off = sroff;
+        sd.sh_row_off = shoff;
+        sd.means = sc.means;
+        sd.idx_sr = sc.idx_sr;
+        sd.idx_sh = sc.idx_sh;
+        sd.sr = sc.sr.ptr;
+        sd.sh = sc.sh.ptr;
+        sd.opacity = sc.opacity_logit;
+        sd.sr_stride = sc.sr.row_stride;
+        sd.sr_col0 = sc.sr.col0;
+        sd.sh_stride = sc.sh.row_stride;
+        sd.sh_col0 = sc.sh.col0;
+        sd.opacity_mode = sc.opacity_mode;
+        sd.fused = (sc.idx_sr == sc.idx_sh && sc.sr.ptr == sc.sh.ptr && sc.sr.row_stride == sc.sh.row_stride &&
+                    sc.sh.col0 == sc.sr.col0 + 8 && sc.opacity_mode == 1 && sc.sr.rows == sc.sh.rows) ? 1 : 0;
+        if (!sd.fused) h->fused = false;
+        goff += sc.n;
+        sroff += sc.sr.rows;
+        shoff += sc.sh.rows;
+    }
+    d.n_gauss = goff;
+    d.sr_rows_total = sroff;
+    d.sh_rows_total = shoff;
+    if (goff >= ((int64_t)1 << 32) || sroff >= ((int64_t)1 << 32) || shoff >= ((int64_t)1 << 32)) return CGS_EINVAL;
+    h->rows_total = std::max(sroff, shoff);
+    int64_t roff = 0, toff = 0, poff = 0;
+    for (int v = 0; v < b->n_views; ++v) {
+        const cgs_camera& c = b->cameras[v];
+        const int s = b->view_scene[v];
+        if (s < 0 || s >= b->n_scenes) return CGS_EINVAL;
+        if (c.width <= 0 || c.height <= 0 || c.width > 65535 * kTile || c.height > 65535 * kTile) return CGS_EINVAL;
+        if (!(c.fx > 0.f) || !(c.fy > 0.f)) return CGS_EINVAL;
+        ViewDesc& vd = d.views[v];
+        vd.W = c.width;
+        vd.H = c.height;
+        vd.tiles_x = (c.width + kTile - 1) / kTile;
+        vd.tiles_y = (c.height + kTile - 1) / kTile;
+        vd.scene = s;
+        vd.tile_off = toff;
+        vd.pix_off = poff;
+        vd.rec_off = roff;
+        vd.fx = c.fx; vd.fy = c.fy; vd.cx = c.cx; vd.cy = c.cy;
+        memcpy(vd.Rt, c.Rt, sizeof(vd.Rt));
+        memcpy(vd.campos, c.campos, sizeof(vd.campos));
+        memcpy(vd.bg, c.bg, sizeof(vd.bg));
+        roff += b->scenes[s].n;
+        toff += (int64_t)vd.tiles_x * vd.tiles_y;
+        poff += (int64_t)c.width * c.height;
+    }
+    d.n_rec = roff;
+    d.n_tiles = toff;
+    d.n_pix = poff;
+    if (roff >= ((int64_t)1 << 32) || toff >= ((int64_t)1 << 31)) return CGS_EINVAL;
+    int nv = 0;
+    for (int s = 0; s < b->n_scenes; ++s) {
+        d.scenes[s].vfirst = nv;
+        for (int v = 0; v < b->n_views; ++v)
+            if (b->view_scene[v] == s) d.view_list[nv++] = v;
+        d.scenes[s].vcount = nv - d.scenes[s].vfirst;
+    }
+    const cgs_schedule* sch = b->schedule;
+    h->wpb = (sch && (sch->blend_waves_per_block == 1 || sch->blend_waves_per_block == 2)) ? sch->blend_waves_per_block
+                                                                                            : 4;
+    d.tile_order = sch ? sch->tile_order : 0;
+    h->tile_bits = bits_for(d.n_tiles);
+    h->inst_buf = (passes_for(h->tile_bits) - 1) & 1;
+    h->dsort_buf = (passes_for(31) - 1) & 1;
+
+    // workspace plan
+    WsPlan& p = h->p;
+    const int64_t R = d.n_rec, G = d.n_gauss, cap = d.capacity, T = d.n_tiles;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    p.desc = take(sizeof(BatchDesc));
+    p.counters = take(sizeof(DevCounters));
+    p.rec_geom = take(16 * (size_t)R);
+    p.rec_col = take(16 * (size_t)R);
+    p.rec_blue = take(4 * (size_t)R);
+    p.depth_key = take(4 * (size_t)R);
+    p.tile_rect = take(8 * (size_t)R);
+    p.ntiles = take(4 * (size_t)R);
+    for (int i = 0; i < 2; ++i) { p.dsort_key[i] = take(4 * (size_t)R); p.dsort_val[i] = take(4 * (size_t)R); }
+    p.offs = take(4 * (size_t)R);
+    for (int i = 0; i < 2; ++i) { p.inst_key[i] = take(4 * (size_t)cap); p.inst_val[i] = take(4 * (size_t)cap); }
+    p.tile_range = take(8 * (size_t)T);
+    const int64_t nmax = std::max(std::max(R, cap), G);
+    p.radix_blocks_max = (nmax + kSortTile - 1) / kSortTile;
+    p.radix_counts = take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(p.radix_blocks_max, 1));
+    p.scan_blocks_max = (int64_t)scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * p.radix_blocks_max));
+    p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
+    p.g2d = take(4 * 9 * (size_t)R);
+    p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
+    for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
+    p.row_start = take(8 * (size_t)(h->rows_total + 1));
+    p.reduce_blocks = (G + kReduceBlock - 1) / kReduceBlock;
+    p.partials = take(4 * (size_t)kMaxRowWidth * 2 * (size_t)std::max<int64_t>(p.reduce_blocks, 1));
+    p.total = o;
+    return CGS_OK;
+}
+
+cgs_status hip_status(hipError_t e) { return e == hipSuccess ? CGS_OK : CGS_EHIP; }
+
+#define CGS_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return CGS_EHIP;          \
+    } while (0)
+
+// Upload the used part of the descriptor (header + views, then scenes).
+hipError_t upload_desc(const Host& h, void* ws, hipStream_t st) {
+    char* base = static_cast<char*>(ws) + h.p.desc;
+    const size_t head = offsetof(BatchDesc, views) + sizeof(ViewDesc) * (size_t)h.d.n_views;
+    hipError_t e = upload_bytes(base, &h.d, head, st);
+    if (e != hipSuccess) return e;
+    const size_t so = offsetof(BatchDesc, scenes);
+    return upload_bytes(base + so, reinterpret_cast<const char*>(&h.d) + so, sizeof(SceneDesc) * (size_t)h.d.n_scenes,
+                        st);
+}
+
+}  // namespace
+}  // namespace cgs
+
+using namespace cgs;
+
+extern "C" {
+
+int32_t cgs_version(void) { return 10000; }
+
+const char* cgs_status_str(int32_t s) {
+    switch (s) {
+        case CGS_OK: return "ok";
+        case CGS_EINVAL: return "invalid argument";
+        case CGS_EUNSUPPORTED: return "unsupported option";
+        case CGS_ECAPACITY: return "instance capacity exceeded";
+        case CGS_EHIP: return "HIP launch failed";
+        case CGS_EWORKSPACE: return "workspace too small";
+        default: return "unknown status";
+    }
+}
+
+size_t cgs_workspace_bytes(const cgs_batch* batch) {
+    static thread_local Host h;
+    if (plan_batch(batch, &h) != CGS_OK) return 0;
+    return h.p.total;
+}
+
+cgs_status cgs_workspace_layout(const cgs_batch* batch, cgs_ws_layout* out) {
+    static thread_local Host h;
+    cgs_status s = plan_batch(batch, &h);
+    if (s != CGS_OK) return s;
+    if (!out) return CGS_EINVAL;
+    out->rec_geom = h.p.rec_geom;
+    out->rec_col = h.p.rec_col;
+    out->rec_blue = h.p.rec_blue;
+    out->depth_key = h.p.depth_key;
+    out->tile_rect = h.p.tile_rect;
+    out->inst_rec = h.p.inst_val[h.inst_buf];
+    out->tile_range = h.p.tile_range;
+    out->n_records = h.d.n_rec;
+    out->n_tiles = h.d.n_tiles;
+    return CGS_OK;
+}
+
+cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_final, int32_t* n_last, void* ws,
+                              size_t ws_bytes, int64_t* d_info, void* stream) {
+    static thread_local Host h;
+    cgs_status s = plan_batch(batch, &h);
+    if (s != CGS_OK) return s;
+    if (!ws) return CGS_EINVAL;
+    if (ws_bytes < h.p.total) return CGS_EWORKSPACE;
+    if (h.d.n_pix > 0 && (!image || !T_final || !n_last)) return CGS_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const WsPlan& p = h.p;
+    const BatchDesc* dd = at<const BatchDesc>(ws, p.desc);
+    DevCounters* cnt = at<DevCounters>(ws, p.counters);
+    unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
+    uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
+    CGS_TRY(upload_desc(h, ws, st));
+    CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, at<float4>(ws, p.rec_geom),
+                              at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), at<uint32_t>(ws, p.depth_key),
+                              at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), st));
+    // depth order of every record (stable: ties keep record order)
+    uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
+    uint32_t* dv[2] = {at<uint32_t>(ws, p.dsort_val[0]), at<uint32_t>(ws, p.dsort_val[1])};
+    hipError_t e;
+    int db = radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, counts, bsum,
+                              st, &e);
+    CGS_TRY(e);
+    // instance offsets in depth order, capacity check, emission
+    CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), dv[db], h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));
+    CGS_TRY(launch_capacity(cnt, h.d.capacity, d_info, st));
+    uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
+    uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
+    CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.tile_rect), cnt, ik[1], iv[1],
+                        st));
+    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, counts, bsum, st, &e);
+    CGS_TRY(e);
+    if (ib != h.inst_buf) return CGS_EHIP;
+    CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
+    CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
+                             at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), image,
+                             T_final, n_last, st));
+    return CGS_OK;
+}
+
+cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, const float* T_final,
+                               const int32_t* n_last, const cgs_scene_grads* grads, void* ws, size_t ws_bytes,
+                               int64_t* d_info, void* stream) {
+    (void)d_info;
+    static thread_local Host h;
+    cgs_status s = plan_batch(batch, &h);
+    if (s != CGS_OK) return s;
+    if (!ws || !grads) return CGS_EINVAL;
+    if (ws_bytes < h.p.total) return CGS_EWORKSPACE;
+    if (h.d.n_pix > 0 && (!grad_image || !T_final || !n_last)) return CGS_EINVAL;
+    bool single = h.fused;
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        const cgs_scene_grads& g = grads[i];
+        SceneDesc& sd = h.d.scenes[i];
+        if (sd.n > 0 && !g.means) return CGS_EINVAL;
+        if (!g.sr || (!g.sh && !sd.fused)) return CGS_EINVAL;
+        const int srcols = h.opacity_mode ? 8 : 7;
+        if (g.sr_col0 < 0 || g.sr_stride < g.sr_col0 + srcols) return CGS_EINVAL;
+        if (g.sh && (g.sh_col0 < 0 || g.sh_stride < g.sh_col0 + h.d.row_width - 8)) return CGS_EINVAL;
+        if (h.opacity_mode == 0 && sd.n > 0 && !g.opacity) return CGS_EINVAL;
+        sd.g_means = g.means;
+        sd.g_sr = g.sr;
+        sd.g_sr_stride = g.sr_stride;
+        sd.g_sr_col0 = g.sr_col0;
+        sd.g_sh = g.sh ? g.sh : g.sr;
+        sd.g_sh_stride = g.sh ? g.sh_stride : g.sr_stride;
+        sd.g_sh_col0 = g.sh ? g.sh_col0 : g.sr_col0 + 8;
+        sd.g_opacity = g.opacity;
+        if (!(sd.g_sh == sd.g_sr && sd.g_sh_stride == sd.g_sr_stride && sd.g_sh_col0 == sd.g_sr_col0 + 8))
+            single = false;
+        if (!sd.fused && g.sr_stride < g.sr_col0 + srcols) return CGS_EINVAL;
+        if (single && g.sr_stride < g.sr_col0 + h.d.row_width) return CGS_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const WsPlan& p = h.p;
+    const BatchDesc* dd = at<const BatchDesc>(ws, p.desc);
+    unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
+    uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
+    DevCounters* cnt = at<DevCounters>(ws, p.counters);
+    CGS_TRY(upload_desc(h, ws, st));
+    float* g2d = at<float>(ws, p.g2d);
+    CGS_TRY(fill_u32(g2d, 0u, 9 * (size_t)h.d.n_rec, st));
+    CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
+                             at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue),
+                             grad_image, T_final, n_last, g2d, st));
+    float* gth = at<float>(ws, p.gtheta);
+    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, g2d, gth, st));
+    (void)cnt;
+    uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
+    uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
+    uint32_t* rr = at<uint32_t>(ws, p.row_start);
+    float* part = at<float>(ws, p.partials);
+    const int nparts = single ? 1 : 2;
+    for (int part_i = 0; part_i < nparts; ++part_i) {
+        const int64_t rows = part_i == 0 ? h.d.sr_rows_total : h.d.sh_rows_total;
+        int c0, D;
+        if (single) { c0 = 0; D = h.d.row_width; }
+        else if (part_i == 0) { c0 = 0; D = h.opacity_mode ? 8 : 7; }
+        else { c0 = 8; D = h.d.row_width - 8; }
+        CGS_TRY(launch_row_keys(dd, part_i, h.d.n_gauss, pk[1], st));
+        hipError_t e;
+        int pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), counts, bsum, st, &e);
+        CGS_TRY(e);
+        CGS_TRY(tile_ranges(pk[pb], nullptr, h.d.n_gauss, rows, rr, st));
+        CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, part,
+                              st));
+    }
+    return CGS_OK;
+}
+
+size_t cgs_codebook_grad_reduce_workspace_bytes(int64_t n, int64_t k, int32_t d) {
+    if (n < 0 || k <= 0 || d <= 0) return 0;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { o = align_up(o + bytes); };
+    take(sizeof(BatchDesc));
+    for (int i = 0; i < 4; ++i) take(4 * (size_t)n);
+    take(8 * (size_t)(k + 1));
+    const int64_t rb = (n + kReduceBlock - 1) / kReduceBlock;
+    take(4 * (size_t)kMaxRowWidth * 2 * (size_t)std::max<int64_t>(rb, 1));
+    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1));
+    take(8 * scan_bsum_count(std::max<int64_t>(n, kRadixBins * nb)));
+    return o;
+}
+
+cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* idx, const int32_t* perm, int64_t n,
+                                    int64_t k, int32_t d, float* grad_cb, int64_t ld_out, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    if (n < 0 || k <= 0 || d <= 0 || ld < d || ld_out < d) return CGS_EINVAL;
+    if (k >= ((int64_t)1 << 32) || n >= ((int64_t)1 << 32)) return CGS_EINVAL;
+    if (!grad_cb || !ws || (n > 0 && (!g || !idx))) return CGS_EINVAL;
+    const size_t need = cgs_codebook_grad_reduce_workspace_bytes(n, k, d);
+    if (ws_bytes < need) return CGS_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    static thread_local BatchDesc hd;
+    memset(&hd, 0, offsetof(BatchDesc, views));
+    hd.n_scenes = 1;
+    hd.n_gauss = n;
+    hd.sr_rows_total = k;
+    SceneDesc sd;
+    memset(&sd, 0, sizeof(sd));
+    sd.n = n;
+    sd.sr_rows = k;
+    sd.g_sr = grad_cb;
+    sd.g_sr_stride = (int32_t)ld_out;
+    sd.g_sr_col0 = 0;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    const size_t o_desc = take(sizeof(BatchDesc));
+    uint32_t* pk[2];
+    uint32_t* pv[2];
+    for (int i = 0; i < 2; ++i) { pk[i] = at<uint32_t>(ws, take(4 * (size_t)n)); pv[i] = at<uint32_t>(ws, take(4 * (size_t)n)); }
+    uint32_t* rr = at<uint32_t>(ws, take(8 * (size_t)(k + 1)));
+    const int64_t rb = (n + kReduceBlock - 1) / kReduceBlock;
+    float* part = at<float>(ws, take(4 * (size_t)kMaxRowWidth * 2 * (size_t)std::max<int64_t>(rb, 1)));
+    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    uint32_t* counts = at<uint32_t>(ws, take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1)));
+    unsigned long long* bsum = at<unsigned long long>(ws, take(8 * scan_bsum_count(std::max<int64_t>(n, kRadixBins * nb))));
+    char* dbase = static_cast<char*>(ws) + o_desc;
+    CGS_TRY(upload_bytes(dbase, &hd, offsetof(BatchDesc, views), st));
+    CGS_TRY(upload_bytes(dbase + offsetof(BatchDesc, scenes), &sd, sizeof(sd), st));
+    const BatchDesc* dd = reinterpret_cast<const BatchDesc*>(dbase);
+    int pb = 0;
+    if (perm) {
+        CGS_TRY(launch_gather_keys(idx, perm, n, pk[0], pv[0], st));
+    } else {
+        CGS_TRY(launch_copy_keys(idx, n, pk[1], st));
+        hipError_t e;
+        pb = radix_sort_pairs(pk[1], nullptr, pk, pv, n, nullptr, bits_for(k), counts, bsum, st, &e);
+        CGS_TRY(e);
+    }
+    CGS_TRY(tile_ranges(pk[pb], nullptr, n, k, rr, st));
+    for (int c0 = 0; c0 < d; c0 += kMaxRowWidth) {
+        const int D = std::min<int>(kMaxRowWidth, d - c0);
+        CGS_TRY(launch_reduce(dd, 0, g, ld, c0, D, c0, pk[pb], pv[pb], n, k, rr, part, st));
+    }
+    return CGS_OK;
+}
+
+size_t cgs_bin_tiles_workspace_bytes(int64_t n, int32_t tiles_x, int32_t tiles_y, int32_t n_views, int64_t capacity) {
+    if (n < 0 || tiles_x <= 0 || tiles_y <= 0 || n_views <= 0 || capacity < 0) return 0;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { o = align_up(o + bytes); };
+    take(sizeof(DevCounters));
+    for (int i = 0; i < 6; ++i) take(4 * (size_t)n);        // ntiles, offs, dsort key/val x2
+    for (int i = 0; i < 4; ++i) take(4 * (size_t)capacity); // instance key/val x2
+    const int64_t nmax = std::max(n, capacity);
+    const int64_t nb = (nmax + kSortTile - 1) / kSortTile;
+    take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1));
+    take(8 * scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * nb)));
+    return o;
+}
+
+cgs_status cgs_bin_tiles(const uint32_t* depth_key, const uint16_t* trect, const int32_t* view_of, int64_t n,
+                         int32_t tiles_x, int32_t tiles_y, int32_t n_views, uint64_t* sorted_key, uint32_t* sorted_gid,
+                         uint32_t* tile_range, int64_t capacity, int64_t* d_info, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (n < 0 || tiles_x <= 0 || tiles_y <= 0 || n_views <= 0 || capacity < 0) return CGS_EINVAL;
+    if (tiles_x > 65535 || tiles_y > 65535) return CGS_EINVAL;
+    const int64_t ntile = (int64_t)tiles_x * tiles_y * n_views;
+    if (ntile >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 32) || capacity >= ((int64_t)1 << 32)) return CGS_EINVAL;
+    if (!ws || !sorted_gid || !tile_range || (n > 0 && (!depth_key || !trect))) return CGS_EINVAL;
+    if (ws_bytes < cgs_bin_tiles_workspace_bytes(n, tiles_x, tiles_y, n_views, capacity)) return CGS_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    DevCounters* cnt = at<DevCounters>(ws, take(sizeof(DevCounters)));
+    uint32_t* nt = at<uint32_t>(ws, take(4 * (size_t)n));
+    uint32_t* offs = at<uint32_t>(ws, take(4 * (size_t)n));
+    uint32_t* dk[2];
+    uint32_t* dv[2];
+    for (int i = 0; i < 2; ++i) { dk[i] = at<uint32_t>(ws, take(4 * (size_t)n)); dv[i] = at<uint32_t>(ws, take(4 * (size_t)n)); }
+    uint32_t* ik[2];
+    uint32_t* iv[2];
+    for (int i = 0; i < 2; ++i) {
+        ik[i] = at<uint32_t>(ws, take(4 * (size_t)capacity));
+        iv[i] = at<uint32_t>(ws, take(4 * (size_t)capacity));
+    }
+    const int64_t nmax = std::max(n, capacity);
+    const int64_t nb = (nmax + kSortTile - 1) / kSortTile;
+    uint32_t* counts = at<uint32_t>(ws, take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1)));
+    unsigned long long* bsum = at<unsigned long long>(ws, take(8 * scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * nb))));
+    CGS_TRY(launch_plain_counts(trect, n, nt, st));
+    hipError_t e;
+    int db = radix_sort_pairs(depth_key, nullptr, dk, dv, n, nullptr, 32, counts, bsum, st, &e);
+    CGS_TRY(e);
+    CGS_TRY(scan_u32(nt, dv[db], n, offs, &cnt->n_inst, bsum, st));
+    CGS_TRY(launch_capacity(cnt, capacity, d_info, st));
+    CGS_TRY(launch_emit_plain(trect, view_of, dv[db], offs, n, tiles_x, tiles_y, cnt, ik[1], iv[1], st));
+    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, capacity, &cnt->n_inst_ok, bits_for(ntile), counts, bsum, st, &e);
+    CGS_TRY(e);
+    CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, capacity, ntile, tile_range, st));
+    CGS_TRY(launch_plain_keys(ik[ib], iv[ib], depth_key, cnt, capacity, sorted_key, sorted_gid, st));
+    return CGS_OK;
+}
+
+size_t cgs_loss_l1_workspace_bytes(int64_t n) {
+    (void)n;
+    return 4 * 1024;
+}
+
+cgs_status cgs_loss_l1(const float* image, const float* target, int64_t n, float* grad, float* loss, void* ws,
+                       size_t ws_bytes, void* stream) {
+    if (n < 0 || !loss || !ws || (n > 0 && (!image || !target || !grad))) return CGS_EINVAL;
+    if (ws_bytes < cgs_loss_l1_workspace_bytes(n)) return CGS_EWORKSPACE;
+    int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    if (nb < 1) nb = 1;
+    return hip_status(launch_l1(image, target, n, grad, loss, static_cast<float*>(ws), nb, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

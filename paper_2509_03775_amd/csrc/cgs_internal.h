@@ -1,0 +1,194 @@
+// Internal declarations of libcgs: the device-side batch descriptor, the
+// workspace plan and wave64 helpers for gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cgs.h"
+
+namespace cgs {
+
+constexpr int kTile = 16;               // tile edge in pixels
+constexpr int kWave = 64;               // CDNA wavefront width
+constexpr int kSortItems = 16;          // keys per lane in the radix/scan kernels
+constexpr int kSortBlock = 256;         // threads per radix/scan workgroup
+constexpr int kSortTile = kSortItems * kSortBlock;   // keys per workgroup (4096)
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kReduceBlock = 128;       // Gaussians per codebook-reduction workgroup
+constexpr int kMaxRowWidth = 8 + 48;    // ls3 q4 logit1 + degree-3 SH
+constexpr uint32_t kCulledKey = 0x7f800000u;   // +inf bits: sorts after every depth
+
+// ---------------------------------------------------------------- descriptors
+struct ViewDesc {
+    int32_t W, H, tiles_x, tiles_y;
+    int32_t scene, pad0;
+    int64_t tile_off, pix_off, rec_off;
+    float fx, fy, cx, cy;
+    float Rt[12];
+    float campos[3];
+    float bg[3];
+};
+
+struct SceneDesc {
+    int64_t n, g_off;
+    int64_t sr_rows, sh_rows, sr_row_off, sh_row_off;
+    const float* means;
+    const int32_t* idx_sr;
+    const int32_t* idx_sh;
+    const void* sr;
+    const void* sh;
+    const float* opacity;
+    int32_t sr_stride, sr_col0, sh_stride, sh_col0;
+    int32_t opacity_mode, vfirst, vcount, fused;
+    float* g_means;
+    float* g_sr;
+    float* g_sh;
+    float* g_opacity;
+    int32_t g_sr_stride, g_sr_col0, g_sh_stride, g_sh_col0;
+};
+
+struct BatchDesc {
+    int32_t n_views, n_scenes, sh_degree, dtype;
+    int32_t row_width;      // 8 + 3 (d+1)^2: per-Gaussian gradient row
+    int32_t tile_order;
+    int64_t n_rec, n_gauss, n_tiles, n_pix, capacity;
+    int64_t sr_rows_total, sh_rows_total;
+    int32_t view_list[CGS_MAX_VIEWS];   // views grouped by scene
+    ViewDesc views[CGS_MAX_VIEWS];
+    SceneDesc scenes[CGS_MAX_SCENES];
+};
+
+// Device counters kept in the workspace.
+struct DevCounters {
+    unsigned long long n_inst;     // instances needed
+    unsigned long long n_inst_ok;  // instances emitted (0 on overflow)
+    unsigned long long pad[6];
+};
+
+// ---------------------------------------------------------- workspace plan
+struct WsPlan {
+    size_t desc, counters;
+    size_t rec_geom, rec_col, rec_blue, depth_key, tile_rect, ntiles;
+    size_t dsort_key[2], dsort_val[2];
+    size_t offs;
+    size_t inst_key[2], inst_val[2];
+    size_t tile_range;
+    size_t radix_counts, scan_bsum;
+    size_t g2d, gtheta, psort_key[2], psort_val[2], row_start, partials;
+    size_t total;
+    int64_t radix_blocks_max, scan_blocks_max, reduce_blocks;
+};
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------ wave helpers
+__device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// Orders LDS traffic of one wavefront (all lanes run in lockstep; the fences
+// keep the compiler from moving LDS accesses across the point).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t popc_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// Sum over the 64 lanes (every lane must be active); result valid in all lanes.
+// DPP row shifts build 16-lane sums, row broadcasts combine rows; the total
+// lands in lane 63 and is read back as a wave-uniform value.
+__device__ inline float wave_sum(float v) {
+    int x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t o = (uint32_t)__shfl_xor((int)v, d, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+// Inclusive prefix sum over the wave (u32).
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane) {
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = (uint32_t)__shfl_up((int)v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <int DT>
+__device__ inline float load_cb(const void* p, int64_t i) {
+    if constexpr (DT == CGS_BF16) return bf16_to_f32(static_cast<const uint16_t*>(p)[i]);
+    else return static_cast<const float*>(p)[i];
+}
+
+__device__ inline int find_scene(const BatchDesc* d, int64_t g) {
+    int lo = 0, hi = d->n_scenes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d->scenes[mid].g_off <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int find_view_by_tile(const BatchDesc* d, int64_t t) {
+    int lo = 0, hi = d->n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d->views[mid].tile_off <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int find_view_by_rec(const BatchDesc* d, int64_t r) {
+    int lo = 0, hi = d->n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d->views[mid].rec_off <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------- launchers
+// (defined in the .hip files; all enqueue on `st` and never synchronise)
+hipError_t upload_bytes(void* dst, const void* src, size_t n, hipStream_t st);
+hipError_t fill_u32(void* dst, uint32_t value, size_t count, hipStream_t st);
+
+// Exclusive scan of n u32 values read through `perm` (NULL = identity):
+// out[j] = sum_{i<j} in[perm[i]]; *total = sum of all (u64).
+hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out,
+                    unsigned long long* total, unsigned long long* bsum, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) u32 pairs on bits [0, nbits).  The
+// first pass reads kin/vin (vin NULL: value = position), later passes ping-pong
+// between kbuf/vbuf[0] and [1] (kin may alias kbuf[1]).  n_dev (optional) holds
+// the live item count, clamped to n_max.  Returns the index (0/1) of the
+// buffer pair that holds the result.
+int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
+                     const unsigned long long* n_dev, int nbits, uint32_t* counts, unsigned long long* bsum,
+                     hipStream_t st, hipError_t* err);
+
+hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
+                       int64_t n_tiles, uint32_t* ranges, hipStream_t st);
+
+}  // namespace cgs

@@ -1,0 +1,575 @@
+// Backward render: reverse-order blend (transmittance recovered from T_final
+// by division), per-Gaussian chain rule from the projected parameters to the
+// mean and the codebook-row values, and the codebook reduction as a sort by
+// row index followed by fixed-order segmented sums (no contended atomics).
+#include "cgs_internal.h"
+#include "render_common.h"
+
+namespace cgs {
+
+// ------------------------------------------------------------ backward blend
+// One wavefront per tile, same pixel mapping as the forward.  Each pixel walks
+// its list from n_last-1 down to 0, re-derives alpha with the forward's code,
+// recovers T before the Gaussian as T_after / (1 - alpha), and accumulates
+// dL/d(u, v, -A/2, -B, -C/2, opacity, r, g, b).  The four pixels of a lane are
+// summed in registers, the 64 lanes by a DPP reduction, and one lane adds the
+// tile's total with a global atomic per value.
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restrict__ desc,
+                                                         const uint32_t* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ inst_rec,
+                                                         const float4* __restrict__ rec_geom,
+                                                         const float4* __restrict__ rec_col,
+                                                         const float* __restrict__ rec_blue,
+                                                         const float* __restrict__ grad_image,
+                                                         const float* __restrict__ T_final,
+                                                         const int32_t* __restrict__ n_last,
+                                                         float* __restrict__ g2d) {
+    __shared__ float4 s_g[WPB][64];
+    __shared__ float4 s_c[WPB][64];
+    __shared__ float s_b[WPB][64];
+    __shared__ uint32_t s_r[WPB][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
+    if (tile >= desc->n_tiles) return;
+    const int v = find_view_by_tile(desc, tile);
+    const ViewDesc& vd = desc->views[v];
+    const int64_t lt = tile - vd.tile_off;
+    const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
+    const int px = tx * kTile + (lane & 15);
+    const int py0 = ty * kTile + (lane >> 4);
+    const float fpx = (float)px;
+
+    float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4];
+    uint32_t last[4];
+    uint32_t maxlast = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = py0 + 4 * k;
+        bh0[k] = vd.bg[0]; bh1[k] = vd.bg[1]; bh2[k] = vd.bg[2];
+        if (px < vd.W && py < vd.H) {
+            const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
+            T[k] = T_final[p];
+            last[k] = (uint32_t)n_last[p];
+            dC0[k] = grad_image[3 * p + 0];
+            dC1[k] = grad_image[3 * p + 1];
+            dC2[k] = grad_image[3 * p + 2];
+        } else {
+            T[k] = 1.f; last[k] = 0; dC0[k] = dC1[k] = dC2[k] = 0.f;
+        }
+        maxlast = last[k] > maxlast ? last[k] : maxlast;
+    }
+    maxlast = wave_max_u32(maxlast);
+    const uint32_t start = ranges[2 * tile];
+    const uint32_t len = ranges[2 * tile + 1] - start;
+    if (maxlast > len) maxlast = len;     // n_last inconsistent with this binning: stay in the list
+    for (int64_t bend = maxlast; bend > 0; bend -= 64) {
+        const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
+        const int64_t li = bbeg + lane;
+        if (li < bend) {
+            const uint32_t r = inst_rec[start + li];
+            s_r[w][lane] = r;
+            s_g[w][lane] = rec_geom[r];
+            s_c[w][lane] = rec_col[r];
+            s_b[w][lane] = rec_blue[r];
+        }
+        wave_sync();
+        for (int j = (int)(bend - bbeg) - 1; j >= 0; --j) {
+            const uint32_t pos = (uint32_t)(bbeg + j);     // 0-based list position
+            const float4 g = s_g[w][j];
+            const float4 c = s_c[w][j];
+            const float bl = s_b[w][j];
+            float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (pos >= last[k]) continue;
+                const float dx = fpx - g.x;
+                const float dy = (float)(py0 + 4 * k) - g.y;
+                float G;
+                bool pcl;
+                const float alpha = blend_alpha(dx, dy, g, c, G, pcl);
+                if (alpha < kMinAlpha) continue;
+                any = true;
+                const float Tb = T[k] * __builtin_amdgcn_rcpf(1.f - alpha);
+                const float wgt = alpha * Tb;
+                a_r = fmaf(wgt, dC0[k], a_r);
+                a_g = fmaf(wgt, dC1[k], a_g);
+                a_bl = fmaf(wgt, dC2[k], a_bl);
+                const float e0 = c.z - bh0[k], e1 = c.w - bh1[k], e2 = bl - bh2[k];
+                const float dalpha = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
+                bh0[k] = fmaf(alpha, e0, bh0[k]);
+                bh1[k] = fmaf(alpha, e1, bh1[k]);
+                bh2[k] = fmaf(alpha, e2, bh2[k]);
+                T[k] = Tb;
+                if (c.y * G < kMaxAlpha) {
+                    a_o = fmaf(dalpha, G, a_o);
+                    if (!pcl) {
+                        const float dp = dalpha * alpha;
+                        const float dpx = dp * dx, dpy = dp * dy;
+                        a_a = fmaf(dpx, dx, a_a);
+                        a_b = fmaf(dpx, dy, a_b);
+                        a_c = fmaf(dpy, dy, a_c);
+                        // d power / d u = -(2 a' dx + b' dy), a' = -A/2, b' = -B
+                        a_u = fmaf(-dp, fmaf(2.f * g.z, dx, g.w * dy), a_u);
+                        a_v = fmaf(-dp, fmaf(2.f * c.x, dy, g.w * dx), a_v);
+                    }
+                }
+            }
+            if (__ballot(any) != 0ull) {
+                const float s0 = wave_sum(a_u), s1 = wave_sum(a_v), s2 = wave_sum(a_a);
+                const float s3 = wave_sum(a_b), s4 = wave_sum(a_c), s5 = wave_sum(a_o);
+                const float s6 = wave_sum(a_r), s7 = wave_sum(a_g), s8 = wave_sum(a_bl);
+                if (lane == 0) {
+                    float* dst = g2d + 9 * (int64_t)s_r[w][j];
+                    atomicAdd(dst + 0, s0); atomicAdd(dst + 1, s1); atomicAdd(dst + 2, s2);
+                    atomicAdd(dst + 3, s3); atomicAdd(dst + 4, s4); atomicAdd(dst + 5, s5);
+                    atomicAdd(dst + 6, s6); atomicAdd(dst + 7, s7); atomicAdd(dst + 8, s8);
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ------------------------------------------------------------ chain rule
+// One thread per Gaussian: recompute the projection of every view of its
+// scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
+// the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
+template <int DT, int SHD>
+__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ g2d,
+                                               float* __restrict__ gtheta) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gg >= desc->n_gauss) return;
+    const int s = find_scene(desc, gg);
+    const SceneDesc& sd = desc->scenes[s];
+    const int64_t g = gg - sd.g_off;
+    const int RW = desc->row_width;
+
+    GaussParams gp;
+    float* out = gtheta + gg * RW;
+    if (!load_gaussian<DT, SHD>(sd, g, gp)) {
+        for (int i = 0; i < RW; ++i) out[i] = 0.f;
+        if (sd.g_means) { sd.g_means[3 * g] = 0.f; sd.g_means[3 * g + 1] = 0.f; sd.g_means[3 * g + 2] = 0.f; }
+        if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = 0.f;
+        return;
+    }
+    GaussShape sh;
+    gaussian_shape(gp, sh);
+    const float opac = 1.0f / (1.0f + __expf(-gp.logit));
+
+    float dmu[3] = {0.f, 0.f, 0.f};
+    float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float dk[48];
+#pragma unroll
+    for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
+    float dop = 0.f;
+
+    for (int vi = 0; vi < sd.vcount; ++vi) {
+        const int v = desc->view_list[sd.vfirst + vi];
+        const ViewDesc& vd = desc->views[v];
+        const int64_t r = vd.rec_off + g;
+        const float* gr = g2d + 9 * r;
+        float d[9];
+        bool nz = false;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { d[i] = gr[i]; nz |= d[i] != 0.f; }
+        if (!nz) continue;
+        ViewProj p;
+        if (!project_view(vd, gp.mean, sh, p)) continue;
+        float A, B, C;
+        conic_of(p.a, p.b, p.c, A, B, C);
+        dop += d[5];
+        // conic (A, B, C) gradient from the stored (-A/2, -B, -C/2)
+        const float dA = -0.5f * d[2], dB = -d[3], dC = -0.5f * d[4];
+        // dL/dSigma2D (symmetric-matrix gradient) = -K Gk K, Gk = [[dA, dB/2], [dB/2, dC]]
+        const float hb = 0.5f * dB;
+        const float m00 = A * dA + B * hb, m01 = A * hb + B * dC;
+        const float m10 = B * dA + C * hb, m11 = B * hb + C * dC;
+        const float G00 = -(m00 * A + m01 * B);
+        const float G01 = -(m00 * B + m01 * C);
+        const float G11 = -(m10 * B + m11 * C);
+        // dSigma3D += T^T G T ; dT = 2 G T Sigma
+        float GT[2][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            GT[0][j] = G00 * p.T[0][j] + G01 * p.T[1][j];
+            GT[1][j] = G01 * p.T[0][j] + G11 * p.T[1][j];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dSig[i][j] = fmaf(p.T[0][i], GT[0][j], fmaf(p.T[1][i], GT[1][j], dSig[i][j]));
+        float dT[2][3];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                dT[a][j] = 2.f * (GT[a][0] * sh.S[0][j] + GT[a][1] * sh.S[1][j] + GT[a][2] * sh.S[2][j]);
+        // T = J W  ->  dJ = dT W^T (only the non-zero entries of J matter)
+        const float* Wm = vd.Rt;   // rows at 0, 4, 8
+        const float dJ00 = dT[0][0] * Wm[0] + dT[0][1] * Wm[1] + dT[0][2] * Wm[2];
+        const float dJ02 = dT[0][0] * Wm[8] + dT[0][1] * Wm[9] + dT[0][2] * Wm[10];
+        const float dJ11 = dT[1][0] * Wm[4] + dT[1][1] * Wm[5] + dT[1][2] * Wm[6];
+        const float dJ12 = dT[1][0] * Wm[8] + dT[1][1] * Wm[9] + dT[1][2] * Wm[10];
+        const float iz = 1.f / p.zc, iz2 = iz * iz;
+        // camera-space gradient
+        float gx = d[0] * vd.fx * iz;
+        float gy = d[1] * vd.fy * iz;
+        float gz = -(d[0] * vd.fx * p.xc + d[1] * vd.fy * p.yc) * iz2;
+        gz += -(dJ00 * vd.fx + dJ11 * vd.fy) * iz2;
+        if (!p.clx) {   // J02 = -fx x / z^2
+            gx += dJ02 * (-vd.fx * iz2);
+            gz += dJ02 * (2.f * vd.fx * p.xc * iz2 * iz);
+        } else {        // J02 = -fx txc / z, txc constant
+            gz += dJ02 * (vd.fx * p.txc * iz2);
+        }
+        if (!p.cly) {
+            gy += dJ12 * (-vd.fy * iz2);
+            gz += dJ12 * (2.f * vd.fy * p.yc * iz2 * iz);
+        } else {
+            gz += dJ12 * (vd.fy * p.tyc * iz2);
+        }
+        // x_c = W mu + t  ->  dmu += W^T dx_c
+        dmu[0] += Wm[0] * gx + Wm[4] * gy + Wm[8] * gz;
+        dmu[1] += Wm[1] * gx + Wm[5] * gy + Wm[9] * gz;
+        dmu[2] += Wm[2] * gx + Wm[6] * gy + Wm[10] * gz;
+        // colour: c = max(0, sum Y k + 1/2), Y of the unit direction camera -> mean
+        {
+            float ex = gp.mean[0] - vd.campos[0], ey = gp.mean[1] - vd.campos[1], ez = gp.mean[2] - vd.campos[2];
+            const float il = rsqrtf(ex * ex + ey * ey + ez * ez);
+            const float x = ex * il, y = ey * il, z = ez * il;
+            float Y[16];
+            sh_basis<SHD>(x, y, z, Y);
+            float dcol[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.5f;
+#pragma unroll
+                for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], gp.sh[3 * j + ch], acc);
+                dcol[ch] = acc > 0.f ? d[6 + ch] : 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < NCO; ++j)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) dk[3 * j + ch] = fmaf(Y[j], dcol[ch], dk[3 * j + ch]);
+            if constexpr (SHD >= 1) {
+                float e[16];
+#pragma unroll
+                for (int j = 0; j < NCO; ++j)
+                    e[j] = dcol[0] * gp.sh[3 * j] + dcol[1] * gp.sh[3 * j + 1] + dcol[2] * gp.sh[3 * j + 2];
+                float qx = -kY1 * e[3], qy = -kY1 * e[1], qz = kY1 * e[2];
+                if constexpr (SHD >= 2) {
+                    qx += kY2a * y * e[4] - kY2a * z * e[7] - 2.f * kY2b * x * e[6] + 2.f * kY2c * x * e[8];
+                    qy += kY2a * x * e[4] - kY2a * z * e[5] - 2.f * kY2b * y * e[6] - 2.f * kY2c * y * e[8];
+                    qz += -kY2a * y * e[5] - kY2a * x * e[7] + 4.f * kY2b * z * e[6];
+                    if constexpr (SHD >= 3) {
+                        const float xx = x * x, yy = y * y, zz = z * z;
+                        qx += -kY3a * 6.f * x * y * e[9] + kY3b * y * z * e[10] + kY3c * 2.f * x * y * e[11]
+                              - kY3d * 6.f * x * z * e[12] - kY3c * (4.f * zz - 3.f * xx - yy) * e[13]
+                              + kY3e * 2.f * x * z * e[14] - kY3a * (3.f * xx - 3.f * yy) * e[15];
+                        qy += -kY3a * (3.f * xx - 3.f * yy) * e[9] + kY3b * x * z * e[10]
+                              - kY3c * (4.f * zz - xx - 3.f * yy) * e[11] - kY3d * 6.f * y * z * e[12]
+                              + kY3c * 2.f * x * y * e[13] - kY3e * 2.f * y * z * e[14] + kY3a * 6.f * x * y * e[15];
+                        qz += kY3b * x * y * e[10] - kY3c * 8.f * y * z * e[11]
+                              + kY3d * (6.f * zz - 3.f * xx - 3.f * yy) * e[12] - kY3c * 8.f * x * z * e[13]
+                              + kY3e * (xx - yy) * e[14];
+                    }
+                }
+                // through the normalisation dir = e / |e|
+                const float dd = qx * x + qy * y + qz * z;
+                dmu[0] += (qx - x * dd) * il;
+                dmu[1] += (qy - y * dd) * il;
+                dmu[2] += (qz - z * dd) * il;
+            }
+        }
+    }
+    // Sigma = M M^T -> dM = (G + G^T) M ; M = R diag(s)
+    float dR[3][3], ds[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float dM = (dSig[i][0] + dSig[0][i]) * sh.M[0][j] + (dSig[i][1] + dSig[1][i]) * sh.M[1][j] +
+                             (dSig[i][2] + dSig[2][i]) * sh.M[2][j];
+            dR[i][j] = dM * sh.s[j];
+            ds[j] = fmaf(dM, sh.R[i][j], ds[j]);
+        }
+    const float w = sh.qn[0], x = sh.qn[1], y = sh.qn[2], z = sh.qn[3];
+    float dqw = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+    float dqx = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
+                       w * dR[2][1] - 2.f * x * dR[2][2]);
+    float dqy = 2.f * (-2.f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
+                       z * dR[2][1] - 2.f * y * dR[2][2]);
+    float dqz = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
+                       y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+    float dq[4] = {0.f, 0.f, 0.f, 0.f};
+    if (sh.qlen > 0.f) {
+        const float proj = dqw * w + dqx * x + dqy * y + dqz * z;
+        const float il = 1.f / sh.qlen;
+        dq[0] = (dqw - w * proj) * il;
+        dq[1] = (dqx - x * proj) * il;
+        dq[2] = (dqy - y * proj) * il;
+        dq[3] = (dqz - z * proj) * il;
+    }
+    out[0] = ds[0] * sh.s[0];
+    out[1] = ds[1] * sh.s[1];
+    out[2] = ds[2] * sh.s[2];
+    out[3] = dq[0]; out[4] = dq[1]; out[5] = dq[2]; out[6] = dq[3];
+    const float dlogit = dop * opac * (1.f - opac);
+    out[7] = dlogit;
+#pragma unroll
+    for (int i = 0; i < 3 * NCO; ++i) out[8 + i] = dk[i];
+    if (sd.g_means) {
+        sd.g_means[3 * g + 0] = dmu[0];
+        sd.g_means[3 * g + 1] = dmu[1];
+        sd.g_means[3 * g + 2] = dmu[2];
+    }
+    if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
+}
+
+// ------------------------------------------------- codebook row reduction
+// Sort keys for the reduction: global row = row offset of the scene + index.
+__global__ __launch_bounds__(256) void k_row_keys(const BatchDesc* __restrict__ desc, int part,
+                                                  uint32_t* __restrict__ key) {
+    const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gg >= desc->n_gauss) return;
+    const int s = find_scene(desc, gg);
+    const SceneDesc& sd = desc->scenes[s];
+    const int64_t g = gg - sd.g_off;
+    key[gg] = part == 0 ? (uint32_t)(sd.sr_row_off + sd.idx_sr[g]) : (uint32_t)(sd.sh_row_off + sd.idx_sh[g]);
+}
+
+struct RowOut {
+    float* ptr;
+    int64_t stride;
+    int32_t col0;
+};
+
+__device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, int64_t* local) {
+    int lo = 0, hi = desc->n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t off = part == 0 ? desc->scenes[mid].sr_row_off : desc->scenes[mid].sh_row_off;
+        if (off <= row) lo = mid; else hi = mid - 1;
+    }
+    const SceneDesc& sd = desc->scenes[lo];
+    if (part == 0) {
+        *local = row - sd.sr_row_off;
+        return RowOut{sd.g_sr, sd.g_sr_stride, sd.g_sr_col0};
+    }
+    *local = row - sd.sh_row_off;
+    return RowOut{sd.g_sh, sd.g_sh_stride, sd.g_sh_col0};
+}
+
+// A workgroup owns kReduceBlock consecutive positions of the row-sorted order.
+// It stages their gradient columns [c0, c0+D) in LDS, splits the positions into
+// runs of equal row, and sums each (run, column) in position order.  A run that
+// holds a whole row is written to the output; a run cut by the workgroup's
+// edge is written to partial slot 0 (first run) or 1 (last run) and finished
+// by k_reduce_fixup in workgroup order, so the result does not depend on
+// scheduling.
+__global__ __launch_bounds__(kReduceBlock) void k_reduce_rows(const BatchDesc* __restrict__ desc, int part,
+                                                              const float* __restrict__ gtheta, int64_t ld, int c0,
+                                                              int D, int oshift, const uint32_t* __restrict__ skey,
+                                                              const uint32_t* __restrict__ sval, int64_t n,
+                                                              int64_t n_rows,
+                                                              const uint32_t* __restrict__ row_range,
+                                                              float* __restrict__ partials) {
+    __shared__ float s_v[kReduceBlock * (kMaxRowWidth + 1)];
+    __shared__ uint32_t s_key[kReduceBlock];
+    __shared__ uint32_t s_gid[kReduceBlock];
+    __shared__ int s_seg_first[kReduceBlock + 1];
+    __shared__ int s_nseg;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kReduceBlock;
+    const int cnt = (int)((n - base) < kReduceBlock ? (n - base) : kReduceBlock);
+    const int LD = D + 1;
+    if (t < cnt) {
+        s_key[t] = skey[base + t];
+        s_gid[t] = sval[base + t];
+    }
+    __syncthreads();
+    for (int e = t; e < cnt * D; e += kReduceBlock) {
+        const int row = e / D, col = e - row * D;
+        s_v[row * LD + col] = gtheta[(int64_t)s_gid[row] * ld + c0 + col];
+    }
+    if (t == 0) {
+        int ns = 0;
+        for (int i = 0; i < cnt; ++i)
+            if (i == 0 || s_key[i] != s_key[i - 1]) s_seg_first[ns++] = i;
+        s_seg_first[ns] = cnt;
+        s_nseg = ns;
+    }
+    __syncthreads();
+    const int nseg = s_nseg;
+    for (int job = t; job < nseg * D; job += kReduceBlock) {
+        const int sg = job / D, col = job - sg * D;
+        const int i0 = s_seg_first[sg], i1 = s_seg_first[sg + 1];
+        float acc = 0.f;
+        for (int i = i0; i < i1; ++i) acc += s_v[i * LD + col];
+        const uint32_t row = s_key[i0];
+        if ((int64_t)row >= n_rows) continue;     // index outside the codebook: dropped
+        const int64_t rs = row_range[2 * (int64_t)row], re = row_range[2 * (int64_t)row + 1];
+        if (rs >= base && re <= base + cnt) {
+            int64_t lr;
+            const RowOut o = row_out(desc, part, row, &lr);
+            o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
+        } else {
+            const int slot = sg == 0 ? 0 : 1;
+            partials[((int64_t)blockIdx.x * 2 + slot) * kMaxRowWidth + col] = acc;
+        }
+    }
+}
+
+// One thread per (row, column): empty rows get 0; rows spanning several
+// workgroups are summed from the partials in workgroup order.
+__global__ __launch_bounds__(256) void k_reduce_fixup(const BatchDesc* __restrict__ desc, int part, int D,
+                                                      int oshift, int64_t n_rows, const uint32_t* __restrict__ row_range,
+                                                      const float* __restrict__ partials) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_rows * D) return;
+    const int64_t row = e / D;
+    const int col = (int)(e - row * D);
+    const int64_t rs = row_range[2 * row], re = row_range[2 * row + 1];
+    float acc;
+    if (rs == re) {
+        acc = 0.f;
+    } else {
+        const int64_t b0 = rs / kReduceBlock, b1 = (re - 1) / kReduceBlock;
+        if (b0 == b1) return;
+        const int slot0 = (rs == b0 * kReduceBlock) ? 0 : 1;
+        acc = partials[(b0 * 2 + slot0) * kMaxRowWidth + col];
+        for (int64_t b = b0 + 1; b <= b1; ++b) acc += partials[(b * 2) * kMaxRowWidth + col];
+    }
+    int64_t lr;
+    const RowOut o = row_out(desc, part, row, &lr);
+    o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
+}
+
+// Sorted keys from a caller-provided permutation: key[i] = idx[perm[i]].
+__global__ __launch_bounds__(256) void k_gather_keys(const int32_t* __restrict__ idx, const int32_t* __restrict__ perm,
+                                                     int64_t n, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = perm[i];
+    key[i] = (uint32_t)idx[g];
+    val[i] = (uint32_t)g;
+}
+
+__global__ __launch_bounds__(256) void k_copy_keys(const int32_t* __restrict__ idx, int64_t n,
+                                                   uint32_t* __restrict__ key) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    key[i] = (uint32_t)idx[i];
+}
+
+// ---------------------------------------------------------------- L1 loss
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const float* __restrict__ tgt, int64_t n,
+                                            float inv_n, float* __restrict__ grad, float* __restrict__ part) {
+    __shared__ float s[256];
+    float acc = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = img[i] - tgt[i];
+        acc += fabsf(d);
+        grad[i] = d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part, int nb, float inv_n,
+                                                  float* __restrict__ loss) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(s[0] * (double)inv_n);
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
+                            const uint32_t* inst_rec, const float4* rg, const float4* rc, const float* rb,
+                            const float* grad_image, const float* T_final, const int32_t* n_last, float* g2d,
+                            hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (wpb == 1) {
+        hipLaunchKernelGGL(k_blend_bwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rg, rc,
+                           rb, grad_image, T_final, n_last, g2d);
+    } else if (wpb == 2) {
+        hipLaunchKernelGGL(k_blend_bwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
+                           inst_rec, rg, rc, rb, grad_image, T_final, n_last, g2d);
+    } else {
+        hipLaunchKernelGGL(k_blend_bwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
+                           inst_rec, rg, rc, rb, grad_image, T_final, n_last, g2d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, const float* g2d, float* gtheta,
+                        hipStream_t st) {
+    if (n_gauss <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
+#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, g2d, gtheta)
+    if (dtype == CGS_F32) {
+        switch (shd) { case 0: CGS_CH(CGS_F32, 0); break; case 1: CGS_CH(CGS_F32, 1); break;
+                       case 2: CGS_CH(CGS_F32, 2); break; default: CGS_CH(CGS_F32, 3); break; }
+    } else {
+        switch (shd) { case 0: CGS_CH(CGS_BF16, 0); break; case 1: CGS_CH(CGS_BF16, 1); break;
+                       case 2: CGS_CH(CGS_BF16, 2); break; default: CGS_CH(CGS_BF16, 3); break; }
+    }
+#undef CGS_CH
+    return hipGetLastError();
+}
+
+hipError_t launch_row_keys(const BatchDesc* d_desc, int part, int64_t n_gauss, uint32_t* key, hipStream_t st) {
+    if (n_gauss <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_keys, dim3((unsigned)((n_gauss + 255) / 256)), dim3(256), 0, st, d_desc, part, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const BatchDesc* d_desc, int part, const float* gtheta, int64_t ld, int c0, int D,
+                         int oshift, const uint32_t* skey, const uint32_t* sval, int64_t n, int64_t n_rows,
+                         const uint32_t* row_range, float* partials, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((n + kReduceBlock - 1) / kReduceBlock)), dim3(kReduceBlock),
+                           0, st, d_desc, part, gtheta, ld, c0, D, oshift, skey, sval, n, n_rows, row_range, partials);
+    if (n_rows * D > 0)
+        hipLaunchKernelGGL(k_reduce_fixup, dim3((unsigned)((n_rows * D + 255) / 256)), dim3(256), 0, st, d_desc, part,
+                           D, oshift, n_rows, row_range, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_keys(const int32_t* idx, const int32_t* perm, int64_t n, uint32_t* key, uint32_t* val,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, perm, n, key, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_keys(const int32_t* idx, int64_t n, uint32_t* key, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, n, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_l1(const float* img, const float* tgt, int64_t n, float* grad, float* loss, float* part,
+                     int nb, hipStream_t st) {
+    const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
+    if (n > 0) hipLaunchKernelGGL(k_l1, dim3(nb), dim3(256), 0, st, img, tgt, n, inv, grad, part);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, st, part, n > 0 ? nb : 0, 1.0f, loss);
+    return hipGetLastError();
+}
+
+}  // namespace cgs

@@ -1,0 +1,324 @@
+// Per-Gaussian math shared by the forward and backward kernels of libcgs.
+//
+// Two kinds of arithmetic live here:
+//  * the FP32 "skeleton" (skel_* and the marked blocks of gaussian_shape /
+//    project_view): it decides integers -- culling, depth keys, tile
+//    rectangles -- so its operation sequence is fixed (one IEEE rounding per
+//    written operation, no contraction, exp by Cody-Waite reduction and a
+//    Taylor polynomial) and reproducible bit for bit by any IEEE FP32
+//    implementation of the same sequence;
+//  * continuous FP32 math (conic, colour, compositing), free to use fused
+//    multiply-adds and the hardware exp, with an FP64 island for the 2x2
+//    determinant and inverse of near-degenerate projected covariances.
+#pragma once
+
+#include "cgs_internal.h"
+
+namespace cgs {
+
+constexpr float kMinAlpha = 1.0f / 255.0f;   // alpha below this is skipped
+constexpr float kMaxAlpha = 0.99f;           // alpha saturates here
+constexpr float kMinT = 1e-4f;               // stop before T would drop below this
+constexpr float kNear = 0.2f;                // near-plane cull
+constexpr float kBlur = 0.3f;                // low-pass added to Sigma2D
+constexpr float kClampFov = 1.3f;            // Jacobian clamp, in half-fields of view
+
+// Real orthonormal spherical harmonics with the Condon-Shortley phase, as
+// polynomials in the unit direction (x, y, z); index j = l*l + l + m.
+// Normalisation constants in closed form:
+constexpr float kY00 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+constexpr float kY1 = 0.4886025119029199f;     // sqrt(3/(4 pi))
+constexpr float kY2a = 1.0925484305920792f;    // sqrt(15/(4 pi))
+constexpr float kY2b = 0.31539156525252005f;   // sqrt(5/(16 pi))
+constexpr float kY2c = 0.5462742152960396f;    // sqrt(15/(16 pi))
+constexpr float kY3a = 0.5900435899266435f;    // sqrt(35/(32 pi))
+constexpr float kY3b = 2.890611442640554f;     // sqrt(105/(4 pi))
+constexpr float kY3c = 0.4570457994644658f;    // sqrt(21/(32 pi))
+constexpr float kY3d = 0.3731763325901154f;    // sqrt(7/(16 pi))
+constexpr float kY3e = 1.445305721320277f;     // sqrt(105/(16 pi))
+
+// ------------------------------------------------------------ skeleton exp
+// exp(x) = 2^n p(r): n = rint(x / ln 2), r = x - n ln2 with ln 2 split in a
+// 16-bit head and a tail (Cody & Waite), p the degree-7 Taylor polynomial of
+// exp (coefficients 1/k! rounded to float) in Horner form with fused
+// multiply-adds.  x is clamped to [-80, 80] so results stay normal.
+__device__ inline float skel_exp(float x) {
+#pragma clang fp contract(off)
+    x = x > 80.0f ? 80.0f : x;
+    x = x < -80.0f ? -80.0f : x;
+    const float n = __builtin_rintf(x * 1.44269502162933349609375f);
+    float r = x - n * 0.693145751953125f;
+    r = r - n * 1.428606765330187045037746429443359375e-06f;
+    float p = 1.98412701138295233249664306640625e-04f;
+    p = __builtin_fmaf(p, r, 1.388888922519981861114501953125e-03f);
+    p = __builtin_fmaf(p, r, 8.333333767950534820556640625e-03f);
+    p = __builtin_fmaf(p, r, 4.16666679084300994873046875e-02f);
+    p = __builtin_fmaf(p, r, 1.6666667163372039794921875e-01f);
+    p = __builtin_fmaf(p, r, 0.5f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    return __builtin_ldexpf(p, (int)n);
+}
+
+// ---------------------------------------------------------- Gaussian state
+struct GaussParams {
+    float mean[3];
+    float ls[3];
+    float q[4];     // (w, x, y, z) as stored
+    float logit;
+    float sh[48];   // [coef][rgb]
+};
+
+// Returns false (and loads nothing) when an index is outside its codebook:
+// such a Gaussian is treated as culled and receives zero gradient.
+template <int DT, int SHD>
+__device__ inline bool load_gaussian(const SceneDesc& sd, int64_t g, GaussParams& gp) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    const int64_t ksr = sd.idx_sr[g];
+    const int64_t ksh = sd.idx_sh[g];
+    if (ksr < 0 || ksr >= sd.sr_rows || ksh < 0 || ksh >= sd.sh_rows) return false;
+    gp.mean[0] = sd.means[3 * g + 0];
+    gp.mean[1] = sd.means[3 * g + 1];
+    gp.mean[2] = sd.means[3 * g + 2];
+    const int64_t bsr = ksr * sd.sr_stride + sd.sr_col0;
+    const int64_t bsh = ksh * sd.sh_stride + sd.sh_col0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gp.ls[i] = load_cb<DT>(sd.sr, bsr + i);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gp.q[i] = load_cb<DT>(sd.sr, bsr + 3 + i);
+    gp.logit = sd.opacity_mode ? load_cb<DT>(sd.sr, bsr + 7) : sd.opacity[g];
+#pragma unroll
+    for (int i = 0; i < 3 * NCO; ++i) gp.sh[i] = load_cb<DT>(sd.sh, bsh + i);
+    return true;
+}
+
+// View-independent shape: scale, unit quaternion, R(q), M = R S, Sigma = M M^T.
+struct GaussShape {
+    float s[3];
+    float qn[4];
+    float qlen;
+    float R[3][3];
+    float M[3][3];
+    float S[3][3];
+};
+
+__device__ inline void gaussian_shape(const GaussParams& gp, GaussShape& o) {
+#pragma clang fp contract(off)
+    o.s[0] = skel_exp(gp.ls[0]);
+    o.s[1] = skel_exp(gp.ls[1]);
+    o.s[2] = skel_exp(gp.ls[2]);
+    float w = gp.q[0], x = gp.q[1], y = gp.q[2], z = gp.q[3];
+    float n2 = w * w;
+    n2 = n2 + x * x;
+    n2 = n2 + y * y;
+    n2 = n2 + z * z;
+    if (n2 > 0.0f) {
+        const float len = __builtin_sqrtf(n2);
+        o.qlen = len;
+        w = w / len; x = x / len; y = y / len; z = z / len;
+    } else {
+        o.qlen = 0.0f;
+        w = 1.0f; x = 0.0f; y = 0.0f; z = 0.0f;
+    }
+    o.qn[0] = w; o.qn[1] = x; o.qn[2] = y; o.qn[3] = z;
+    o.R[0][0] = 1.0f - 2.0f * (y * y + z * z);
+    o.R[0][1] = 2.0f * (x * y - w * z);
+    o.R[0][2] = 2.0f * (x * z + w * y);
+    o.R[1][0] = 2.0f * (x * y + w * z);
+    o.R[1][1] = 1.0f - 2.0f * (x * x + z * z);
+    o.R[1][2] = 2.0f * (y * z - w * x);
+    o.R[2][0] = 2.0f * (x * z - w * y);
+    o.R[2][1] = 2.0f * (y * z + w * x);
+    o.R[2][2] = 1.0f - 2.0f * (x * x + y * y);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o.M[i][j] = o.R[i][j] * o.s[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            float acc = o.M[i][0] * o.M[j][0];
+            acc = acc + o.M[i][1] * o.M[j][1];
+            acc = acc + o.M[i][2] * o.M[j][2];
+            o.S[i][j] = acc;
+            o.S[j][i] = acc;
+        }
+}
+
+// ------------------------------------------------------------- projection
+struct ViewProj {
+    float xc, yc, zc;
+    float tx, ty;          // x/z, y/z
+    float txc, tyc;        // clamped
+    bool clx, cly;         // clamp active
+    float j00, j02, j11, j12;
+    float T[2][3];         // J W
+    float U0[3];           // (T Sigma) row 0
+    float a, b, c;         // Sigma2D (+ 0.3 on the diagonal)
+    float u, v;
+    int tx0, ty0, tx1, ty1;
+};
+
+// Camera point, cull, Jacobian, Sigma2D and the tile rectangle.  Returns false
+// when the Gaussian is culled (behind the near plane or off the image).
+__device__ inline bool project_view(const ViewDesc& vd, const float* mu, const GaussShape& sh, ViewProj& p) {
+#pragma clang fp contract(off)
+    const float* Rt = vd.Rt;
+    float xc = Rt[0] * mu[0]; xc = xc + Rt[1] * mu[1]; xc = xc + Rt[2] * mu[2]; xc = xc + Rt[3];
+    float yc = Rt[4] * mu[0]; yc = yc + Rt[5] * mu[1]; yc = yc + Rt[6] * mu[2]; yc = yc + Rt[7];
+    float zc = Rt[8] * mu[0]; zc = zc + Rt[9] * mu[1]; zc = zc + Rt[10] * mu[2]; zc = zc + Rt[11];
+    p.xc = xc; p.yc = yc; p.zc = zc;
+    if (!(zc > kNear)) return false;
+    const float tx = xc / zc, ty = yc / zc;
+    const float limx = kClampFov * ((0.5f * (float)vd.W) / vd.fx);
+    const float limy = kClampFov * ((0.5f * (float)vd.H) / vd.fy);
+    const float txc = fminf(limx, fmaxf(-limx, tx));
+    const float tyc = fminf(limy, fmaxf(-limy, ty));
+    p.tx = tx; p.ty = ty; p.txc = txc; p.tyc = tyc;
+    p.clx = !(tx >= -limx && tx <= limx);
+    p.cly = !(ty >= -limy && ty <= limy);
+    p.j00 = vd.fx / zc;
+    p.j02 = -(vd.fx * txc) / zc;
+    p.j11 = vd.fy / zc;
+    p.j12 = -(vd.fy * tyc) / zc;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        p.T[0][j] = p.j00 * Rt[0 + j] + p.j02 * Rt[8 + j];
+        p.T[1][j] = p.j11 * Rt[4 + j] + p.j12 * Rt[8 + j];
+    }
+    float d2[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        float U[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            float acc = p.T[a][0] * sh.S[0][j];
+            acc = acc + p.T[a][1] * sh.S[1][j];
+            acc = acc + p.T[a][2] * sh.S[2][j];
+            U[j] = acc;
+        }
+        if (a == 0) { p.U0[0] = U[0]; p.U0[1] = U[1]; p.U0[2] = U[2]; }
+        float acc = U[0] * p.T[a][0];
+        acc = acc + U[1] * p.T[a][1];
+        acc = acc + U[2] * p.T[a][2];
+        d2[a] = acc + kBlur;
+    }
+    p.a = d2[0];
+    p.c = d2[1];
+    {
+        float acc = p.U0[0] * p.T[1][0];
+        acc = acc + p.U0[1] * p.T[1][1];
+        acc = acc + p.U0[2] * p.T[1][2];
+        p.b = acc;
+    }
+    p.u = vd.fx * tx + vd.cx;
+    p.v = vd.fy * ty + vd.cy;
+    const float ex = 3.0f * __builtin_sqrtf(p.a);
+    const float ey = 3.0f * __builtin_sqrtf(p.c);
+    const float xlo = fmaxf(__builtin_ceilf(p.u - ex), 0.0f);
+    const float xhi = fminf(__builtin_floorf(p.u + ex), (float)(vd.W - 1));
+    const float ylo = fmaxf(__builtin_ceilf(p.v - ey), 0.0f);
+    const float yhi = fminf(__builtin_floorf(p.v + ey), (float)(vd.H - 1));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) return false;
+    p.tx0 = ((int)xlo) >> 4;
+    p.ty0 = ((int)ylo) >> 4;
+    p.tx1 = (((int)xhi) >> 4) + 1;
+    p.ty1 = (((int)yhi) >> 4) + 1;
+    return true;
+}
+
+// Conic = inverse of [[a, b], [b, c]].  The FP32 determinant loses the
+// leading digits when the footprint is very elongated (a c ~ b^2); then
+// determinant and inverse are taken in FP64.
+__device__ inline void conic_of(float a, float b, float c, float& A, float& B, float& C) {
+    const float det = a * c - b * b;
+    if (det > 0x1p-10f * (a * c)) {
+        const float id = 1.0f / det;
+        A = c * id; B = -b * id; C = a * id;
+    } else {
+        const double da = a, db = b, dc = c;
+        const double dd = da * dc - db * db;
+        const double id = 1.0 / dd;
+        A = (float)(dc * id); B = (float)(-db * id); C = (float)(da * id);
+    }
+}
+
+// ---------------------------------------------------------------- colour
+template <int SHD>
+__device__ inline void sh_basis(float x, float y, float z, float* Y) {
+    Y[0] = kY00;
+    if constexpr (SHD >= 1) {
+        Y[1] = -kY1 * y;
+        Y[2] = kY1 * z;
+        Y[3] = -kY1 * x;
+    }
+    if constexpr (SHD >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kY2a * (x * y);
+        Y[5] = -kY2a * (y * z);
+        Y[6] = kY2b * (2.0f * zz - xx - yy);
+        Y[7] = -kY2a * (x * z);
+        Y[8] = kY2c * (xx - yy);
+        if constexpr (SHD >= 3) {
+            Y[9] = -kY3a * y * (3.0f * xx - yy);
+            Y[10] = kY3b * (x * y * z);
+            Y[11] = -kY3c * y * (4.0f * zz - xx - yy);
+            Y[12] = kY3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -kY3c * x * (4.0f * zz - xx - yy);
+            Y[14] = kY3e * z * (xx - yy);
+            Y[15] = -kY3a * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+// colour = max(0, sum_j Y_j(dir) k_j + 1/2), dir = (mean - campos)/|.|.
+// pre (optional) receives the unclamped values.
+template <int SHD>
+__device__ inline void sh_colour(const ViewDesc& vd, const GaussParams& gp, float* col, float* pre) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    float dx = gp.mean[0] - vd.campos[0], dy = gp.mean[1] - vd.campos[1], dz = gp.mean[2] - vd.campos[2];
+    const float il = rsqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= il; dy *= il; dz *= il;
+    float Y[16];
+    sh_basis<SHD>(dx, dy, dz, Y);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = 0.5f;
+#pragma unroll
+        for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], gp.sh[3 * j + ch], acc);
+        if (pre) pre[ch] = acc;
+        col[ch] = fmaxf(acc, 0.0f);
+    }
+}
+
+// ------------------------------------------------------------- compositing
+// alpha of one (pixel, Gaussian) pair.  g = (u, v, -A/2, -B),
+// c = (-C/2, opacity, r, g): power = -(A dx^2 + 2 B dx dy + C dy^2)/2, clamped
+// to <= 0 (rounding residue of a positive-definite form), alpha = min(0.99,
+// o exp(power)).  Forward and backward call this same function so both take
+// identical decisions.
+__device__ inline float blend_alpha(float dx, float dy, const float4& g, const float4& c, float& G, bool& pclamp) {
+#pragma clang fp contract(off)
+    const float t = __builtin_fmaf(g.z, dx, g.w * dy);
+    float pw = __builtin_fmaf(t, dx, (c.x * dy) * dy);
+    pclamp = pw > 0.0f;
+    pw = pclamp ? 0.0f : pw;
+    G = __expf(pw);
+    const float og = c.y * G;
+    return og < kMaxAlpha ? og : kMaxAlpha;
+}
+
+// Map a workgroup index to the tile group it shades.  Order 1 groups
+// consecutive tiles on one XCD: the dispatcher deals workgroups to the 8 XCDs
+// round-robin, so workgroup b runs on XCD b % 8; we hand XCD x a contiguous
+// range of tile groups so neighbouring tiles (which share Gaussians) hit the
+// same L2.
+__device__ inline int64_t tile_of_block(const BatchDesc* d, int64_t b, int64_t nb) {
+    if (d->tile_order != 1) return b;
+    const int64_t q = nb / 8, rm = nb % 8;
+    const int64_t x = b % 8, k = b / 8;
+    return x * q + (x < rm ? x : rm) + k;
+}
+
+}  // namespace cgs

@@ -1,0 +1,298 @@
+// Forward render: codebook gather + projection + SH colour (one thread per
+// Gaussian, looping over the views of its scene so the gather and the
+// view-independent activations are done once per batch), instance emission,
+// and the front-to-back blend (paper Sec. 2.1, Eq. 1-3).
+#include "cgs_internal.h"
+#include "render_common.h"
+
+namespace cgs {
+
+// ---------------------------------------------------------------- preprocess
+template <int DT, int SHD>
+__global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict__ desc,
+                                                    float4* __restrict__ rec_geom, float4* __restrict__ rec_col,
+                                                    float* __restrict__ rec_blue, uint32_t* __restrict__ depth_key,
+                                                    uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gg >= desc->n_gauss) return;
+    const int s = find_scene(desc, gg);
+    const SceneDesc& sd = desc->scenes[s];
+    const int64_t g = gg - sd.g_off;
+
+    GaussParams gp;
+    const bool valid = load_gaussian<DT, SHD>(sd, g, gp);
+    GaussShape sh;
+    if (valid) gaussian_shape(gp, sh);
+    const float opac = valid ? 1.0f / (1.0f + __expf(-gp.logit)) : 0.0f;
+
+    for (int vi = 0; vi < sd.vcount; ++vi) {
+        const int v = desc->view_list[sd.vfirst + vi];
+        const ViewDesc& vd = desc->views[v];
+        const int64_t r = vd.rec_off + g;
+        ViewProj vp;
+        const bool keep = valid && project_view(vd, gp.mean, sh, vp);
+        if (!keep) {
+            depth_key[r] = kCulledKey;
+            tile_rect[r] = make_uint2(0u, 0u);
+            ntiles[r] = 0u;
+            rec_geom[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec_col[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec_blue[r] = 0.f;
+            continue;
+        }
+        float A, B, C;
+        conic_of(vp.a, vp.b, vp.c, A, B, C);
+        float col[3];
+        sh_colour<SHD>(vd, gp, col, nullptr);
+        depth_key[r] = __float_as_uint(vp.zc);
+        tile_rect[r] = make_uint2((uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16), (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16));
+        ntiles[r] = (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0));
+        rec_geom[r] = make_float4(vp.u, vp.v, -0.5f * A, -B);
+        rec_col[r] = make_float4(-0.5f * C, opac, col[0], col[1]);
+        rec_blue[r] = col[2];
+        (void)NCO;
+    }
+}
+
+// ------------------------------------------------------------ capacity check
+__global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) {
+    unsigned long long m = cnt->n_inst;
+    bool ok = (int64_t)m <= capacity;
+    cnt->n_inst_ok = ok ? m : 0ull;
+    if (d_info) {
+        d_info[0] = ok ? CGS_OK : CGS_ECAPACITY;
+        d_info[1] = (int64_t)m;
+    }
+}
+
+// ------------------------------------------------------------------ emission
+// One thread per record in depth order: write (tile, record) for every tile
+// of the record's rectangle, row-major, at the record's scanned offset.
+__global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ sorted_rec,
+                                              const uint32_t* __restrict__ offs, const uint2* __restrict__ tile_rect,
+                                              const DevCounters* __restrict__ cnt, uint32_t* __restrict__ inst_key,
+                                              uint32_t* __restrict__ inst_val) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= desc->n_rec) return;
+    if (cnt->n_inst_ok == 0ull) return;
+    const uint32_t r = sorted_rec[j];
+    const uint2 tr = tile_rect[r];
+    const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu, y1 = tr.y >> 16;
+    if (x1 <= x0 || y1 <= y0) return;
+    const int v = find_view_by_rec(desc, r);
+    const ViewDesc& vd = desc->views[v];
+    uint32_t o = offs[j];
+    for (uint32_t ty = y0; ty < y1; ++ty) {
+        const uint32_t rowbase = (uint32_t)vd.tile_off + ty * (uint32_t)vd.tiles_x;
+        for (uint32_t tx = x0; tx < x1; ++tx) {
+            inst_key[o] = rowbase + tx;
+            inst_val[o] = r;
+            ++o;
+        }
+    }
+}
+
+// Forward of the standalone binning call: instance keys from caller arrays.
+__global__ __launch_bounds__(256) void k_emit_plain(const uint16_t* __restrict__ trect, const int32_t* __restrict__ view_of,
+                                                    const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ offs,
+                                                    int64_t n, int32_t tiles_x, int32_t tiles_y,
+                                                    const DevCounters* __restrict__ cnt, uint32_t* __restrict__ inst_key,
+                                                    uint32_t* __restrict__ inst_val) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (cnt->n_inst_ok == 0ull) return;
+    const uint32_t r = sorted_rec[j];
+    const uint32_t x0 = trect[4 * r], y0 = trect[4 * r + 1], x1 = trect[4 * r + 2], y1 = trect[4 * r + 3];
+    if (x1 <= x0 || y1 <= y0) return;
+    const uint32_t vw = view_of ? (uint32_t)view_of[r] : 0u;
+    uint32_t o = offs[j];
+    for (uint32_t ty = y0; ty < y1; ++ty)
+        for (uint32_t tx = x0; tx < x1; ++tx) {
+            inst_key[o] = (vw * (uint32_t)tiles_y + ty) * (uint32_t)tiles_x + tx;
+            inst_val[o] = r;
+            ++o;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_plain_counts(const uint16_t* __restrict__ trect, int64_t n,
+                                                      uint32_t* __restrict__ ntiles) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x0 = trect[4 * i], y0 = trect[4 * i + 1], x1 = trect[4 * i + 2], y1 = trect[4 * i + 3];
+    ntiles[i] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__ sorted_tile,
+                                                    const uint32_t* __restrict__ sorted_gid,
+                                                    const uint32_t* __restrict__ depth_key,
+                                                    const DevCounters* __restrict__ cnt, int64_t cap,
+                                                    uint64_t* __restrict__ out_key, uint32_t* __restrict__ out_gid) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t m = (int64_t)cnt->n_inst_ok;
+    if (m > cap) m = cap;
+    if (i >= m) return;
+    const uint32_t gid = sorted_gid[i];
+    if (out_key) out_key[i] = ((uint64_t)sorted_tile[i] << 32) | (uint64_t)depth_key[gid];
+    out_gid[i] = gid;
+}
+
+// ------------------------------------------------------------ forward blend
+// One wavefront per 16x16 tile; lane l shades pixels (l & 15, (l >> 4) + 4k),
+// k = 0..3.  The tile's sorted records are staged 64 at a time in LDS (one
+// load per lane) and read back as wave-uniform broadcasts.
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
+                                                         const uint32_t* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ inst_rec,
+                                                         const float4* __restrict__ rec_geom,
+                                                         const float4* __restrict__ rec_col,
+                                                         const float* __restrict__ rec_blue,
+                                                         float* __restrict__ image, float* __restrict__ T_final,
+                                                         int32_t* __restrict__ n_last) {
+    __shared__ float4 s_g[WPB][64];
+    __shared__ float4 s_c[WPB][64];
+    __shared__ float s_b[WPB][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
+    if (tile >= desc->n_tiles) return;
+    const int v = find_view_by_tile(desc, tile);
+    const ViewDesc& vd = desc->views[v];
+    const int64_t lt = tile - vd.tile_off;
+    const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
+    const int px = tx * kTile + (lane & 15);
+    const int py0 = ty * kTile + (lane >> 4);
+    const float fpx = (float)px;
+
+    float T[4], C0[4], C1[4], C2[4];
+    uint32_t last[4];
+    bool live[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T[k] = 1.f; C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0;
+        live[k] = px < vd.W && (py0 + 4 * k) < vd.H;
+    }
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    for (uint32_t b = start; b < end; b += 64) {
+        if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
+        const uint32_t idx = b + lane;
+        if (idx < end) {
+            const uint32_t r = inst_rec[idx];
+            s_g[w][lane] = rec_geom[r];
+            s_c[w][lane] = rec_col[r];
+            s_b[w][lane] = rec_blue[r];
+        }
+        wave_sync();
+        const int cnt = (int)min(64u, end - b);
+        for (int j = 0; j < cnt; ++j) {
+            if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
+            const float4 g = s_g[w][j];
+            const float4 c = s_c[w][j];
+            const float bl = s_b[w][j];
+            const uint32_t pos = (b - start) + (uint32_t)j + 1u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!live[k]) continue;
+                const float dx = fpx - g.x;
+                const float dy = (float)(py0 + 4 * k) - g.y;
+                float G;
+                bool pcl;
+                const float alpha = blend_alpha(dx, dy, g, c, G, pcl);
+                if (alpha < kMinAlpha) continue;
+                const float Tn = T[k] * (1.f - alpha);
+                if (Tn < kMinT) { live[k] = false; continue; }
+                const float wgt = alpha * T[k];
+                C0[k] = fmaf(wgt, c.z, C0[k]);
+                C1[k] = fmaf(wgt, c.w, C1[k]);
+                C2[k] = fmaf(wgt, bl, C2[k]);
+                T[k] = Tn;
+                last[k] = pos;
+            }
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int py = py0 + 4 * k;
+        if (px < vd.W && py < vd.H) {
+            const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
+            image[3 * p + 0] = C0[k] + T[k] * vd.bg[0];
+            image[3 * p + 1] = C1[k] + T[k] * vd.bg[1];
+            image[3 * p + 2] = C2[k] + T[k] * vd.bg[2];
+            T_final[p] = T[k];
+            n_last[p] = (int32_t)last[k];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, float4* rg, float4* rc,
+                             float* rb, uint32_t* dk, uint2* tr, uint32_t* nt, hipStream_t st) {
+    if (n_gauss <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rg, rc, rb, dk, tr, nt)
+    if (dtype == CGS_F32) {
+        switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
+                       case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }
+    } else {
+        switch (shd) { case 0: CGS_PRE(CGS_BF16, 0); break; case 1: CGS_PRE(CGS_BF16, 1); break;
+                       case 2: CGS_PRE(CGS_BF16, 2); break; default: CGS_PRE(CGS_BF16, 3); break; }
+    }
+#undef CGS_PRE
+    return hipGetLastError();
+}
+
+hipError_t launch_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info, hipStream_t st) {
+    hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, st, cnt, capacity, d_info);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const BatchDesc* d_desc, int64_t n_rec, const uint32_t* sorted_rec, const uint32_t* offs,
+                       const uint2* tr, const DevCounters* cnt, uint32_t* ik, uint32_t* iv, hipStream_t st) {
+    if (n_rec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0, st, d_desc, sorted_rec, offs, tr,
+                       cnt, ik, iv);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_counts(const uint16_t* trect, int64_t n, uint32_t* nt, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plain_counts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, trect, n, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_plain(const uint16_t* trect, const int32_t* view_of, const uint32_t* sorted_rec,
+                             const uint32_t* offs, int64_t n, int32_t tiles_x, int32_t tiles_y,
+                             const DevCounters* cnt, uint32_t* ik, uint32_t* iv, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit_plain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, trect, view_of, sorted_rec,
+                       offs, n, tiles_x, tiles_y, cnt, ik, iv);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_keys(const uint32_t* stile, const uint32_t* sgid, const uint32_t* dkey, const DevCounters* cnt,
+                             int64_t cap, uint64_t* out_key, uint32_t* out_gid, hipStream_t st) {
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plain_keys, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, stile, sgid, dkey, cnt, cap,
+                       out_key, out_gid);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_fwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
+                            const uint32_t* inst_rec, const float4* rg, const float4* rc, const float* rb,
+                            float* image, float* T_final, int32_t* n_last, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (wpb == 1) {
+        hipLaunchKernelGGL(k_blend_fwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rg, rc,
+                           rb, image, T_final, n_last);
+    } else if (wpb == 2) {
+        hipLaunchKernelGGL(k_blend_fwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
+                           inst_rec, rg, rc, rb, image, T_final, n_last);
+    } else {
+        hipLaunchKernelGGL(k_blend_fwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
+                           inst_rec, rg, rc, rb, image, T_final, n_last);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cgs

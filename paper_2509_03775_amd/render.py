@@ -1,0 +1,217 @@
+"""Torch-facing wrapper of libcgs: device-resident scenes, a view batch with its
+workspace, and a torch.autograd.Function whose backward calls
+cgs_render_backward.  PyTorch supplies device memory and streams only; every
+step of the render runs in the HIP library (see cgs.py).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import cgs
+from . import scenes as sc
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class DeviceScene:
+    """One scene's state on the GPU in the fused single-codebook layout:
+    means float32 [N,3], idx int32 [N], codebook [K, 8 + 3(d+1)^2] in float32
+    or bfloat16 (row: log-scale 3, quaternion 4, opacity logit 1, SH)."""
+
+    def __init__(self, means: torch.Tensor, idx: torch.Tensor, cb: torch.Tensor, sh_degree: int):
+        assert means.dtype == torch.float32 and means.is_contiguous() and means.dim() == 2 and means.shape[1] == 3
+        assert idx.dtype == torch.int32 and idx.is_contiguous() and idx.shape[0] == means.shape[0]
+        assert cb.dtype in (torch.float32, torch.bfloat16) and cb.is_contiguous()
+        assert cb.shape[1] == sc.row_width(sh_degree)
+        self.means, self.idx, self.cb, self.sh_degree = means, idx, cb, sh_degree
+
+    @classmethod
+    def from_host(cls, s: sc.Scene, device="cuda", bf16: Optional[bool] = None) -> "DeviceScene":
+        use_bf16 = (s.cb_bf16 is not None) if bf16 is None else bf16
+        means = torch.from_numpy(np.ascontiguousarray(s.means)).to(device)
+        idx = torch.from_numpy(np.ascontiguousarray(s.idx)).to(device)
+        if use_bf16:
+            bits = s.cb_bf16 if s.cb_bf16 is not None else sc.f32_to_bf16_bits(s.cb)
+            cb = torch.from_numpy(bits.view(np.int16)).to(device).view(torch.bfloat16)
+        else:
+            cb = torch.from_numpy(np.ascontiguousarray(s.cb)).to(device)
+        return cls(means, idx, cb.contiguous(), s.sh_degree)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def k(self) -> int:
+        return int(self.cb.shape[0])
+
+    @property
+    def r(self) -> int:
+        return int(self.cb.shape[1])
+
+    def descriptor(self) -> cgs.Scene:
+        dt = cgs.CGS_BF16 if self.cb.dtype == torch.bfloat16 else cgs.CGS_F32
+        d = cgs.Scene()
+        d.n = self.n
+        d.sh_degree = self.sh_degree
+        d.opacity_mode = 1
+        d.means = self.means.data_ptr()
+        d.idx_sr = self.idx.data_ptr()
+        d.idx_sh = self.idx.data_ptr()
+        d.sr = cgs.CbView(self.cb.data_ptr(), dt, self.r, self.k, 0, 0)
+        d.sh = cgs.CbView(self.cb.data_ptr(), dt, self.r, self.k, 8, 0)
+        d.opacity_logit = None
+        return d
+
+
+def camera_struct(c: sc.Camera) -> cgs.Camera:
+    out = cgs.Camera()
+    out.width, out.height = int(c.width), int(c.height)
+    out.fx, out.fy, out.cx, out.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+    out.Rt[:] = [float(x) for x in np.asarray(c.Rt, np.float32).reshape(12)]
+    out.campos[:] = [float(x) for x in np.asarray(c.campos, np.float32)]
+    out.bg[:] = [float(x) for x in np.asarray(c.bg, np.float32)]
+    return out
+
+
+class Renderer:
+    """A batch of views over device scenes with a persistent workspace and
+    preallocated outputs.  forward()/backward() enqueue on the current stream
+    and never synchronise (graph-capturable); fit_capacity() sizes the
+    instance buffers from a measured run."""
+
+    def __init__(self, scenes: Sequence[DeviceScene], cameras: Sequence[sc.Camera],
+                 view_scene: Sequence[int], capacity: Optional[int] = None,
+                 waves_per_block: int = 4, tile_order: int = 0, device="cuda"):
+        self.scenes = list(scenes)
+        self.cameras = list(cameras)
+        self.device = torch.device(device)
+        nv, ns = len(self.cameras), len(self.scenes)
+        self._scene_arr = (cgs.Scene * ns)(*[s.descriptor() for s in self.scenes])
+        self._cam_arr = (cgs.Camera * nv)(*[camera_struct(c) for c in self.cameras])
+        self._vs_arr = (ctypes.c_int32 * nv)(*[int(v) for v in view_scene])
+        self.view_scene = [int(v) for v in view_scene]
+        self._sched = cgs.Schedule()
+        self._sched.blend_waves_per_block = waves_per_block
+        self._sched.tile_order = tile_order
+        self.n_pixels = sum(c.width * c.height for c in self.cameras)
+        self.pix_off = np.concatenate([[0], np.cumsum([c.width * c.height for c in self.cameras])]).astype(np.int64)
+        if capacity is None:
+            capacity = max(1024, int(3 * sum(self.scenes[v].n for v in self.view_scene)))
+        self.batch = cgs.Batch()
+        self.batch.scenes = ctypes.cast(self._scene_arr, ctypes.POINTER(cgs.Scene))
+        self.batch.n_scenes = ns
+        self.batch.n_views = nv
+        self.batch.cameras = ctypes.cast(self._cam_arr, ctypes.POINTER(cgs.Camera))
+        self.batch.view_scene = ctypes.cast(self._vs_arr, ctypes.POINTER(ctypes.c_int32))
+        self.batch.schedule = ctypes.pointer(self._sched)
+        self.image = torch.empty((self.n_pixels, 3), dtype=torch.float32, device=self.device)
+        self.T_final = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
+        self.n_last = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
+        self.d_info = torch.zeros(4, dtype=torch.int64, device=self.device)
+        self.grad_means = [torch.empty_like(s.means) for s in self.scenes]
+        self.grad_cb = [torch.empty((s.k, s.r), dtype=torch.float32, device=self.device) for s in self.scenes]
+        gr = []
+        for s, gm, gc in zip(self.scenes, self.grad_means, self.grad_cb):
+            g = cgs.SceneGrads()
+            g.means = gm.data_ptr()
+            g.sr, g.sr_stride, g.sr_col0 = gc.data_ptr(), s.r, 0
+            g.sh, g.sh_stride, g.sh_col0 = gc.data_ptr(), s.r, 8
+            g.opacity = None
+            gr.append(g)
+        self._grads = (cgs.SceneGrads * ns)(*gr)
+        self.set_capacity(capacity)
+
+    def set_capacity(self, capacity: int) -> None:
+        self.capacity = int(capacity)
+        self.batch.instance_capacity = self.capacity
+        nbytes = cgs.workspace_bytes(self.batch)
+        if nbytes == 0:
+            raise cgs.CgsError("cgs_workspace_bytes", cgs.CGS_EINVAL)
+        self.ws_bytes = nbytes
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def forward(self, stream=None) -> torch.Tensor:
+        cgs.render_forward(self.batch, self.image.data_ptr(), self.T_final.data_ptr(), self.n_last.data_ptr(),
+                           self.ws.data_ptr(), self.ws_bytes, self.d_info.data_ptr(), _stream_ptr(stream))
+        return self.image
+
+    def backward(self, grad_image: torch.Tensor, stream=None):
+        assert grad_image.dtype == torch.float32 and grad_image.is_contiguous()
+        assert grad_image.numel() == 3 * self.n_pixels
+        cgs.render_backward(self.batch, grad_image.data_ptr(), self.T_final.data_ptr(), self.n_last.data_ptr(),
+                            self._grads, self.ws.data_ptr(), self.ws_bytes, self.d_info.data_ptr(),
+                            _stream_ptr(stream))
+        return self.grad_means, self.grad_cb
+
+    def instances(self) -> int:
+        """Instances the last forward needed (synchronises)."""
+        return int(self.d_info[1].item())
+
+    def fit_capacity(self, slack: float = 1.05) -> int:
+        """Run the forward, and if the instance buffers overflowed, grow them
+        and run again (synchronises; call outside timed or captured regions)."""
+        self.forward()
+        torch.cuda.synchronize()
+        info = self.d_info.cpu().numpy()
+        if info[0] == cgs.CGS_ECAPACITY:
+            self.set_capacity(int(info[1] * slack) + 1024)
+            self.forward()
+            torch.cuda.synchronize()
+            info = self.d_info.cpu().numpy()
+            if info[0] != cgs.CGS_OK:
+                raise cgs.CgsError("cgs_render_forward (capacity)", int(info[0]))
+        return int(info[1])
+
+    def layout(self) -> cgs.WsLayout:
+        return cgs.workspace_layout(self.batch)
+
+    def view_image(self, v: int) -> torch.Tensor:
+        c = self.cameras[v]
+        return self.image[self.pix_off[v]:self.pix_off[v + 1]].view(c.height, c.width, 3)
+
+
+class CgsRenderFunction(torch.autograd.Function):
+    """image = render(means_0, codebook_0, means_1, codebook_1, ...).
+
+    The backward recomputes each blended Gaussian's transmittance from the
+    per-pixel final transmittance instead of storing it per pair."""
+
+    @staticmethod
+    def forward(ctx, renderer: Renderer, *tensors):
+        ctx.renderer = renderer
+        img = renderer.forward()
+        return img.clone()
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        r: Renderer = ctx.renderer
+        gm, gc = r.backward(grad_image.contiguous().float())
+        out: List[Optional[torch.Tensor]] = [None]
+        for s, m, c in zip(r.scenes, gm, gc):
+            out.append(m.clone())
+            out.append(c.clone().to(s.cb.dtype))
+        return tuple(out)
+
+
+def render(renderer: Renderer) -> torch.Tensor:
+    """Differentiable render of every view of the batch ([pixels, 3])."""
+    tensors = []
+    for s in renderer.scenes:
+        tensors += [s.means, s.cb]
+    return CgsRenderFunction.apply(renderer, *tensors)
+
+
+def loss_l1(image: torch.Tensor, target: torch.Tensor, grad: torch.Tensor, loss: torch.Tensor,
+            ws: torch.Tensor, stream=None) -> None:
+    """L1 loss and its gradient by the library kernel (writes grad and loss)."""
+    n = image.numel()
+    cgs.loss_l1(image.data_ptr(), target.data_ptr(), n, grad.data_ptr(), loss.data_ptr(), ws.data_ptr(),
+                ws.numel(), _stream_ptr(stream))
