@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Forward+backward rendered Mpixel/s of the codebook-indexed differentiable
+Gaussian-splatting hot path on one MI355X.
+
+A step is one pass of the whole path over one batch: preprocess (codebook
+gather, projection, SH colour), tile binning (depth sort, emission, tile
+sort), forward blend, L1 loss, backward blend, per-Gaussian chain rule and the
+codebook-gradient reduction.  Inputs are seeded synthetic scenes resident in
+HBM before the timed region.  The headline line measures the 4M-Gaussian,
+BF16-codebook workload with its four 1957x1091 views in one batched call;
+the plain-FP32 form (FP32 codebook, one call per view) and the 1M-Gaussian
+workload are reported beside it in "forms".
+
+Prints ONE JSON line.  --gpus N with N > 1 is refused: this build measures a
+single GPU.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2509_03775_amd import cgs, render, scenes as sc  # noqa: E402
+
+METRIC = "fwd+bwd rendered Mpixel/s at 1M/4M Gaussians, BF16-batched vs plain FP32"
+HEADLINE = "clusters4m_bf16_4x1957x1091"
+VALU_PEAK = 256 * 4 * 16 * 2.4e9        # FP32 lane-operations/s, non-packed issue rate
+HBM_PEAK = 8.0e12                       # bytes/s
+# Algorithmic FP32 operations per (pixel, Gaussian) pair (an FMA, an exp, a
+# compare each count as one): alpha of a pair (2 sub, 5 for the quadratic
+# form, exp, opacity product, 0.99 clamp, 1/255 test) = 11; a blended pair
+# adds 8 in the forward (1-alpha, T product, T test, weight, 3 colour FMAs,
+# count) and 30 in the backward (T recovery 2, weight 1, colour grads 3,
+# alpha grad 7, background update 3, opacity grad 2, power grads 12).
+OPS_ALPHA, OPS_FWD_BLEND, OPS_BWD_BLEND = 11, 8, 30
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """hipEvent_t handles created through the HIP runtime torch already loaded."""
+
+    def __init__(self, n):
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.ev = (ctypes.c_void_p * n)()
+        for i in range(n):
+            h = ctypes.c_void_p()
+            rc = self.lib.hipEventCreate(ctypes.byref(h))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed ({rc})")
+            self.ev[i] = h
+
+    def slice(self, i, n):
+        return ctypes.cast(ctypes.byref(self.ev, i * ctypes.sizeof(ctypes.c_void_p)), ctypes.POINTER(ctypes.c_void_p))
+
+    def elapsed(self, i, j):
+        out = ctypes.c_float()
+        rc = self.lib.hipEventElapsedTime(ctypes.byref(out), self.ev[i], self.ev[j])
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return out.value
+
+
+class Form:
+    """One way to run a step: `batched` renders every view in one call; `plain`
+    issues one call per view."""
+
+    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08):
+        self.wl = wl
+        self.batched = batched
+        ds = [render.DeviceScene.from_host(s, bf16=wl.bf16) for s in wl.scenes]
+        self.scenes = ds
+        if batched:
+            groups = [list(range(len(wl.cameras)))]
+        else:
+            groups = [[v] for v in range(len(wl.cameras))]
+        self.renderers = []
+        self.targets, self.grads, self.losses = [], [], []
+        for gidx in groups:
+            used = sorted(set(int(wl.view_scene[v]) for v in gidx))
+            remap = {s: i for i, s in enumerate(used)}
+            r = render.Renderer([ds[s] for s in used], [wl.cameras[v] for v in gidx],
+                                [remap[int(wl.view_scene[v])] for v in gidx])
+            m = r.fit_capacity()
+            r.set_capacity(int(m * capacity_slack) + 4096)
+            r.fit_capacity()
+            tgt = np.concatenate([wl.targets[v].reshape(-1, 3) for v in gidx], 0)
+            self.targets.append(torch.from_numpy(tgt).cuda())
+            self.grads.append(torch.empty_like(self.targets[-1]))
+            self.losses.append(torch.zeros(1, device="cuda"))
+            self.renderers.append(r)
+        n = max(t.numel() for t in self.targets)
+        self.loss_ws = torch.empty(cgs.loss_l1_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+        self.n_pixels = wl.n_pixels
+
+    def step(self):
+        for r, t, g, l in zip(self.renderers, self.targets, self.grads, self.losses):
+            img = r.forward()
+            render.loss_l1(img, t, g, l, self.loss_ws)
+            r.backward(g)
+
+    def time(self, steps, warmup, events: HipEvents = None):
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0 = self.renderers[0]
+        e0.record()
+        for k in range(steps):
+            if events is not None:
+                r0._sched.stage_events = events.slice(k * cgs.STAGE_EVENTS, cgs.STAGE_EVENTS)
+            self.step()
+        e1.record()
+        torch.cuda.synchronize()
+        if events is not None:
+            r0._sched.stage_events = None
+        return e0.elapsed_time(e1) / steps
+
+
+def stage_times(ev: HipEvents, steps):
+    names = [("preprocess", 0, 1), ("binning", 1, 2), ("blend_fwd", 2, 3), ("blend_bwd", 4, 5),
+             ("chain", 5, 6), ("codebook_reduce", 6, 7)]
+    out = {}
+    for name, a, b in names:
+        out[name] = float(np.mean([ev.elapsed(k * cgs.STAGE_EVENTS + a, k * cgs.STAGE_EVENTS + b)
+                                   for k in range(steps)]))
+    return out
+
+
+def pair_counts(form: Form):
+    """Pairs the backward evaluates (sum of n_last) and pairs blended."""
+    e_eval = e_blend = 0
+    for r in form.renderers:
+        r.forward()
+        e_eval += int(r.n_last.to(torch.int64).sum().item())
+        nb = torch.zeros(r.n_pixels, dtype=torch.int32, device="cuda")
+        r._sched.n_blend = nb.data_ptr()
+        r.forward()
+        torch.cuda.synchronize()
+        r._sched.n_blend = None
+        e_blend += int(nb.to(torch.int64).sum().item())
+    return e_eval, e_blend
+
+
+def cpu_baseline(wl: sc.Workload, target_s: float):
+    """The FP64 oracle on a bounded sample of the same workload: forward, L1
+    gradient and backward of randomly chosen 16x16 tiles of view 0."""
+    import oracle
+    cam, s = wl.cameras[0], wl.scenes[int(wl.view_scene[0])]
+    P = wl.n_pixels
+    rng = np.random.default_rng(7)
+    tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
+
+    def run(ntiles):
+        pick = rng.choice(tx * ty, size=ntiles, replace=False)
+        pix = []
+        for t in pick:
+            x0, y0 = (t % tx) * 16, (t // tx) * 16
+            yy, xx = np.mgrid[y0:min(y0 + 16, cam.height), x0:min(x0 + 16, cam.width)]
+            pix.append(np.stack([xx.ravel(), yy.ravel()], 1))
+        pix = np.concatenate(pix).astype(np.int32)
+        t0 = time.perf_counter()
+        o = oracle.render_view(s, cam, pix)
+        tgt = wl.targets[0][pix[:, 1], pix[:, 0]].astype(np.float64)
+        g = np.sign(o["color"] - tgt) / (3.0 * P)
+        o2 = oracle.render_view(s, cam, pix, grad_color=g)
+        oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
+        return time.perf_counter() - t0, pix.shape[0], ntiles
+
+    t1, _, _ = run(2)
+    n = int(max(2, min(512, 2 * target_s / max(t1, 1e-3))))
+    dt, npix, ntiles = run(n)
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": npix / dt / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
+                      f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}
+
+
+def blend_roofline(stage, ms, e_eval, e_blend):
+    if stage == "blend_fwd":
+        ops = OPS_ALPHA * e_eval + OPS_FWD_BLEND * e_blend
+    else:
+        ops = OPS_ALPHA * e_eval + OPS_BWD_BLEND * e_blend
+    ach = ops / (ms * 1e-3)
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
+            "frac": ach / VALU_PEAK, "traffic": None, "kernel": "k_blend_bwd" if stage == "blend_bwd" else "k_blend_fwd",
+            "ops_per_launch": ops}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--extra-forms", default="fp32_plain,1m", help="comma list: fp32_plain, 1m, none")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the path shards by view; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cgs.load()
+    torch.cuda.set_device(0)
+
+    log(f"[bench] generating {args.workload}")
+    wl = sc.make_workload(args.workload)
+    head = Form(wl, batched=True)
+    ev = HipEvents(args.steps * cgs.STAGE_EVENTS)
+    log(f"[bench] timing {args.workload} batched: {args.steps} steps after {args.warmup} warmup")
+    ms = head.time(args.steps, args.warmup, ev)
+    stages = stage_times(ev, args.steps)
+    value = wl.n_pixels / (ms * 1e-3) / 1e6
+    e_eval, e_blend = pair_counts(head)
+    dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
+    roof = blend_roofline(dom, stages[dom], e_eval, e_blend)
+    forms = {f"{'bf16' if wl.bf16 else 'fp32'}_batched:{args.workload}": value}
+    extras = [x for x in args.extra_forms.split(",") if x and x != "none"]
+    del head
+    torch.cuda.empty_cache()
+    if "fp32_plain" in extras:
+        log(f"[bench] timing {args.workload} plain fp32")
+        wl32 = sc.make_workload(args.workload, bf16=False)
+        f = Form(wl32, batched=False)
+        forms[f"fp32_plain:{args.workload}"] = wl32.n_pixels / (f.time(max(3, args.steps // 2), 2) * 1e-3) / 1e6
+        del f
+        torch.cuda.empty_cache()
+    if "1m" in extras:
+        name = "clusters1m_1600x1064"
+        for bf in (True, False):
+            log(f"[bench] timing {name} {'bf16 batched' if bf else 'fp32 plain'}")
+            w1 = sc.make_workload(name, bf16=bf)
+            f = Form(w1, batched=bf)
+            forms[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = \
+                w1.n_pixels / (f.time(max(3, args.steps // 2), 2) * 1e-3) / 1e6
+            del f
+            torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+    cam = wl.cameras[0]
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "form": "batched", "codebook_storage": "bf16" if wl.bf16 else "f32",
+                   "gaussians": int(sum(s.n for s in wl.scenes)), "codebook_rows": int(wl.scenes[0].k),
+                   "sh_degree": int(wl.scenes[0].sh_degree), "views": len(wl.cameras),
+                   "resolution": f"{cam.width}x{cam.height}", "pixels": int(wl.n_pixels)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "stages_ms": stages,
+        "pairs": {"evaluated": e_eval, "blended": e_blend},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,11 +109,22 @@ typedef struct {
     float* opacity;
 } cgs_scene_grads;
 
-/* Launch schedule knobs; zero-initialised fields take the defaults. */
+/* Launch schedule knobs and optional instrumentation; zero-initialised
+ * fields take the defaults.
+ * stage_events: host array [CGS_STAGE_EVENTS] of hipEvent_t (caller-created)
+ *   or NULL.  When set, the forward records event 0 before its first launch,
+ *   1 after preprocessing, 2 after binning, 3 after the blend; the backward
+ *   records 4 just before the backward blend, 5 after it, 6 after the
+ *   per-Gaussian chain rule, 7 after the codebook reduction.  All on `stream`.
+ * n_blend: device int32 [P] or NULL; when set the forward also writes the
+ *   number of Gaussians blended into each pixel (a slower instrumented blend). */
+enum { CGS_STAGE_EVENTS = 8 };
 typedef struct {
-    int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup; default 4 */
+    int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup: 1, 2 or 4 (default) */
     int32_t tile_order;              /* 0: row-major tiles, 1: XCD-grouped order */
-    int32_t reserved[6];
+    int32_t reserved[2];
+    void** stage_events;
+    int32_t* n_blend;
 } cgs_schedule;
 
 /* A batch of views over one or more scenes, rendered by one call. */
@@ -157,9 +168,9 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
  * every blended Gaussian is recomputed from T_final by division, not stored).
  * Writes, per scene, dL/dmeans and dL/dcodebook: the per-Gaussian parameter
  * gradients summed over Gaussians sharing a codebook row (the gradient of
- * S_diff needed by the update step, Sec. 4.4).  Deterministic for the
- * codebook rows (fixed-order segmented sums); the means gradients use
- * floating-point atomics over tiles.  grads: host array [n_scenes]. */
+ * S_diff needed by the update step, Sec. 4.4).  Deterministic: every sum is
+ * taken in a fixed order (no floating-point atomics), so repeated calls give
+ * bitwise-identical gradients.  grads: host array [n_scenes]. */
 cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image,
                                const float* T_final, const int32_t* n_last,
                                const cgs_scene_grads* grads,

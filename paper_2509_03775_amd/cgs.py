@@ -43,8 +43,12 @@ class SceneGrads(ctypes.Structure):
                 ("sh", c_void_p), ("sh_stride", c_int32), ("sh_col0", c_int32), ("opacity", c_void_p)]
 
 
+STAGE_EVENTS = 8
+
+
 class Schedule(ctypes.Structure):
-    _fields_ = [("blend_waves_per_block", c_int32), ("tile_order", c_int32), ("reserved", c_int32 * 6)]
+    _fields_ = [("blend_waves_per_block", c_int32), ("tile_order", c_int32), ("reserved", c_int32 * 2),
+                ("stage_events", POINTER(c_void_p)), ("n_blend", c_void_p)]
 
 
 class Batch(ctypes.Structure):

@@ -16,18 +16,19 @@ hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, float
                              uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const DevCounters*,
-                       uint32_t*, uint32_t*, hipStream_t);
+                       uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, const uint32_t*, int64_t, int32_t,
                              int32_t, const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_keys(const uint32_t*, const uint32_t*, const uint32_t*, const DevCounters*, int64_t,
                              uint64_t*, uint32_t*, hipStream_t);
 hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            const float4*, const float*, float*, float*, int32_t*, hipStream_t);
+                            const float4*, const float*, float*, float*, int32_t*, int32_t*, hipStream_t);
 hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            const float4*, const float*, const float*, const float*, const int32_t*, float*,
-                            hipStream_t);
-hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, float*, hipStream_t);
+                            const float4*, const float*, const uint2*, const uint32_t*, const float*, const float*,
+                            const int32_t*, float*, hipStream_t);
+hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const uint32_t*, const uint32_t*,
+                        const DevCounters*, float*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, float*, hipStream_t);
@@ -56,6 +57,8 @@ struct Host {
     int dsort_buf;         // buffer pair holding the depth-sorted records
     int tile_bits;
     bool fused;            // every scene uses the single-codebook layout
+    hipEvent_t* events;    // optional stage events
+    int32_t* n_blend;      // optional per-pixel blended count
     int opacity_mode;
     int64_t rows_total;    // rows of the reduction key space (max of both parts)
 };
@@ -167,6 +170,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     h->wpb = (sch && (sch->blend_waves_per_block == 1 || sch->blend_waves_per_block == 2)) ? sch->blend_waves_per_block
                                                                                             : 4;
     d.tile_order = sch ? sch->tile_order : 0;
+    h->events = sch ? reinterpret_cast<hipEvent_t*>(sch->stage_events) : nullptr;
+    h->n_blend = sch ? sch->n_blend : nullptr;
     h->tile_bits = bits_for(d.n_tiles);
     h->inst_buf = (passes_for(h->tile_bits) - 1) & 1;
     h->dsort_buf = (passes_for(31) - 1) & 1;
@@ -193,7 +198,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.radix_counts = take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(p.radix_blocks_max, 1));
     p.scan_blocks_max = (int64_t)scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * p.radix_blocks_max));
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
-    p.g2d = take(4 * 9 * (size_t)R);
+    p.emit_off = take(4 * (size_t)R);
+    p.ginst = take(4 * 9 * (size_t)cap);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
     p.row_start = take(8 * (size_t)(h->rows_total + 1));
@@ -220,6 +226,10 @@ hipError_t upload_desc(const Host& h, void* ws, hipStream_t st) {
     const size_t so = offsetof(BatchDesc, scenes);
     return upload_bytes(base + so, reinterpret_cast<const char*>(&h.d) + so, sizeof(SceneDesc) * (size_t)h.d.n_scenes,
                         st);
+}
+
+hipError_t mark(const Host& h, int i, hipStream_t st) {
+    return h.events ? hipEventRecord(h.events[i], st) : hipSuccess;
 }
 
 }  // namespace
@@ -280,10 +290,12 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     DevCounters* cnt = at<DevCounters>(ws, p.counters);
     unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
     uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
+    CGS_TRY(mark(h, 0, st));
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, at<float4>(ws, p.rec_geom),
                               at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), st));
+    CGS_TRY(mark(h, 1, st));
     // depth order of every record (stable: ties keep record order)
     uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
     uint32_t* dv[2] = {at<uint32_t>(ws, p.dsort_val[0]), at<uint32_t>(ws, p.dsort_val[1])};
@@ -297,14 +309,16 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
     uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
     CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.tile_rect), cnt, ik[1], iv[1],
-                        st));
+                        at<uint32_t>(ws, p.emit_off), st));
     int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, counts, bsum, st, &e);
     CGS_TRY(e);
     if (ib != h.inst_buf) return CGS_EHIP;
     CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
+    CGS_TRY(mark(h, 2, st));
     CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
                              at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), image,
-                             T_final, n_last, st));
+                             T_final, n_last, h.n_blend, st));
+    CGS_TRY(mark(h, 3, st));
     return CGS_OK;
 }
 
@@ -348,14 +362,17 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
     uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
     DevCounters* cnt = at<DevCounters>(ws, p.counters);
     CGS_TRY(upload_desc(h, ws, st));
-    float* g2d = at<float>(ws, p.g2d);
-    CGS_TRY(fill_u32(g2d, 0u, 9 * (size_t)h.d.n_rec, st));
+    CGS_TRY(mark(h, 4, st));
+    float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
                              at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue),
-                             grad_image, T_final, n_last, g2d, st));
+                             at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.emit_off), grad_image, T_final, n_last,
+                             ginst, st));
+    CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
-    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, g2d, gth, st));
-    (void)cnt;
+    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, ginst, at<uint32_t>(ws, p.emit_off),
+                         at<uint32_t>(ws, p.ntiles), cnt, gth, st));
+    CGS_TRY(mark(h, 6, st));
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
     uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
     uint32_t* rr = at<uint32_t>(ws, p.row_start);
@@ -375,6 +392,7 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
         CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, part,
                               st));
     }
+    CGS_TRY(mark(h, 7, st));
     return CGS_OK;
 }
 

@@ -12,8 +12,12 @@ namespace cgs {
 // its list from n_last-1 down to 0, re-derives alpha with the forward's code,
 // recovers T before the Gaussian as T_after / (1 - alpha), and accumulates
 // dL/d(u, v, -A/2, -B, -C/2, opacity, r, g, b).  The four pixels of a lane are
-// summed in registers, the 64 lanes by a DPP reduction, and one lane adds the
-// tile's total with a global atomic per value.
+// summed in registers and the 64 lanes by a DPP reduction.  The tile's total
+// for a record goes to that (tile, record) instance's own slot -- slot =
+// the record's emission offset + the tile's row-major index in the record's
+// rectangle -- with plain stores: no atomics, and the per-record sum over its
+// tiles is taken later in a fixed order, so the backward is deterministic.
+// Instances the walk never reaches (beyond every pixel's n_last) get zeros.
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
@@ -21,14 +25,16 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                                                          const float4* __restrict__ rec_geom,
                                                          const float4* __restrict__ rec_col,
                                                          const float* __restrict__ rec_blue,
+                                                         const uint2* __restrict__ tile_rect,
+                                                         const uint32_t* __restrict__ emit_off,
                                                          const float* __restrict__ grad_image,
                                                          const float* __restrict__ T_final,
                                                          const int32_t* __restrict__ n_last,
-                                                         float* __restrict__ g2d) {
+                                                         float* __restrict__ ginst) {
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
-    __shared__ uint32_t s_r[WPB][64];
+    __shared__ float s_o[WPB][64][9];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
     if (tile >= desc->n_tiles) return;
@@ -63,15 +69,21 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     const uint32_t start = ranges[2 * tile];
     const uint32_t len = ranges[2 * tile + 1] - start;
     if (maxlast > len) maxlast = len;     // n_last inconsistent with this binning: stay in the list
+    auto slot_of = [&](uint32_t r) -> int64_t {
+        const uint2 tr = tile_rect[r];
+        const int x0 = (int)(tr.x & 0xffffu), y0 = (int)(tr.x >> 16), x1 = (int)(tr.y & 0xffffu);
+        return (int64_t)emit_off[r] + (int64_t)(ty - y0) * (x1 - x0) + (tx - x0);
+    };
     for (int64_t bend = maxlast; bend > 0; bend -= 64) {
         const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
         const int64_t li = bbeg + lane;
+        int64_t slot = -1;
         if (li < bend) {
             const uint32_t r = inst_rec[start + li];
-            s_r[w][lane] = r;
             s_g[w][lane] = rec_geom[r];
             s_c[w][lane] = rec_col[r];
             s_b[w][lane] = rec_blue[r];
+            slot = slot_of(r);
         }
         wave_sync();
         for (int j = (int)(bend - bbeg) - 1; j >= 0; --j) {
@@ -116,19 +128,30 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                     }
                 }
             }
+            float sums[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             if (__ballot(any) != 0ull) {
-                const float s0 = wave_sum(a_u), s1 = wave_sum(a_v), s2 = wave_sum(a_a);
-                const float s3 = wave_sum(a_b), s4 = wave_sum(a_c), s5 = wave_sum(a_o);
-                const float s6 = wave_sum(a_r), s7 = wave_sum(a_g), s8 = wave_sum(a_bl);
-                if (lane == 0) {
-                    float* dst = g2d + 9 * (int64_t)s_r[w][j];
-                    atomicAdd(dst + 0, s0); atomicAdd(dst + 1, s1); atomicAdd(dst + 2, s2);
-                    atomicAdd(dst + 3, s3); atomicAdd(dst + 4, s4); atomicAdd(dst + 5, s5);
-                    atomicAdd(dst + 6, s6); atomicAdd(dst + 7, s7); atomicAdd(dst + 8, s8);
-                }
+                sums[0] = wave_sum(a_u); sums[1] = wave_sum(a_v); sums[2] = wave_sum(a_a);
+                sums[3] = wave_sum(a_b); sums[4] = wave_sum(a_c); sums[5] = wave_sum(a_o);
+                sums[6] = wave_sum(a_r); sums[7] = wave_sum(a_g); sums[8] = wave_sum(a_bl);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) s_o[w][j][k] = sums[k];
             }
         }
         wave_sync();
+        if (slot >= 0) {
+            float* dst = ginst + 9 * slot;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) dst[k] = s_o[w][lane][k];
+        }
+        wave_sync();
+    }
+    // list positions no pixel of this tile reached: zero gradient
+    for (uint32_t li = maxlast + (uint32_t)lane; li < len; li += 64) {
+        float* dst = ginst + 9 * slot_of(inst_rec[start + li]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) dst[k] = 0.f;
     }
 }
 
@@ -137,8 +160,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
 // the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
 template <int DT, int SHD>
-__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ g2d,
-                                               float* __restrict__ gtheta) {
+__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
+                                               const uint32_t* __restrict__ emit_off,
+                                               const uint32_t* __restrict__ ntiles,
+                                               const DevCounters* __restrict__ cnt, float* __restrict__ gtheta) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gg >= desc->n_gauss) return;
@@ -165,16 +190,23 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
 #pragma unroll
     for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
     float dop = 0.f;
+    const bool binned = cnt->n_inst_ok != 0ull;
 
     for (int vi = 0; vi < sd.vcount; ++vi) {
         const int v = desc->view_list[sd.vfirst + vi];
         const ViewDesc& vd = desc->views[v];
         const int64_t r = vd.rec_off + g;
-        const float* gr = g2d + 9 * r;
-        float d[9];
+        // dL/d(record) = sum over the record's tile instances, in emission order
+        const uint32_t nt = binned ? ntiles[r] : 0u;
+        if (nt == 0u) continue;
+        float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const float* gi = ginst + 9 * (int64_t)emit_off[r];
+        for (uint32_t e = 0; e < nt; ++e)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] += gi[9 * e + i];
         bool nz = false;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) { d[i] = gr[i]; nz |= d[i] != 0.f; }
+        for (int i = 0; i < 9; ++i) nz |= d[i] != 0.f;
         if (!nz) continue;
         ViewProj p;
         if (!project_view(vd, gp.mean, sh, p)) continue;
@@ -484,7 +516,7 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-__global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part, int nb, float inv_n,
+__global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part, int nb, int64_t n,
                                                   float* __restrict__ loss) {
     __shared__ double s[256];
     double acc = 0.0;
@@ -495,33 +527,34 @@ __global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part
         if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *loss = (float)(s[0] * (double)inv_n);
+    if (threadIdx.x == 0) *loss = n > 0 ? (float)(s[0] / (double)n) : 0.f;
 }
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
                             const uint32_t* inst_rec, const float4* rg, const float4* rc, const float* rb,
-                            const float* grad_image, const float* T_final, const int32_t* n_last, float* g2d,
-                            hipStream_t st) {
+                            const uint2* tr, const uint32_t* eo, const float* grad_image, const float* T_final,
+                            const int32_t* n_last, float* ginst, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (wpb == 1) {
         hipLaunchKernelGGL(k_blend_bwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rg, rc,
-                           rb, grad_image, T_final, n_last, g2d);
+                           rb, tr, eo, grad_image, T_final, n_last, ginst);
     } else if (wpb == 2) {
         hipLaunchKernelGGL(k_blend_bwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
-                           inst_rec, rg, rc, rb, grad_image, T_final, n_last, g2d);
+                           inst_rec, rg, rc, rb, tr, eo, grad_image, T_final, n_last, ginst);
     } else {
         hipLaunchKernelGGL(k_blend_bwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
-                           inst_rec, rg, rc, rb, grad_image, T_final, n_last, g2d);
+                           inst_rec, rg, rc, rb, tr, eo, grad_image, T_final, n_last, ginst);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, const float* g2d, float* gtheta,
+hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, const float* ginst,
+                        const uint32_t* eo, const uint32_t* nt, const DevCounters* cnt, float* gtheta,
                         hipStream_t st) {
     if (n_gauss <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
-#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, g2d, gtheta)
+#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, ginst, eo, nt, cnt, gtheta)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_CH(CGS_F32, 0); break; case 1: CGS_CH(CGS_F32, 1); break;
                        case 2: CGS_CH(CGS_F32, 2); break; default: CGS_CH(CGS_F32, 3); break; }
@@ -568,7 +601,7 @@ hipError_t launch_l1(const float* img, const float* tgt, int64_t n, float* grad,
                      int nb, hipStream_t st) {
     const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
     if (n > 0) hipLaunchKernelGGL(k_l1, dim3(nb), dim3(256), 0, st, img, tgt, n, inv, grad, part);
-    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, st, part, n > 0 ? nb : 0, 1.0f, loss);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, st, part, n > 0 ? nb : 0, n, loss);
     return hipGetLastError();
 }
 

@@ -72,11 +72,12 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
 __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ sorted_rec,
                                               const uint32_t* __restrict__ offs, const uint2* __restrict__ tile_rect,
                                               const DevCounters* __restrict__ cnt, uint32_t* __restrict__ inst_key,
-                                              uint32_t* __restrict__ inst_val) {
+                                              uint32_t* __restrict__ inst_val, uint32_t* __restrict__ emit_off) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= desc->n_rec) return;
-    if (cnt->n_inst_ok == 0ull) return;
     const uint32_t r = sorted_rec[j];
+    emit_off[r] = offs[j];
+    if (cnt->n_inst_ok == 0ull) return;
     const uint2 tr = tile_rect[r];
     const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu, y1 = tr.y >> 16;
     if (x1 <= x0 || y1 <= y0) return;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__
 // One wavefront per 16x16 tile; lane l shades pixels (l & 15, (l >> 4) + 4k),
 // k = 0..3.  The tile's sorted records are staged 64 at a time in LDS (one
 // load per lane) and read back as wave-uniform broadcasts.
-template <int WPB>
+template <int WPB, bool STATS>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
                                                          const float4* __restrict__ rec_col,
                                                          const float* __restrict__ rec_blue,
                                                          float* __restrict__ image, float* __restrict__ T_final,
-                                                         int32_t* __restrict__ n_last) {
+                                                         int32_t* __restrict__ n_last, int32_t* __restrict__ n_blend) {
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
@@ -165,11 +166,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     const float fpx = (float)px;
 
     float T[4], C0[4], C1[4], C2[4];
-    uint32_t last[4];
+    uint32_t last[4], nb[4];
     bool live[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        T[k] = 1.f; C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0;
+        T[k] = 1.f; C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
         live[k] = px < vd.W && (py0 + 4 * k) < vd.H;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -207,6 +208,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
                 C2[k] = fmaf(wgt, bl, C2[k]);
                 T[k] = Tn;
                 last[k] = pos;
+                if constexpr (STATS) ++nb[k];
             }
         }
         wave_sync();
@@ -221,6 +223,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
             image[3 * p + 2] = C2[k] + T[k] * vd.bg[2];
             T_final[p] = T[k];
             n_last[p] = (int32_t)last[k];
+            if constexpr (STATS) n_blend[p] = (int32_t)nb[k];
         }
     }
 }
@@ -248,10 +251,11 @@ hipError_t launch_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info, 
 }
 
 hipError_t launch_emit(const BatchDesc* d_desc, int64_t n_rec, const uint32_t* sorted_rec, const uint32_t* offs,
-                       const uint2* tr, const DevCounters* cnt, uint32_t* ik, uint32_t* iv, hipStream_t st) {
+                       const uint2* tr, const DevCounters* cnt, uint32_t* ik, uint32_t* iv, uint32_t* eo,
+                       hipStream_t st) {
     if (n_rec <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0, st, d_desc, sorted_rec, offs, tr,
-                       cnt, ik, iv);
+                       cnt, ik, iv, eo);
     return hipGetLastError();
 }
 
@@ -280,18 +284,16 @@ hipError_t launch_plain_keys(const uint32_t* stile, const uint32_t* sgid, const 
 
 hipError_t launch_blend_fwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
                             const uint32_t* inst_rec, const float4* rg, const float4* rc, const float* rb,
-                            float* image, float* T_final, int32_t* n_last, hipStream_t st) {
+                            float* image, float* T_final, int32_t* n_last, int32_t* n_blend, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    if (wpb == 1) {
-        hipLaunchKernelGGL(k_blend_fwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rg, rc,
-                           rb, image, T_final, n_last);
-    } else if (wpb == 2) {
-        hipLaunchKernelGGL(k_blend_fwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
-                           inst_rec, rg, rc, rb, image, T_final, n_last);
+#define CGS_BF(W, S) hipLaunchKernelGGL((k_blend_fwd<W, S>), dim3((unsigned)((n_tiles + W - 1) / W)), dim3(W * 64), \
+                                        0, st, d_desc, ranges, inst_rec, rg, rc, rb, image, T_final, n_last, n_blend)
+    if (n_blend) {
+        if (wpb == 1) CGS_BF(1, true); else if (wpb == 2) CGS_BF(2, true); else CGS_BF(4, true);
     } else {
-        hipLaunchKernelGGL(k_blend_fwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
-                           inst_rec, rg, rc, rb, image, T_final, n_last);
+        if (wpb == 1) CGS_BF(1, false); else if (wpb == 2) CGS_BF(2, false); else CGS_BF(4, false);
     }
+#undef CGS_BF
     return hipGetLastError();
 }
 
