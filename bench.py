@@ -75,7 +75,7 @@ class Form:
     """One way to run a step: `batched` renders every view in one call; `plain`
     issues one call per view."""
 
-    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08):
+    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08, waves_per_block=4, tile_order=0):
         self.wl = wl
         self.batched = batched
         ds = [render.DeviceScene.from_host(s, bf16=wl.bf16) for s in wl.scenes]
@@ -90,10 +90,12 @@ class Form:
             used = sorted(set(int(wl.view_scene[v]) for v in gidx))
             remap = {s: i for i, s in enumerate(used)}
             r = render.Renderer([ds[s] for s in used], [wl.cameras[v] for v in gidx],
-                                [remap[int(wl.view_scene[v])] for v in gidx])
+                                [remap[int(wl.view_scene[v])] for v in gidx], waves_per_block=waves_per_block,
+                                tile_order=tile_order)
             m = r.fit_capacity()
             r.set_capacity(int(m * capacity_slack) + 4096)
             r.fit_capacity()
+            self.instances = getattr(self, "instances", 0) + m
             tgt = np.concatenate([wl.targets[v].reshape(-1, 3) for v in gidx], 0)
             self.targets.append(torch.from_numpy(tgt).cuda())
             self.grads.append(torch.empty_like(self.targets[-1]))
@@ -206,6 +208,11 @@ def main():
     ap.add_argument("--extra-forms", default="fp32_plain,1m", help="comma list: fp32_plain, 1m, none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--tile-order", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a device-to-device copy of this many MiB (a kernel of known traffic "
+                         "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -215,9 +222,17 @@ def main():
     cgs.load()
     torch.cuda.set_device(0)
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.arange(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read + {args.copy_calibration_mib} MiB written")
+        del src, dst
     log(f"[bench] generating {args.workload}")
     wl = sc.make_workload(args.workload)
-    head = Form(wl, batched=True)
+    head = Form(wl, batched=True, waves_per_block=args.waves_per_block, tile_order=args.tile_order)
     ev = HipEvents(args.steps * cgs.STAGE_EVENTS)
     log(f"[bench] timing {args.workload} batched: {args.steps} steps after {args.warmup} warmup")
     ms = head.time(args.steps, args.warmup, ev)
@@ -227,6 +242,7 @@ def main():
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
     roof = blend_roofline(dom, stages[dom], e_eval, e_blend)
     forms = {f"{'bf16' if wl.bf16 else 'fp32'}_batched:{args.workload}": value}
+    n_inst = head.instances
     extras = [x for x in args.extra_forms.split(",") if x and x != "none"]
     del head
     torch.cuda.empty_cache()
@@ -264,7 +280,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "stages_ms": stages,
-        "pairs": {"evaluated": e_eval, "blended": e_blend},
+        "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst},
+        "schedule": {"waves_per_block": args.waves_per_block, "tile_order": args.tile_order},
     }
     print(json.dumps(out), flush=True)
 

@@ -31,7 +31,7 @@ hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const
                         const DevCounters*, float*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
-                         const uint32_t*, int64_t, int64_t, const uint32_t*, float*, hipStream_t);
+                         const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
 hipError_t launch_gather_keys(const int32_t*, const int32_t*, int64_t, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_copy_keys(const int32_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_l1(const float*, const float*, int64_t, float*, float*, float*, int, hipStream_t);
@@ -203,8 +203,6 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
     p.row_start = take(8 * (size_t)(h->rows_total + 1));
-    p.reduce_blocks = (G + kReduceBlock - 1) / kReduceBlock;
-    p.partials = take(4 * (size_t)kMaxRowWidth * 2 * (size_t)std::max<int64_t>(p.reduce_blocks, 1));
     p.total = o;
     return CGS_OK;
 }
@@ -376,7 +374,6 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
     uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
     uint32_t* rr = at<uint32_t>(ws, p.row_start);
-    float* part = at<float>(ws, p.partials);
     const int nparts = single ? 1 : 2;
     for (int part_i = 0; part_i < nparts; ++part_i) {
         const int64_t rows = part_i == 0 ? h.d.sr_rows_total : h.d.sh_rows_total;
@@ -389,8 +386,7 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
         int pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), counts, bsum, st, &e);
         CGS_TRY(e);
         CGS_TRY(tile_ranges(pk[pb], nullptr, h.d.n_gauss, rows, rr, st));
-        CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, part,
-                              st));
+        CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
     }
     CGS_TRY(mark(h, 7, st));
     return CGS_OK;
@@ -403,8 +399,6 @@ size_t cgs_codebook_grad_reduce_workspace_bytes(int64_t n, int64_t k, int32_t d)
     take(sizeof(BatchDesc));
     for (int i = 0; i < 4; ++i) take(4 * (size_t)n);
     take(8 * (size_t)(k + 1));
-    const int64_t rb = (n + kReduceBlock - 1) / kReduceBlock;
-    take(4 * (size_t)kMaxRowWidth * 2 * (size_t)std::max<int64_t>(rb, 1));
     const int64_t nb = (n + kSortTile - 1) / kSortTile;
     take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1));
     take(8 * scan_bsum_count(std::max<int64_t>(n, kRadixBins * nb)));
@@ -439,8 +433,6 @@ cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* i
     uint32_t* pv[2];
     for (int i = 0; i < 2; ++i) { pk[i] = at<uint32_t>(ws, take(4 * (size_t)n)); pv[i] = at<uint32_t>(ws, take(4 * (size_t)n)); }
     uint32_t* rr = at<uint32_t>(ws, take(8 * (size_t)(k + 1)));
-    const int64_t rb = (n + kReduceBlock - 1) / kReduceBlock;
-    float* part = at<float>(ws, take(4 * (size_t)kMaxRowWidth * 2 * (size_t)std::max<int64_t>(rb, 1)));
     const int64_t nb = (n + kSortTile - 1) / kSortTile;
     uint32_t* counts = at<uint32_t>(ws, take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1)));
     unsigned long long* bsum = at<unsigned long long>(ws, take(8 * scan_bsum_count(std::max<int64_t>(n, kRadixBins * nb))));
@@ -458,10 +450,7 @@ cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* i
         CGS_TRY(e);
     }
     CGS_TRY(tile_ranges(pk[pb], nullptr, n, k, rr, st));
-    for (int c0 = 0; c0 < d; c0 += kMaxRowWidth) {
-        const int D = std::min<int>(kMaxRowWidth, d - c0);
-        CGS_TRY(launch_reduce(dd, 0, g, ld, c0, D, c0, pk[pb], pv[pb], n, k, rr, part, st));
-    }
+    CGS_TRY(launch_reduce(dd, 0, g, ld, 0, d, 0, pk[pb], pv[pb], n, k, rr, st));
     return CGS_OK;
 }
 

@@ -16,7 +16,7 @@ constexpr int kSortBlock = 256;         // threads per radix/scan workgroup
 constexpr int kSortTile = kSortItems * kSortBlock;   // keys per workgroup (4096)
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kReduceBlock = 128;       // Gaussians per codebook-reduction workgroup
+constexpr int kReduceChunk = 64;        // sorted positions owned by one reduction wavefront
 constexpr int kMaxRowWidth = 8 + 48;    // ls3 q4 logit1 + degree-3 SH
 constexpr uint32_t kCulledKey = 0x7f800000u;   // +inf bits: sorts after every depth
 
@@ -76,9 +76,9 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range;
     size_t radix_counts, scan_bsum;
-    size_t emit_off, ginst, gtheta, psort_key[2], psort_val[2], row_start, partials;
+    size_t emit_off, ginst, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
-    int64_t radix_blocks_max, scan_blocks_max, reduce_blocks;
+    int64_t radix_blocks_max, scan_blocks_max;
 };
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }

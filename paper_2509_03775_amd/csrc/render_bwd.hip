@@ -34,6 +34,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
+    __shared__ uint32_t s_p[WPB][64];
     __shared__ float s_o[WPB][64][9];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
@@ -45,13 +46,16 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     const int px = tx * kTile + (lane & 15);
     const int py0 = ty * kTile + (lane >> 4);
     const float fpx = (float)px;
+    const float bx0 = (float)(tx * kTile), by0 = (float)(ty * kTile);
+    const float bx1 = (float)min(tx * kTile + kTile - 1, vd.W - 1), by1 = (float)min(ty * kTile + kTile - 1, vd.H - 1);
 
-    float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4];
+    float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpy[4];
     uint32_t last[4];
     uint32_t maxlast = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int py = py0 + 4 * k;
+        fpy[k] = (float)py;
         bh0[k] = vd.bg[0]; bh1[k] = vd.bg[1]; bh2[k] = vd.bg[2];
         if (px < vd.W && py < vd.H) {
             const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
@@ -78,29 +82,44 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
         const int64_t li = bbeg + lane;
         int64_t slot = -1;
+        bool keep = false;
+        float4 g, c;
+        float bl = 0.f;
         if (li < bend) {
             const uint32_t r = inst_rec[start + li];
-            s_g[w][lane] = rec_geom[r];
-            s_c[w][lane] = rec_col[r];
-            s_b[w][lane] = rec_blue[r];
+            g = rec_geom[r];
+            c = rec_col[r];
+            bl = rec_blue[r];
             slot = slot_of(r);
+            keep = may_touch(g, c, bx0, by0, bx1, by1);
+        }
+        const uint64_t km = __ballot(keep);
+        const uint32_t mine = popc_below(km);
+        if (keep) {
+            s_g[w][mine] = g;
+            s_c[w][mine] = c;
+            s_b[w][mine] = bl;
+            s_p[w][mine] = (uint32_t)li;
         }
         wave_sync();
-        for (int j = (int)(bend - bbeg) - 1; j >= 0; --j) {
-            const uint32_t pos = (uint32_t)(bbeg + j);     // 0-based list position
-            const float4 g = s_g[w][j];
-            const float4 c = s_c[w][j];
-            const float bl = s_b[w][j];
+        const int cnt = (int)__popcll(km);
+        for (int j = cnt - 1; j >= 0; --j) {
+            const uint32_t pos = s_p[w][j];     // 0-based list position
+            const float4 gg = s_g[w][j];
+            const float4 cc = s_c[w][j];
+            const float bb = s_b[w][j];
+            // natural-log conic entries for the derivatives of power
+            const float na = kLn2 * gg.z, nb = kLn2 * gg.w, nc = kLn2 * cc.x;
             float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (pos >= last[k]) continue;
-                const float dx = fpx - g.x;
-                const float dy = (float)(py0 + 4 * k) - g.y;
+                const float dx = fpx - gg.x;
+                const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
-                const float alpha = blend_alpha(dx, dy, g, c, G, pcl);
+                const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
                 if (alpha < kMinAlpha) continue;
                 any = true;
                 const float Tb = T[k] * __builtin_amdgcn_rcpf(1.f - alpha);
@@ -108,13 +127,13 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 a_r = fmaf(wgt, dC0[k], a_r);
                 a_g = fmaf(wgt, dC1[k], a_g);
                 a_bl = fmaf(wgt, dC2[k], a_bl);
-                const float e0 = c.z - bh0[k], e1 = c.w - bh1[k], e2 = bl - bh2[k];
+                const float e0 = cc.z - bh0[k], e1 = cc.w - bh1[k], e2 = bb - bh2[k];
                 const float dalpha = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
                 bh0[k] = fmaf(alpha, e0, bh0[k]);
                 bh1[k] = fmaf(alpha, e1, bh1[k]);
                 bh2[k] = fmaf(alpha, e2, bh2[k]);
                 T[k] = Tb;
-                if (c.y * G < kMaxAlpha) {
+                if (cc.y * G < kMaxAlpha) {
                     a_o = fmaf(dalpha, G, a_o);
                     if (!pcl) {
                         const float dp = dalpha * alpha;
@@ -123,8 +142,8 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                         a_b = fmaf(dpx, dy, a_b);
                         a_c = fmaf(dpy, dy, a_c);
                         // d power / d u = -(2 a' dx + b' dy), a' = -A/2, b' = -B
-                        a_u = fmaf(-dp, fmaf(2.f * g.z, dx, g.w * dy), a_u);
-                        a_v = fmaf(-dp, fmaf(2.f * c.x, dy, g.w * dx), a_v);
+                        a_u = fmaf(-dp, fmaf(2.f * na, dx, nb * dy), a_u);
+                        a_v = fmaf(-dp, fmaf(2.f * nc, dy, nb * dx), a_v);
                     }
                 }
             }
@@ -142,8 +161,13 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         wave_sync();
         if (slot >= 0) {
             float* dst = ginst + 9 * slot;
+            if (keep) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) dst[k] = s_o[w][lane][k];
+                for (int k = 0; k < 9; ++k) dst[k] = s_o[w][mine][k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) dst[k] = 0.f;
+            }
         }
         wave_sync();
     }
@@ -395,89 +419,70 @@ __device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, i
     return RowOut{sd.g_sh, sd.g_sh_stride, sd.g_sh_col0};
 }
 
-// A workgroup owns kReduceBlock consecutive positions of the row-sorted order.
-// It stages their gradient columns [c0, c0+D) in LDS, splits the positions into
-// runs of equal row, and sums each (run, column) in position order.  A run that
-// holds a whole row is written to the output; a run cut by the workgroup's
-// edge is written to partial slot 0 (first run) or 1 (last run) and finished
-// by k_reduce_fixup in workgroup order, so the result does not depend on
-// scheduling.
-__global__ __launch_bounds__(kReduceBlock) void k_reduce_rows(const BatchDesc* __restrict__ desc, int part,
-                                                              const float* __restrict__ gtheta, int64_t ld, int c0,
-                                                              int D, int oshift, const uint32_t* __restrict__ skey,
-                                                              const uint32_t* __restrict__ sval, int64_t n,
-                                                              int64_t n_rows,
-                                                              const uint32_t* __restrict__ row_range,
-                                                              float* __restrict__ partials) {
-    __shared__ float s_v[kReduceBlock * (kMaxRowWidth + 1)];
-    __shared__ uint32_t s_key[kReduceBlock];
-    __shared__ uint32_t s_gid[kReduceBlock];
-    __shared__ int s_seg_first[kReduceBlock + 1];
-    __shared__ int s_nseg;
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kReduceBlock;
-    const int cnt = (int)((n - base) < kReduceBlock ? (n - base) : kReduceBlock);
-    const int LD = D + 1;
-    if (t < cnt) {
-        s_key[t] = skey[base + t];
-        s_gid[t] = sval[base + t];
+// One wavefront per chunk of kReduceChunk consecutive positions of the
+// row-sorted order, lanes over columns.  The wave owns every row that starts
+// inside its chunk (running past the chunk's end to finish the last one) and
+// sums each row's Gaussians one position at a time, so every row is a plain
+// sequential sum in sorted (row, Gaussian index) order: deterministic and
+// independent of where the row sits in the batch.  A row read is one
+// contiguous load of D floats across the lanes.
+__global__ __launch_bounds__(256) void k_reduce_rows(const BatchDesc* __restrict__ desc, int part,
+                                                     const float* __restrict__ gtheta, int64_t ld, int c0, int D,
+                                                     int oshift, const uint32_t* __restrict__ skey,
+                                                     const uint32_t* __restrict__ sval, int64_t n, int64_t n_rows,
+                                                     const uint32_t* __restrict__ row_range) {
+    const int lane = threadIdx.x & 63;
+    const int64_t chunk = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t p0 = chunk * kReduceChunk;
+    if (p0 >= n) return;
+    const int64_t pend = p0 + kReduceChunk < n ? p0 + kReduceChunk : n;
+    // first row starting at or after p0
+    int64_t p;
+    {
+        const uint32_t r = skey[p0];
+        if ((int64_t)r >= n_rows) return;
+        p = (int64_t)row_range[2 * (int64_t)r] == p0 ? p0 : (int64_t)row_range[2 * (int64_t)r + 1];
     }
-    __syncthreads();
-    for (int e = t; e < cnt * D; e += kReduceBlock) {
-        const int row = e / D, col = e - row * D;
-        s_v[row * LD + col] = gtheta[(int64_t)s_gid[row] * ld + c0 + col];
-    }
-    if (t == 0) {
-        int ns = 0;
-        for (int i = 0; i < cnt; ++i)
-            if (i == 0 || s_key[i] != s_key[i - 1]) s_seg_first[ns++] = i;
-        s_seg_first[ns] = cnt;
-        s_nseg = ns;
-    }
-    __syncthreads();
-    const int nseg = s_nseg;
-    for (int job = t; job < nseg * D; job += kReduceBlock) {
-        const int sg = job / D, col = job - sg * D;
-        const int i0 = s_seg_first[sg], i1 = s_seg_first[sg + 1];
-        float acc = 0.f;
-        for (int i = i0; i < i1; ++i) acc += s_v[i * LD + col];
-        const uint32_t row = s_key[i0];
-        if ((int64_t)row >= n_rows) continue;     // index outside the codebook: dropped
-        const int64_t rs = row_range[2 * (int64_t)row], re = row_range[2 * (int64_t)row + 1];
-        if (rs >= base && re <= base + cnt) {
-            int64_t lr;
-            const RowOut o = row_out(desc, part, row, &lr);
-            o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
-        } else {
-            const int slot = sg == 0 ? 0 : 1;
-            partials[((int64_t)blockIdx.x * 2 + slot) * kMaxRowWidth + col] = acc;
+    while (p < pend) {
+        const uint32_t r = skey[p];
+        if ((int64_t)r >= n_rows) break;                    // index outside the codebook: dropped
+        const int64_t e = row_range[2 * (int64_t)r + 1];
+        int64_t lr;
+        const RowOut o = row_out(desc, part, r, &lr);
+        for (int cb = 0; cb < D; cb += 64) {
+            const int col = cb + lane;
+            const bool on = col < D;
+            float acc = 0.f;
+            int64_t q = p;
+            for (; q + 4 <= e; q += 4) {
+                const float a0 = on ? gtheta[(int64_t)sval[q] * ld + c0 + col] : 0.f;
+                const float a1 = on ? gtheta[(int64_t)sval[q + 1] * ld + c0 + col] : 0.f;
+                const float a2 = on ? gtheta[(int64_t)sval[q + 2] * ld + c0 + col] : 0.f;
+                const float a3 = on ? gtheta[(int64_t)sval[q + 3] * ld + c0 + col] : 0.f;
+                acc += a0;
+                acc += a1;
+                acc += a2;
+                acc += a3;
+            }
+            for (; q < e; ++q) acc += on ? gtheta[(int64_t)sval[q] * ld + c0 + col] : 0.f;
+            if (on) o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
         }
+        p = e;
     }
 }
 
-// One thread per (row, column): empty rows get 0; rows spanning several
-// workgroups are summed from the partials in workgroup order.
-__global__ __launch_bounds__(256) void k_reduce_fixup(const BatchDesc* __restrict__ desc, int part, int D,
-                                                      int oshift, int64_t n_rows, const uint32_t* __restrict__ row_range,
-                                                      const float* __restrict__ partials) {
+// Rows no Gaussian maps to get a zero gradient.
+__global__ __launch_bounds__(256) void k_reduce_empty(const BatchDesc* __restrict__ desc, int part, int D,
+                                                      int oshift, int64_t n_rows,
+                                                      const uint32_t* __restrict__ row_range) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_rows * D) return;
     const int64_t row = e / D;
     const int col = (int)(e - row * D);
-    const int64_t rs = row_range[2 * row], re = row_range[2 * row + 1];
-    float acc;
-    if (rs == re) {
-        acc = 0.f;
-    } else {
-        const int64_t b0 = rs / kReduceBlock, b1 = (re - 1) / kReduceBlock;
-        if (b0 == b1) return;
-        const int slot0 = (rs == b0 * kReduceBlock) ? 0 : 1;
-        acc = partials[(b0 * 2 + slot0) * kMaxRowWidth + col];
-        for (int64_t b = b0 + 1; b <= b1; ++b) acc += partials[(b * 2) * kMaxRowWidth + col];
-    }
+    if (row_range[2 * row] != row_range[2 * row + 1]) return;
     int64_t lr;
     const RowOut o = row_out(desc, part, row, &lr);
-    o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
+    o.ptr[lr * o.stride + o.col0 + oshift + col] = 0.f;
 }
 
 // Sorted keys from a caller-provided permutation: key[i] = idx[perm[i]].
@@ -574,13 +579,14 @@ hipError_t launch_row_keys(const BatchDesc* d_desc, int part, int64_t n_gauss, u
 
 hipError_t launch_reduce(const BatchDesc* d_desc, int part, const float* gtheta, int64_t ld, int c0, int D,
                          int oshift, const uint32_t* skey, const uint32_t* sval, int64_t n, int64_t n_rows,
-                         const uint32_t* row_range, float* partials, hipStream_t st) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((n + kReduceBlock - 1) / kReduceBlock)), dim3(kReduceBlock),
-                           0, st, d_desc, part, gtheta, ld, c0, D, oshift, skey, sval, n, n_rows, row_range, partials);
+                         const uint32_t* row_range, hipStream_t st) {
+    const int64_t chunks = (n + kReduceChunk - 1) / kReduceChunk;
+    if (chunks > 0)
+        hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)((chunks + 3) / 4)), dim3(256), 0, st, d_desc, part, gtheta,
+                           ld, c0, D, oshift, skey, sval, n, n_rows, row_range);
     if (n_rows * D > 0)
-        hipLaunchKernelGGL(k_reduce_fixup, dim3((unsigned)((n_rows * D + 255) / 256)), dim3(256), 0, st, d_desc, part,
-                           D, oshift, n_rows, row_range, partials);
+        hipLaunchKernelGGL(k_reduce_empty, dim3((unsigned)((n_rows * D + 255) / 256)), dim3(256), 0, st, d_desc, part,
+                           D, oshift, n_rows, row_range);
     return hipGetLastError();
 }
 

@@ -293,20 +293,43 @@ __device__ inline void sh_colour(const ViewDesc& vd, const GaussParams& gp, floa
 }
 
 // ------------------------------------------------------------- compositing
-// alpha of one (pixel, Gaussian) pair.  g = (u, v, -A/2, -B),
-// c = (-C/2, opacity, r, g): power = -(A dx^2 + 2 B dx dy + C dy^2)/2, clamped
-// to <= 0 (rounding residue of a positive-definite form), alpha = min(0.99,
-// o exp(power)).  Forward and backward call this same function so both take
-// identical decisions.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// alpha of one (pixel, Gaussian) pair.  Records hold the conic pre-scaled by
+// log2(e): g = (u, v, -A/2 log2e, -B log2e), c = (-C/2 log2e, opacity, r, g),
+// so power log2e = (g.z dx + g.w dy) dx + c.x dy^2 and exp(power) is one
+// hardware exp2.  power is clamped to <= 0 (rounding residue of a positive-
+// definite form); alpha = min(0.99, o exp(power)).  Forward and backward call
+// this same function so both take identical decisions.
 __device__ inline float blend_alpha(float dx, float dy, const float4& g, const float4& c, float& G, bool& pclamp) {
 #pragma clang fp contract(off)
     const float t = __builtin_fmaf(g.z, dx, g.w * dy);
     float pw = __builtin_fmaf(t, dx, (c.x * dy) * dy);
     pclamp = pw > 0.0f;
     pw = pclamp ? 0.0f : pw;
-    G = __expf(pw);
+    G = __builtin_amdgcn_exp2f(pw);
     const float og = c.y * G;
     return og < kMaxAlpha ? og : kMaxAlpha;
+}
+
+// Can the record reach alpha >= 1/255 anywhere in the pixel box [x0,x1] x
+// [y0,y1]?  Outside the axis-aligned box of the ellipse where exact alpha on
+// the stored record values equals (1/255)(1 - 1e-3), exact alpha is below
+// that level, so the FP32 alpha of blend_alpha (relative error ~1e-6) is
+// below 1/255 and the pair would be skipped anyway.  Dropping such records
+// before the per-pixel loop therefore changes no result.
+__device__ inline bool may_touch(const float4& g, const float4& c, float x0, float y0, float x1, float y1) {
+    const float lo = kMinAlpha * 0.999f;
+    const float o = c.y;
+    if (!(o > lo)) return false;
+    const float A = -2.f * kLn2 * g.z, B = -kLn2 * g.w, C = -2.f * kLn2 * c.x;
+    const float det = A * C - B * B;
+    if (!(det > 0.f)) return true;
+    const float rho = 2.f * __logf(o / lo);
+    const float hx = __builtin_sqrtf(rho * C / det) * 1.0001f + 1e-3f;
+    const float hy = __builtin_sqrtf(rho * A / det) * 1.0001f + 1e-3f;
+    return (g.x + hx >= x0) && (g.x - hx <= x1) && (g.y + hy >= y0) && (g.y - hy <= y1);
 }
 
 // Map a workgroup index to the tile group it shades.  Order 1 groups

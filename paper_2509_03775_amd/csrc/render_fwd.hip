@@ -48,8 +48,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         depth_key[r] = __float_as_uint(vp.zc);
         tile_rect[r] = make_uint2((uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16), (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16));
         ntiles[r] = (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0));
-        rec_geom[r] = make_float4(vp.u, vp.v, -0.5f * A, -B);
-        rec_col[r] = make_float4(-0.5f * C, opac, col[0], col[1]);
+        rec_geom[r] = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
+        rec_col[r] = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
         rec_blue[r] = col[2];
         (void)NCO;
     }
@@ -140,8 +140,10 @@ __global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__
 
 // ------------------------------------------------------------ forward blend
 // One wavefront per 16x16 tile; lane l shades pixels (l & 15, (l >> 4) + 4k),
-// k = 0..3.  The tile's sorted records are staged 64 at a time in LDS (one
-// load per lane) and read back as wave-uniform broadcasts.
+// k = 0..3.  The tile's sorted records are read 64 at a time (one per lane);
+// records that cannot reach alpha >= 1/255 inside the tile are dropped and the
+// rest are packed in order into LDS (ballot prefix), then read back as
+// wave-uniform broadcasts.  List positions are kept, so n_last is unchanged.
 template <int WPB, bool STATS>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
+    __shared__ uint32_t s_p[WPB][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
     if (tile >= desc->n_tiles) return;
@@ -164,48 +167,63 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     const int px = tx * kTile + (lane & 15);
     const int py0 = ty * kTile + (lane >> 4);
     const float fpx = (float)px;
+    const float bx0 = (float)(tx * kTile), by0 = (float)(ty * kTile);
+    const float bx1 = (float)min(tx * kTile + kTile - 1, vd.W - 1), by1 = (float)min(ty * kTile + kTile - 1, vd.H - 1);
 
-    float T[4], C0[4], C1[4], C2[4];
+    float T[4], C0[4], C1[4], C2[4], fpy[4];
     uint32_t last[4], nb[4];
     bool live[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         T[k] = 1.f; C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
+        fpy[k] = (float)(py0 + 4 * k);
         live[k] = px < vd.W && (py0 + 4 * k) < vd.H;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     for (uint32_t b = start; b < end; b += 64) {
         if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
         const uint32_t idx = b + lane;
+        bool keep = false;
+        float4 g, c;
+        float bl = 0.f;
         if (idx < end) {
             const uint32_t r = inst_rec[idx];
-            s_g[w][lane] = rec_geom[r];
-            s_c[w][lane] = rec_col[r];
-            s_b[w][lane] = rec_blue[r];
+            g = rec_geom[r];
+            c = rec_col[r];
+            bl = rec_blue[r];
+            keep = may_touch(g, c, bx0, by0, bx1, by1);
+        }
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+            const uint32_t slot = popc_below(km);
+            s_g[w][slot] = g;
+            s_c[w][slot] = c;
+            s_b[w][slot] = bl;
+            s_p[w][slot] = idx - start + 1u;
         }
         wave_sync();
-        const int cnt = (int)min(64u, end - b);
+        const int cnt = (int)__popcll(km);
         for (int j = 0; j < cnt; ++j) {
             if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
-            const float4 g = s_g[w][j];
-            const float4 c = s_c[w][j];
-            const float bl = s_b[w][j];
-            const uint32_t pos = (b - start) + (uint32_t)j + 1u;
+            const float4 gg = s_g[w][j];
+            const float4 cc = s_c[w][j];
+            const float bb = s_b[w][j];
+            const uint32_t pos = s_p[w][j];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!live[k]) continue;
-                const float dx = fpx - g.x;
-                const float dy = (float)(py0 + 4 * k) - g.y;
+                const float dx = fpx - gg.x;
+                const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
-                const float alpha = blend_alpha(dx, dy, g, c, G, pcl);
+                const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
                 if (alpha < kMinAlpha) continue;
                 const float Tn = T[k] * (1.f - alpha);
                 if (Tn < kMinT) { live[k] = false; continue; }
                 const float wgt = alpha * T[k];
-                C0[k] = fmaf(wgt, c.z, C0[k]);
-                C1[k] = fmaf(wgt, c.w, C1[k]);
-                C2[k] = fmaf(wgt, bl, C2[k]);
+                C0[k] = fmaf(wgt, cc.z, C0[k]);
+                C1[k] = fmaf(wgt, cc.w, C1[k]);
+                C2[k] = fmaf(wgt, bb, C2[k]);
                 T[k] = Tn;
                 last[k] = pos;
                 if constexpr (STATS) ++nb[k];

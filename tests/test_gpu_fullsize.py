@@ -131,7 +131,8 @@ def test_sampled_image_and_gradients(name):
 
 def test_batched_equals_per_view_calls():
     """The uneven 16-scene batch in one call gives bitwise the per-scene
-    results of 16 separate calls (same kernels, fixed-order sums)."""
+    results of separate calls (same kernels; every sum has a fixed order that
+    does not depend on where a scene sits in the batch)."""
     name = "uneven16_512px"
     say(f"[batched vs plain] {name}")
     wl, r = workload_and_renderer(name)
@@ -249,20 +250,22 @@ def test_autograd_and_finite_differences_1m():
     used = np.unique(s.idx[fz["order"][np.unique(fz["fz_rec"])]])
     rng = np.random.default_rng(11)
     entries = rng.choice(used, size=min(64, used.size), replace=False)
-    rows0 = oracle.decode_rows(s).astype(np.float64)
+    rows = oracle.decode_rows(s).astype(np.float64)     # per-Gaussian rows, perturbed in place
     h = 1e-3
     worst = 0.0
     for k in entries:
         d = rng.standard_normal(s.r)
         d /= np.linalg.norm(d)
+        sel = np.nonzero(s.idx == k)[0]
+        base_row = rows[sel[0]].copy()
 
         def L(sign):
-            cb = s.cb.astype(np.float64).copy()
-            cb[k] += sign * h * d
-            o = oracle.render_view(s, cam, pix, frozen=fz, rows32=cb[s.idx])
+            rows[sel] = base_row + sign * h * d
+            o = oracle.render_view(s, cam, pix, frozen=fz, rows32=rows)
             return float((o["color"] * gcol).sum())
 
         fd = (L(1) - L(-1)) / (2 * h)
+        rows[sel] = base_row
         an = float(ag_cb[k] @ d)
         ora = float(ogcb[k] @ d)
         scale = max(abs(fd), 1e-3 * np.linalg.norm(ogcb[k]) + 1e-12)
@@ -270,5 +273,4 @@ def test_autograd_and_finite_differences_1m():
         worst = max(worst, err)
         assert abs(ora - fd) <= 1e-4 * scale + 1e-12, (k, ora, fd)
         assert err <= 2e-3, (k, an, fd)
-    say(f"  64-entry FD: worst relative difference GPU vs FD {worst:.2e}")
-    del rows0
+    say(f"  {len(entries)}-entry FD: worst relative difference GPU vs FD {worst:.2e}")
