@@ -75,7 +75,7 @@ class Form:
     """One way to run a step: `batched` renders every view in one call; `plain`
     issues one call per view."""
 
-    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08, waves_per_block=4, tile_order=0):
+    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08, waves_per_block=1, tile_order=0):
         self.wl = wl
         self.batched = batched
         ds = [render.DeviceScene.from_host(s, bf16=wl.bf16) for s in wl.scenes]
@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--extra-forms", default="fp32_plain,1m", help="comma list: fp32_plain, 1m, none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--waves-per-block", type=int, default=1)
     ap.add_argument("--tile-order", type=int, default=0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (a kernel of known traffic "

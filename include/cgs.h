@@ -120,7 +120,7 @@ typedef struct {
  *   number of Gaussians blended into each pixel (a slower instrumented blend). */
 enum { CGS_STAGE_EVENTS = 8 };
 typedef struct {
-    int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup: 1, 2 or 4 (default) */
+    int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup: 1 (default), 2 or 4 */
     int32_t tile_order;              /* 0: row-major tiles, 1: XCD-grouped order */
     int32_t reserved[2];
     void** stage_events;

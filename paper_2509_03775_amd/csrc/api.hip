@@ -167,8 +167,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         d.scenes[s].vcount = nv - d.scenes[s].vfirst;
     }
     const cgs_schedule* sch = b->schedule;
-    h->wpb = (sch && (sch->blend_waves_per_block == 1 || sch->blend_waves_per_block == 2)) ? sch->blend_waves_per_block
-                                                                                            : 4;
+    h->wpb = (sch && (sch->blend_waves_per_block == 2 || sch->blend_waves_per_block == 4)) ? sch->blend_waves_per_block
+                                                                                            : 1;
     d.tile_order = sch ? sch->tile_order : 0;
     h->events = sch ? reinterpret_cast<hipEvent_t*>(sch->stage_events) : nullptr;
     h->n_blend = sch ? sch->n_blend : nullptr;

@@ -117,6 +117,20 @@ __device__ inline float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sum over each 16-lane row (every lane must be active); lane 15 of each row
+// (lanes 15, 31, 47, 63) receives its row's total.
+__device__ inline float row16_sum(float v) {
+    int x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    return v;
+}
+
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
     for (int d = 32; d >= 1; d >>= 1) {
         uint32_t o = (uint32_t)__shfl_xor((int)v, d, 64);

@@ -8,16 +8,18 @@
 namespace cgs {
 
 // ------------------------------------------------------------ backward blend
-// One wavefront per tile, same pixel mapping as the forward.  Each pixel walks
-// its list from n_last-1 down to 0, re-derives alpha with the forward's code,
-// recovers T before the Gaussian as T_after / (1 - alpha), and accumulates
-// dL/d(u, v, -A/2, -B, -C/2, opacity, r, g, b).  The four pixels of a lane are
-// summed in registers and the 64 lanes by a DPP reduction.  The tile's total
-// for a record goes to that (tile, record) instance's own slot -- slot =
-// the record's emission offset + the tile's row-major index in the record's
-// rectangle -- with plain stores: no atomics, and the per-record sum over its
-// tiles is taken later in a fixed order, so the backward is deterministic.
-// Instances the walk never reaches (beyond every pixel's n_last) get zeros.
+// One wavefront per tile, same pixel mapping and quadrant skipping as the
+// forward.  Each pixel walks its list from n_last-1 down to 0, re-derives
+// alpha with the forward's code, recovers T before the Gaussian as
+// T_after / (1 - alpha), and accumulates dL/d(u, v, -A/2, -B, -C/2, opacity,
+// r, g, b).  The lane's four pixels are summed in registers, each 16-lane row
+// by DPP shifts, and the four row partials of every record are added once per
+// batch by the lane that loaded the record.  The tile's total for a record
+// goes to that (tile, record) instance's own slot -- the record's emission
+// offset + the tile's row-major index in the record's rectangle -- with plain
+// stores: no atomics, and the per-record sum over its tiles is taken later in
+// a fixed order, so the backward is deterministic.  Instances the walk never
+// reaches (beyond every pixel's n_last) get zeros.
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
     __shared__ uint32_t s_p[WPB][64];
-    __shared__ float s_o[WPB][64][9];
+    __shared__ float s_o[WPB][64][4][9];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
     if (tile >= desc->n_tiles) return;
@@ -43,18 +45,17 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     const ViewDesc& vd = desc->views[v];
     const int64_t lt = tile - vd.tile_off;
     const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
-    const int px = tx * kTile + (lane & 15);
-    const int py0 = ty * kTile + (lane >> 4);
-    const float fpx = (float)px;
-    const float bx0 = (float)(tx * kTile), by0 = (float)(ty * kTile);
-    const float bx1 = (float)min(tx * kTile + kTile - 1, vd.W - 1), by1 = (float)min(ty * kTile + kTile - 1, vd.H - 1);
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const float bx0 = (float)x0, by0 = (float)y0;
+    const float bxm = (float)min(x0 + kTile - 1, vd.W - 1), bym = (float)min(y0 + kTile - 1, vd.H - 1);
 
-    float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpy[4];
+    float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpx[4], fpy[4];
     uint32_t last[4];
     uint32_t maxlast = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int py = py0 + 4 * k;
+        const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
+        fpx[k] = (float)px;
         fpy[k] = (float)py;
         bh0[k] = vd.bg[0]; bh1[k] = vd.bg[1]; bh2[k] = vd.bg[2];
         if (px < vd.W && py < vd.H) {
@@ -75,14 +76,16 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     if (maxlast > len) maxlast = len;     // n_last inconsistent with this binning: stay in the list
     auto slot_of = [&](uint32_t r) -> int64_t {
         const uint2 tr = tile_rect[r];
-        const int x0 = (int)(tr.x & 0xffffu), y0 = (int)(tr.x >> 16), x1 = (int)(tr.y & 0xffffu);
-        return (int64_t)emit_off[r] + (int64_t)(ty - y0) * (x1 - x0) + (tx - x0);
+        const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rx1 = (int)(tr.y & 0xffffu);
+        return (int64_t)emit_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
     };
+    const int row = lane >> 4;
+    const bool row_end = (lane & 15) == 15;
     for (int64_t bend = maxlast; bend > 0; bend -= 64) {
         const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
         const int64_t li = bbeg + lane;
         int64_t slot = -1;
-        bool keep = false;
+        uint32_t qm = 0u;
         float4 g, c;
         float bl = 0.f;
         if (li < bend) {
@@ -91,31 +94,33 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             c = rec_col[r];
             bl = rec_blue[r];
             slot = slot_of(r);
-            keep = may_touch(g, c, bx0, by0, bx1, by1);
+            qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
         }
-        const uint64_t km = __ballot(keep);
+        const uint64_t km = __ballot(qm != 0u);
         const uint32_t mine = popc_below(km);
-        if (keep) {
+        if (qm != 0u) {
             s_g[w][mine] = g;
             s_c[w][mine] = c;
             s_b[w][mine] = bl;
-            s_p[w][mine] = (uint32_t)li;
+            s_p[w][mine] = ((uint32_t)li << 4) | qm;
         }
         wave_sync();
         const int cnt = (int)__popcll(km);
         for (int j = cnt - 1; j >= 0; --j) {
-            const uint32_t pos = s_p[w][j];     // 0-based list position
+            const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
+            const uint32_t pos = pq >> 4;     // 0-based list position
             const float4 gg = s_g[w][j];
             const float4 cc = s_c[w][j];
             const float bb = s_b[w][j];
             // natural-log conic entries for the derivatives of power
-            const float na = kLn2 * gg.z, nb = kLn2 * gg.w, nc = kLn2 * cc.x;
+            const float na2 = 2.f * kLn2 * gg.z, nb = kLn2 * gg.w, nc2 = 2.f * kLn2 * cc.x;
             float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
             bool any = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                if (!((pq >> k) & 1u)) continue;          // wave-uniform
                 if (pos >= last[k]) continue;
-                const float dx = fpx - gg.x;
+                const float dx = fpx[k] - gg.x;
                 const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 bh1[k] = fmaf(alpha, e1, bh1[k]);
                 bh2[k] = fmaf(alpha, e2, bh2[k]);
                 T[k] = Tb;
-                if (cc.y * G < kMaxAlpha) {
+                if (alpha < kMaxAlpha) {
                     a_o = fmaf(dalpha, G, a_o);
                     if (!pcl) {
                         const float dp = dalpha * alpha;
@@ -142,28 +147,32 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                         a_b = fmaf(dpx, dy, a_b);
                         a_c = fmaf(dpy, dy, a_c);
                         // d power / d u = -(2 a' dx + b' dy), a' = -A/2, b' = -B
-                        a_u = fmaf(-dp, fmaf(2.f * na, dx, nb * dy), a_u);
-                        a_v = fmaf(-dp, fmaf(2.f * nc, dy, nb * dx), a_v);
+                        a_u = fmaf(-dp, fmaf(na2, dx, nb * dy), a_u);
+                        a_v = fmaf(-dp, fmaf(nc2, dy, nb * dx), a_v);
                     }
                 }
             }
-            float sums[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float* so = &s_o[w][j][row][0];
             if (__ballot(any) != 0ull) {
-                sums[0] = wave_sum(a_u); sums[1] = wave_sum(a_v); sums[2] = wave_sum(a_a);
-                sums[3] = wave_sum(a_b); sums[4] = wave_sum(a_c); sums[5] = wave_sum(a_o);
-                sums[6] = wave_sum(a_r); sums[7] = wave_sum(a_g); sums[8] = wave_sum(a_bl);
-            }
-            if (lane == 0) {
+                const float s0 = row16_sum(a_u), s1 = row16_sum(a_v), s2 = row16_sum(a_a);
+                const float s3 = row16_sum(a_b), s4 = row16_sum(a_c), s5 = row16_sum(a_o);
+                const float s6 = row16_sum(a_r), s7 = row16_sum(a_g), s8 = row16_sum(a_bl);
+                if (row_end) {
+                    so[0] = s0; so[1] = s1; so[2] = s2; so[3] = s3; so[4] = s4;
+                    so[5] = s5; so[6] = s6; so[7] = s7; so[8] = s8;
+                }
+            } else if (row_end) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) s_o[w][j][k] = sums[k];
+                for (int k = 0; k < 9; ++k) so[k] = 0.f;
             }
         }
         wave_sync();
         if (slot >= 0) {
             float* dst = ginst + 9 * slot;
-            if (keep) {
+            if (qm != 0u) {
 #pragma unroll
-                for (int k = 0; k < 9; ++k) dst[k] = s_o[w][mine][k];
+                for (int k = 0; k < 9; ++k)
+                    dst[k] = ((s_o[w][mine][0][k] + s_o[w][mine][1][k]) + s_o[w][mine][2][k]) + s_o[w][mine][3][k];
             } else {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) dst[k] = 0.f;

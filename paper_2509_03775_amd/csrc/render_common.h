@@ -313,23 +313,33 @@ __device__ inline float blend_alpha(float dx, float dy, const float4& g, const f
     return og < kMaxAlpha ? og : kMaxAlpha;
 }
 
-// Can the record reach alpha >= 1/255 anywhere in the pixel box [x0,x1] x
-// [y0,y1]?  Outside the axis-aligned box of the ellipse where exact alpha on
-// the stored record values equals (1/255)(1 - 1e-3), exact alpha is below
-// that level, so the FP32 alpha of blend_alpha (relative error ~1e-6) is
-// below 1/255 and the pair would be skipped anyway.  Dropping such records
-// before the per-pixel loop therefore changes no result.
-__device__ inline bool may_touch(const float4& g, const float4& c, float x0, float y0, float x1, float y1) {
+// Which 8x8 quadrants of a 16x16 tile (pixel origin x0, y0; last valid pixel
+// xm, ym) can the record reach with alpha >= 1/255?  Bit k = quadrant
+// (k & 1, k >> 1).  Outside the axis-aligned box of the ellipse on which exact
+// alpha (on the stored record values) equals (1/255)(1 - 1e-3), exact alpha is
+// below that level, so the FP32 alpha of blend_alpha (relative error ~1e-6)
+// is below 1/255 and every such pair would be skipped anyway: skipping whole
+// quadrants outside the box changes no result.
+__device__ inline uint32_t quadrant_mask(const float4& g, const float4& c, float x0, float y0, float xm, float ym) {
     const float lo = kMinAlpha * 0.999f;
     const float o = c.y;
-    if (!(o > lo)) return false;
+    if (!(o > lo)) return 0u;
     const float A = -2.f * kLn2 * g.z, B = -kLn2 * g.w, C = -2.f * kLn2 * c.x;
     const float det = A * C - B * B;
-    if (!(det > 0.f)) return true;
-    const float rho = 2.f * __logf(o / lo);
-    const float hx = __builtin_sqrtf(rho * C / det) * 1.0001f + 1e-3f;
-    const float hy = __builtin_sqrtf(rho * A / det) * 1.0001f + 1e-3f;
-    return (g.x + hx >= x0) && (g.x - hx <= x1) && (g.y + hy >= y0) && (g.y - hy <= y1);
+    float hx = 3.0e38f, hy = 3.0e38f;
+    if (det > 0.f) {
+        const float rho = 2.f * __logf(o / lo);
+        hx = __builtin_sqrtf(rho * C / det) * 1.0001f + 1e-3f;
+        hy = __builtin_sqrtf(rho * A / det) * 1.0001f + 1e-3f;
+    }
+    const float gx0 = g.x - hx, gx1 = g.x + hx, gy0 = g.y - hy, gy1 = g.y + hy;
+    const float xmid = x0 + 8.f, ymid = y0 + 8.f;
+    const bool cl = gx0 <= fminf(xmid - 1.f, xm) && gx1 >= x0;       // columns x0 .. x0+7
+    const bool cr = gx0 <= xm && gx1 >= xmid && xmid <= xm;          // columns x0+8 .. x0+15
+    const bool rt = gy0 <= fminf(ymid - 1.f, ym) && gy1 >= y0;
+    const bool rb = gy0 <= ym && gy1 >= ymid && ymid <= ym;
+    return (uint32_t)(cl && rt) | ((uint32_t)(cr && rt) << 1) | ((uint32_t)(cl && rb) << 2) |
+           ((uint32_t)(cr && rb) << 3);
 }
 
 // Map a workgroup index to the tile group it shades.  Order 1 groups

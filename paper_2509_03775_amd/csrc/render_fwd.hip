@@ -139,11 +139,13 @@ __global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__
 }
 
 // ------------------------------------------------------------ forward blend
-// One wavefront per 16x16 tile; lane l shades pixels (l & 15, (l >> 4) + 4k),
-// k = 0..3.  The tile's sorted records are read 64 at a time (one per lane);
-// records that cannot reach alpha >= 1/255 inside the tile are dropped and the
-// rest are packed in order into LDS (ballot prefix), then read back as
-// wave-uniform broadcasts.  List positions are kept, so n_last is unchanged.
+// One wavefront per 16x16 tile.  Lane l shades pixel (l & 7, l >> 3) of each
+// of the four 8x8 quadrants k (k & 1 right, k >> 1 lower).  The tile's sorted
+// records are read 64 at a time (one per lane); each lane marks the quadrants
+// its record can reach with alpha >= 1/255, records reaching none are
+// dropped, the rest are packed in order into LDS (ballot prefix) and read
+// back as wave-uniform broadcasts; a quadrant the record cannot reach is
+// skipped by the whole wave.  List positions are kept, so n_last is unchanged.
 template <int WPB, bool STATS>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
@@ -164,26 +166,26 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     const ViewDesc& vd = desc->views[v];
     const int64_t lt = tile - vd.tile_off;
     const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
-    const int px = tx * kTile + (lane & 15);
-    const int py0 = ty * kTile + (lane >> 4);
-    const float fpx = (float)px;
-    const float bx0 = (float)(tx * kTile), by0 = (float)(ty * kTile);
-    const float bx1 = (float)min(tx * kTile + kTile - 1, vd.W - 1), by1 = (float)min(ty * kTile + kTile - 1, vd.H - 1);
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const float bx0 = (float)x0, by0 = (float)y0;
+    const float bxm = (float)min(x0 + kTile - 1, vd.W - 1), bym = (float)min(y0 + kTile - 1, vd.H - 1);
 
-    float T[4], C0[4], C1[4], C2[4], fpy[4];
+    float T[4], C0[4], C1[4], C2[4], fpx[4], fpy[4];
     uint32_t last[4], nb[4];
     bool live[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+        const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
         T[k] = 1.f; C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
-        fpy[k] = (float)(py0 + 4 * k);
-        live[k] = px < vd.W && (py0 + 4 * k) < vd.H;
+        fpx[k] = (float)px;
+        fpy[k] = (float)py;
+        live[k] = px < vd.W && py < vd.H;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     for (uint32_t b = start; b < end; b += 64) {
         if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
         const uint32_t idx = b + lane;
-        bool keep = false;
+        uint32_t qm = 0u;
         float4 g, c;
         float bl = 0.f;
         if (idx < end) {
@@ -191,15 +193,15 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
             g = rec_geom[r];
             c = rec_col[r];
             bl = rec_blue[r];
-            keep = may_touch(g, c, bx0, by0, bx1, by1);
+            qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
         }
-        const uint64_t km = __ballot(keep);
-        if (keep) {
+        const uint64_t km = __ballot(qm != 0u);
+        if (qm != 0u) {
             const uint32_t slot = popc_below(km);
             s_g[w][slot] = g;
             s_c[w][slot] = c;
             s_b[w][slot] = bl;
-            s_p[w][slot] = idx - start + 1u;
+            s_p[w][slot] = ((idx - start + 1u) << 4) | qm;
         }
         wave_sync();
         const int cnt = (int)__popcll(km);
@@ -208,11 +210,13 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
             const float4 gg = s_g[w][j];
             const float4 cc = s_c[w][j];
             const float bb = s_b[w][j];
-            const uint32_t pos = s_p[w][j];
+            const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
+            const uint32_t pos = pq >> 4;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                if (!((pq >> k) & 1u)) continue;          // wave-uniform
                 if (!live[k]) continue;
-                const float dx = fpx - gg.x;
+                const float dx = fpx[k] - gg.x;
                 const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int py = py0 + 4 * k;
+        const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
         if (px < vd.W && py < vd.H) {
             const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
             image[3 * p + 0] = C0[k] + T[k] * vd.bg[0];

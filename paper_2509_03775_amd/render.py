@@ -89,7 +89,7 @@ class Renderer:
 
     def __init__(self, scenes: Sequence[DeviceScene], cameras: Sequence[sc.Camera],
                  view_scene: Sequence[int], capacity: Optional[int] = None,
-                 waves_per_block: int = 4, tile_order: int = 0, device="cuda"):
+                 waves_per_block: int = 1, tile_order: int = 0, device="cuda"):
         self.scenes = list(scenes)
         self.cameras = list(cameras)
         self.device = torch.device(device)
