@@ -191,18 +191,28 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t* keys,
     counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
 }
 
+// Scatter pass.  Ranks are computed per wave in item order as in the
+// histogram pass; the workgroup then places its items in LDS in block-local
+// digit order and writes them out linearly, so each digit's run of items goes
+// to consecutive global addresses (coalesced) instead of 64 scattered writes
+// per instruction.
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint32_t* keys_in, const uint32_t* vals_in,
                                                               uint32_t* keys_out, uint32_t* vals_out,
                                                               int64_t n_max, const unsigned long long* n_dev,
                                                               int shift, int nbits, const uint32_t* offsets,
                                                               int64_t nblocks) {
     __shared__ uint32_t cnt[4][kRadixBins];
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_goff[kRadixBins];
+    __shared__ uint32_t s_wave[kSortBlock / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = 0; i < 4; ++i) cnt[i][threadIdx.x] = 0;
     __syncthreads();
     const int64_t n = live_count(n_max, n_dev);
-    if ((int64_t)blockIdx.x * kSortTile >= n) return;     // whole workgroup: nothing here
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / 4);
+    const int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
+    if (blk0 >= n) return;     // whole workgroup: nothing here
+    const int64_t base = blk0 + (int64_t)w * (kSortTile / 4);
     const uint32_t mask = (1u << nbits) - 1u;
     uint32_t k_[kSortItems], v_[kSortItems];
     uint32_t rank[kSortItems];
@@ -225,25 +235,34 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint32_t* ke
         wave_sync();
     }
     __syncthreads();
-    // Per-digit base of each wave: global (digit, block) offset plus earlier waves.
+    // per digit: block-local start (prefix over digits), each wave's local
+    // base, and the shift from local to global positions
     {
         const uint32_t d = threadIdx.x;
-        uint32_t b = offsets[(int64_t)d * nblocks + blockIdx.x];
-        for (int i = 0; i < 4; ++i) {
-            uint32_t c = cnt[i][d];
-            cnt[i][d] = b;
-            b += c;
-        }
+        uint32_t tot = 0, wb[4];
+        for (int i = 0; i < 4; ++i) { wb[i] = tot; tot += cnt[i][d]; }
+        uint32_t all;
+        const uint32_t dstart = block_excl_scan(tot, s_wave, &all);
+        for (int i = 0; i < 4; ++i) cnt[i][d] = dstart + wb[i];
+        s_goff[d] = offsets[(int64_t)d * nblocks + blockIdx.x] - dstart;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         if (rank[i] != 0xffffffffu) {
-            uint32_t d = (k_[i] >> shift) & mask;
-            uint32_t pos = cnt[w][d] + rank[i];
-            keys_out[pos] = k_[i];
-            vals_out[pos] = v_[i];
+            const uint32_t d = (k_[i] >> shift) & mask;
+            const uint32_t lp = cnt[w][d] + rank[i];
+            s_key[lp] = k_[i];
+            s_val[lp] = v_[i];
         }
+    }
+    __syncthreads();
+    const int m = (int)(n - blk0 < kSortTile ? n - blk0 : kSortTile);
+    for (int i = threadIdx.x; i < m; i += kSortBlock) {
+        const uint32_t key = s_key[i];
+        const uint32_t pos = s_goff[(key >> shift) & mask] + (uint32_t)i;
+        keys_out[pos] = key;
+        vals_out[pos] = s_val[i];
     }
 }
 
