@@ -15,8 +15,9 @@ namespace cgs {
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, float4*, float*, uint32_t*, uint2*,
                              uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
-hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const DevCounters*,
-                       uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+hipError_t launch_gather_depth(int64_t, const uint32_t*, const uint2*, const uint32_t*, uint2*, uint32_t*, hipStream_t);
+hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
+                       const DevCounters*, uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, const uint32_t*, int64_t, int32_t,
                              int32_t, const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
@@ -127,6 +128,18 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         shoff += sc.sh.rows;
     }
     d.n_gauss = goff;
+    {   // 16-byte vector loads of whole rows: degree-3 rows, opacity in the SR row, aligned windows
+        const size_t esz = d.dtype == CGS_BF16 ? 2 : 4;
+        bool vec = s0.sh_degree == 3 && h->opacity_mode == 1;
+        for (int s = 0; s < b->n_scenes && vec; ++s) {
+            const cgs_scene& sc = b->scenes[s];
+            const uintptr_t a0 = reinterpret_cast<uintptr_t>(sc.sr.ptr) + esz * (size_t)sc.sr.col0;
+            const uintptr_t a1 = reinterpret_cast<uintptr_t>(sc.sh.ptr) + esz * (size_t)sc.sh.col0;
+            vec = (a0 % 16 == 0) && (a1 % 16 == 0) && ((esz * (size_t)sc.sr.row_stride) % 16 == 0) &&
+                  ((esz * (size_t)sc.sh.row_stride) % 16 == 0);
+        }
+        d.vec_rows = vec ? 1 : 0;
+    }
     d.sr_rows_total = sroff;
     d.sh_rows_total = shoff;
     if (goff >= ((int64_t)1 << 32) || sroff >= ((int64_t)1 << 32) || shoff >= ((int64_t)1 << 32)) return CGS_EINVAL;
@@ -191,6 +204,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.ntiles = take(4 * (size_t)R);
     for (int i = 0; i < 2; ++i) { p.dsort_key[i] = take(4 * (size_t)R); p.dsort_val[i] = take(4 * (size_t)R); }
     p.offs = take(4 * (size_t)R);
+    p.rect_d = take(8 * (size_t)R);
+    p.cnt_d = take(4 * (size_t)R);
     for (int i = 0; i < 2; ++i) { p.inst_key[i] = take(4 * (size_t)cap); p.inst_val[i] = take(4 * (size_t)cap); }
     p.tile_range = take(8 * (size_t)T);
     const int64_t nmax = std::max(std::max(R, cap), G);
@@ -302,12 +317,14 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
                               st, &e);
     CGS_TRY(e);
     // instance offsets in depth order, capacity check, emission
-    CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), dv[db], h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));
+    CGS_TRY(launch_gather_depth(h.d.n_rec, dv[db], at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles),
+                                at<uint2>(ws, p.rect_d), at<uint32_t>(ws, p.cnt_d), st));
+    CGS_TRY(scan_u32(at<uint32_t>(ws, p.cnt_d), nullptr, h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));
     CGS_TRY(launch_capacity(cnt, h.d.capacity, d_info, st));
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
     uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
-    CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.tile_rect), cnt, ik[1], iv[1],
-                        at<uint32_t>(ws, p.emit_off), st));
+    CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.rect_d),
+                        at<uint32_t>(ws, p.cnt_d), cnt, ik[1], iv[1], at<uint32_t>(ws, p.emit_off), st));
     int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, counts, bsum, st, &e);
     CGS_TRY(e);
     if (ib != h.inst_buf) return CGS_EHIP;

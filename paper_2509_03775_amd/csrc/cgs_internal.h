@@ -53,6 +53,8 @@ struct BatchDesc {
     int32_t n_views, n_scenes, sh_degree, dtype;
     int32_t row_width;      // 8 + 3 (d+1)^2: per-Gaussian gradient row
     int32_t tile_order;
+    int32_t vec_rows;       // every codebook row is 16-byte aligned: vector loads allowed
+    int32_t pad_;
     int64_t n_rec, n_gauss, n_tiles, n_pix, capacity;
     int64_t sr_rows_total, sh_rows_total;
     int32_t view_list[CGS_MAX_VIEWS];   // views grouped by scene
@@ -72,7 +74,7 @@ struct WsPlan {
     size_t desc, counters;
     size_t rec_geom, rec_col, rec_blue, depth_key, tile_rect, ntiles;
     size_t dsort_key[2], dsort_val[2];
-    size_t offs;
+    size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
     size_t tile_range;
     size_t radix_counts, scan_bsum;

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
 
     GaussParams gp;
     float* out = gtheta + gg * RW;
-    if (!load_gaussian<DT, SHD>(sd, g, gp)) {
+    if (!load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0)) {
         for (int i = 0; i < RW; ++i) out[i] = 0.f;
         if (sd.g_means) { sd.g_means[3 * g] = 0.f; sd.g_means[3 * g + 1] = 0.f; sd.g_means[3 * g + 2] = 0.f; }
         if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = 0.f;
@@ -378,14 +378,23 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         dq[2] = (dqy - y * proj) * il;
         dq[3] = (dqz - z * proj) * il;
     }
-    out[0] = ds[0] * sh.s[0];
-    out[1] = ds[1] * sh.s[1];
-    out[2] = ds[2] * sh.s[2];
-    out[3] = dq[0]; out[4] = dq[1]; out[5] = dq[2]; out[6] = dq[3];
     const float dlogit = dop * opac * (1.f - opac);
-    out[7] = dlogit;
+    if constexpr ((8 + 3 * NCO) % 4 == 0) {     // row is a whole number of float4s (16-byte aligned)
+        float4* o4 = reinterpret_cast<float4*>(out);
+        o4[0] = make_float4(ds[0] * sh.s[0], ds[1] * sh.s[1], ds[2] * sh.s[2], dq[0]);
+        o4[1] = make_float4(dq[1], dq[2], dq[3], dlogit);
 #pragma unroll
-    for (int i = 0; i < 3 * NCO; ++i) out[8 + i] = dk[i];
+        for (int i = 0; i < (3 * NCO) / 4; ++i)
+            o4[2 + i] = make_float4(dk[4 * i], dk[4 * i + 1], dk[4 * i + 2], dk[4 * i + 3]);
+    } else {
+        out[0] = ds[0] * sh.s[0];
+        out[1] = ds[1] * sh.s[1];
+        out[2] = ds[2] * sh.s[2];
+        out[3] = dq[0]; out[4] = dq[1]; out[5] = dq[2]; out[6] = dq[3];
+        out[7] = dlogit;
+#pragma unroll
+        for (int i = 0; i < 3 * NCO; ++i) out[8 + i] = dk[i];
+    }
     if (sd.g_means) {
         sd.g_means[3 * g + 0] = dmu[0];
         sd.g_means[3 * g + 1] = dmu[1];

@@ -69,10 +69,38 @@ struct GaussParams {
     float sh[48];   // [coef][rgb]
 };
 
+// N consecutive codebook values starting at element `off` of `base`, read
+// with 16-byte loads (caller guarantees alignment and N * size % 16 == 0).
+template <int DT, int N>
+__device__ inline void load_vec(const void* base, int64_t off, float* out) {
+    if constexpr (DT == CGS_BF16) {
+        static_assert(N % 8 == 0, "BF16 vector rows come in 8s");
+        const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + off);
+#pragma unroll
+        for (int i = 0; i < N / 8; ++i) {
+            const uint4 q = p[i];
+            const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                out[8 * i + 2 * k] = __uint_as_float(wv[k] << 16);
+                out[8 * i + 2 * k + 1] = __uint_as_float(wv[k] & 0xffff0000u);
+            }
+        }
+    } else {
+        static_assert(N % 4 == 0, "FP32 vector rows come in 4s");
+        const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(base) + off);
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+            const float4 q = p[i];
+            out[4 * i] = q.x; out[4 * i + 1] = q.y; out[4 * i + 2] = q.z; out[4 * i + 3] = q.w;
+        }
+    }
+}
+
 // Returns false (and loads nothing) when an index is outside its codebook:
 // such a Gaussian is treated as culled and receives zero gradient.
 template <int DT, int SHD>
-__device__ inline bool load_gaussian(const SceneDesc& sd, int64_t g, GaussParams& gp) {
+__device__ inline bool load_gaussian(const SceneDesc& sd, int64_t g, GaussParams& gp, bool vec) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t ksr = sd.idx_sr[g];
     const int64_t ksh = sd.idx_sh[g];
@@ -82,6 +110,17 @@ __device__ inline bool load_gaussian(const SceneDesc& sd, int64_t g, GaussParams
     gp.mean[2] = sd.means[3 * g + 2];
     const int64_t bsr = ksr * sd.sr_stride + sd.sr_col0;
     const int64_t bsh = ksh * sd.sh_stride + sd.sh_col0;
+    if constexpr (SHD == 3) {
+        if (vec) {      // host-checked: aligned rows, opacity in the SR row
+            float sr[8];
+            load_vec<DT, 8>(sd.sr, bsr, sr);
+            gp.ls[0] = sr[0]; gp.ls[1] = sr[1]; gp.ls[2] = sr[2];
+            gp.q[0] = sr[3]; gp.q[1] = sr[4]; gp.q[2] = sr[5]; gp.q[3] = sr[6];
+            gp.logit = sr[7];
+            load_vec<DT, 48>(sd.sh, bsh, gp.sh);
+            return true;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) gp.ls[i] = load_cb<DT>(sd.sr, bsr + i);
 #pragma unroll

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
     const int64_t g = gg - sd.g_off;
 
     GaussParams gp;
-    const bool valid = load_gaussian<DT, SHD>(sd, g, gp);
+    const bool valid = load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
     GaussShape sh;
     if (valid) gaussian_shape(gp, sh);
     const float opac = valid ? 1.0f / (1.0f + __expf(-gp.logit)) : 0.0f;
@@ -67,30 +67,75 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
 }
 
 // ------------------------------------------------------------------ emission
-// One thread per record in depth order: write (tile, record) for every tile
-// of the record's rectangle, row-major, at the record's scanned offset.
-__global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ sorted_rec,
-                                              const uint32_t* __restrict__ offs, const uint2* __restrict__ tile_rect,
-                                              const DevCounters* __restrict__ cnt, uint32_t* __restrict__ inst_key,
-                                              uint32_t* __restrict__ inst_val, uint32_t* __restrict__ emit_off) {
+// Depth-ordered copies of each record's tile rectangle and tile count (one
+// random gather per record, so the scan and the emission read contiguously).
+__global__ __launch_bounds__(256) void k_gather_depth(int64_t n_rec, const uint32_t* __restrict__ sorted_rec,
+                                                      const uint2* __restrict__ tile_rect,
+                                                      const uint32_t* __restrict__ ntiles, uint2* __restrict__ rect_d,
+                                                      uint32_t* __restrict__ cnt_d) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= desc->n_rec) return;
+    if (j >= n_rec) return;
     const uint32_t r = sorted_rec[j];
-    emit_off[r] = offs[j];
+    rect_d[j] = tile_rect[r];
+    cnt_d[j] = ntiles[r];
+}
+
+// Wave-cooperative emission: a wavefront owns 64 consecutive records of the
+// depth order; their instances occupy one contiguous range of the instance
+// array, which the 64 lanes write in order (each lane finds the record of an
+// instance by a binary search over the wave's offsets in LDS), so writes are
+// coalesced and a record with many tiles does not stall its wave.  Instance
+// (record, tile) keys are the view's tile offset + the row-major tile index;
+// tiles of a record follow row-major order.  Also records each record's
+// emission offset for the backward.
+__global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ sorted_rec,
+                                              const uint32_t* __restrict__ offs, const uint2* __restrict__ rect_d,
+                                              const uint32_t* __restrict__ cnt_d, const DevCounters* __restrict__ cnt,
+                                              uint32_t* __restrict__ inst_key, uint32_t* __restrict__ inst_val,
+                                              uint32_t* __restrict__ emit_off) {
+    __shared__ uint32_t s_rel[4][64], s_w[4][64], s_base[4][64], s_tx[4][64], s_r[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    if (j0 >= desc->n_rec) return;
+    const int64_t j = j0 + lane;
+    const bool valid = j < desc->n_rec;
+    const uint32_t o0 = __builtin_amdgcn_readfirstlane(offs[j0]);
+    uint32_t rel = 0, c = 0, r = 0;
+    if (valid) {
+        r = sorted_rec[j];
+        const uint32_t o = offs[j];
+        emit_off[r] = o;
+        rel = o - o0;
+        c = cnt_d[j];
+    }
+    uint32_t endrel = valid ? rel + c : 0u;
+    endrel = wave_max_u32(endrel);
     if (cnt->n_inst_ok == 0ull) return;
-    const uint2 tr = tile_rect[r];
-    const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu, y1 = tr.y >> 16;
-    if (x1 <= x0 || y1 <= y0) return;
-    const int v = find_view_by_rec(desc, r);
-    const ViewDesc& vd = desc->views[v];
-    uint32_t o = offs[j];
-    for (uint32_t ty = y0; ty < y1; ++ty) {
-        const uint32_t rowbase = (uint32_t)vd.tile_off + ty * (uint32_t)vd.tiles_x;
-        for (uint32_t tx = x0; tx < x1; ++tx) {
-            inst_key[o] = rowbase + tx;
-            inst_val[o] = r;
-            ++o;
+    if (valid && c > 0) {
+        const uint2 tr = rect_d[j];
+        const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu;
+        const ViewDesc& vd = desc->views[find_view_by_rec(desc, r)];
+        s_w[w][lane] = x1 - x0;
+        s_tx[w][lane] = (uint32_t)vd.tiles_x;
+        s_base[w][lane] = (uint32_t)vd.tile_off + y0 * (uint32_t)vd.tiles_x + x0;
+        s_r[w][lane] = r;
+    }
+    s_rel[w][lane] = valid ? rel : endrel;
+    wave_sync();
+    for (uint32_t i = (uint32_t)lane; i < endrel; i += 64) {
+        // last record of the wave whose range starts at or before i
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_rel[w][mid] <= i) lo = mid; else hi = mid - 1;
         }
+        const uint32_t local = i - s_rel[w][lo];
+        const uint32_t wq = s_w[w][lo];
+        uint32_t row = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wq));
+        if (row * wq > local) --row;
+        if ((row + 1) * wq <= local) ++row;
+        inst_key[o0 + i] = s_base[w][lo] + row * s_tx[w][lo] + (local - row * wq);
+        inst_val[o0 + i] = s_r[w][lo];
     }
 }
 
@@ -272,12 +317,21 @@ hipError_t launch_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info, 
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const BatchDesc* d_desc, int64_t n_rec, const uint32_t* sorted_rec, const uint32_t* offs,
-                       const uint2* tr, const DevCounters* cnt, uint32_t* ik, uint32_t* iv, uint32_t* eo,
-                       hipStream_t st) {
+hipError_t launch_gather_depth(int64_t n_rec, const uint32_t* sorted_rec, const uint2* tr, const uint32_t* nt,
+                               uint2* rect_d, uint32_t* cnt_d, hipStream_t st) {
     if (n_rec <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0, st, d_desc, sorted_rec, offs, tr,
-                       cnt, ik, iv, eo);
+    hipLaunchKernelGGL(k_gather_depth, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0, st, n_rec, sorted_rec, tr,
+                       nt, rect_d, cnt_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const BatchDesc* d_desc, int64_t n_rec, const uint32_t* sorted_rec, const uint32_t* offs,
+                       const uint2* rect_d, const uint32_t* cnt_d, const DevCounters* cnt, uint32_t* ik, uint32_t* iv,
+                       uint32_t* eo, hipStream_t st) {
+    if (n_rec <= 0) return hipSuccess;
+    const int64_t waves = (n_rec + 63) / 64;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, d_desc, sorted_rec, offs, rect_d,
+                       cnt_d, cnt, ik, iv, eo);
     return hipGetLastError();
 }
 
