@@ -118,39 +118,40 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             bool any = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!((pq >> k) & 1u)) continue;          // wave-uniform
-                if (pos >= last[k]) continue;
+                if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
+                // Branch-free per pixel: pairs the forward did not blend
+                // (beyond n_last, or alpha < 1/255) get alpha 0 and zero
+                // gradients, which leaves T and the background sum unchanged.
                 const float dx = fpx[k] - gg.x;
                 const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
                 const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
-                if (alpha < kMinAlpha) continue;
-                any = true;
-                const float Tb = T[k] * __builtin_amdgcn_rcpf(1.f - alpha);
-                const float wgt = alpha * Tb;
+                const bool use = (pos < last[k]) && (alpha >= kMinAlpha);
+                any |= use;
+                const float am = use ? alpha : 0.f;
+                const float Tb = use ? T[k] * __builtin_amdgcn_rcpf(1.f - alpha) : T[k];
+                const float wgt = am * Tb;
                 a_r = fmaf(wgt, dC0[k], a_r);
                 a_g = fmaf(wgt, dC1[k], a_g);
                 a_bl = fmaf(wgt, dC2[k], a_bl);
                 const float e0 = cc.z - bh0[k], e1 = cc.w - bh1[k], e2 = bb - bh2[k];
-                const float dalpha = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
-                bh0[k] = fmaf(alpha, e0, bh0[k]);
-                bh1[k] = fmaf(alpha, e1, bh1[k]);
-                bh2[k] = fmaf(alpha, e2, bh2[k]);
+                const float dal = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
+                bh0[k] = fmaf(am, e0, bh0[k]);
+                bh1[k] = fmaf(am, e1, bh1[k]);
+                bh2[k] = fmaf(am, e2, bh2[k]);
                 T[k] = Tb;
-                if (alpha < kMaxAlpha) {
-                    a_o = fmaf(dalpha, G, a_o);
-                    if (!pcl) {
-                        const float dp = dalpha * alpha;
-                        const float dpx = dp * dx, dpy = dp * dy;
-                        a_a = fmaf(dpx, dx, a_a);
-                        a_b = fmaf(dpx, dy, a_b);
-                        a_c = fmaf(dpy, dy, a_c);
-                        // d power / d u = -(2 a' dx + b' dy), a' = -A/2, b' = -B
-                        a_u = fmaf(-dp, fmaf(na2, dx, nb * dy), a_u);
-                        a_v = fmaf(-dp, fmaf(nc2, dy, nb * dx), a_v);
-                    }
-                }
+                const bool open = use && (alpha < kMaxAlpha);      // alpha not saturated at 0.99
+                const float dao = open ? dal : 0.f;
+                a_o = fmaf(dao, G, a_o);
+                const float dp = (open && !pcl) ? dal * alpha : 0.f;  // dL/dpower
+                const float dpx = dp * dx, dpy = dp * dy;
+                a_a = fmaf(dpx, dx, a_a);
+                a_b = fmaf(dpx, dy, a_b);
+                a_c = fmaf(dpy, dy, a_c);
+                // d power / d u = -(2 a' dx + b' dy), a' = -A/2, b' = -B
+                a_u = fmaf(-dp, fmaf(na2, dx, nb * dy), a_u);
+                a_v = fmaf(-dp, fmaf(nc2, dy, nb * dx), a_v);
             }
             float* so = &s_o[w][j][row][0];
             if (__ballot(any) != 0ull) {
