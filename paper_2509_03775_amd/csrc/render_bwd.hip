@@ -119,16 +119,17 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
-                // Branch-free per pixel: pairs the forward did not blend
-                // (beyond n_last, or alpha < 1/255) get alpha 0 and zero
-                // gradients, which leaves T and the background sum unchanged.
                 const float dx = fpx[k] - gg.x;
                 const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
                 const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
                 const bool use = (pos < last[k]) && (alpha >= kMinAlpha);
-                any |= use;
+                if (__ballot(use) == 0ull) continue;       // no pixel of the quadrant blended it
+                any = true;
+                // Branch-free for the lanes of the quadrant: pairs the forward
+                // did not blend get alpha 0 and zero gradients, which leaves T
+                // and the background sum unchanged.
                 const float am = use ? alpha : 0.f;
                 const float Tb = use ? T[k] * __builtin_amdgcn_rcpf(1.f - alpha) : T[k];
                 const float wgt = am * Tb;
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 a_v = fmaf(-dp, fmaf(nc2, dy, nb * dx), a_v);
             }
             float* so = &s_o[w][j][row][0];
-            if (__ballot(any) != 0ull) {
+            if (any) {
                 const float s0 = row16_sum(a_u), s1 = row16_sum(a_v), s2 = row16_sum(a_a);
                 const float s3 = row16_sum(a_b), s4 = row16_sum(a_c), s5 = row16_sum(a_o);
                 const float s6 = row16_sum(a_r), s7 = row16_sum(a_g), s8 = row16_sum(a_bl);

@@ -260,26 +260,22 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
-                // Branch-free per pixel: a pair is blended when the pixel is
-                // still live, alpha >= 1/255 and T stays >= 1e-4; otherwise it
-                // contributes alpha 0 (and a failed T test ends the pixel).
+                if (!live[k]) continue;
                 const float dx = fpx[k] - gg.x;
                 const float dy = fpy[k] - gg.y;
                 float G;
                 bool pcl;
                 const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
+                if (alpha < kMinAlpha) continue;
                 const float Tn = T[k] * (1.f - alpha);
-                const bool cand = live[k] && (alpha >= kMinAlpha);
-                const bool stop = cand && (Tn < kMinT);
-                const bool use = cand && !stop;
-                live[k] = live[k] && !stop;
-                const float wgt = use ? alpha * T[k] : 0.f;
+                if (Tn < kMinT) { live[k] = false; continue; }
+                const float wgt = alpha * T[k];
                 C0[k] = fmaf(wgt, cc.z, C0[k]);
                 C1[k] = fmaf(wgt, cc.w, C1[k]);
                 C2[k] = fmaf(wgt, bb, C2[k]);
-                T[k] = use ? Tn : T[k];
-                last[k] = use ? pos : last[k];
-                if constexpr (STATS) nb[k] += use ? 1u : 0u;
+                T[k] = Tn;
+                last[k] = pos;
+                if constexpr (STATS) ++nb[k];
             }
         }
         wave_sync();
