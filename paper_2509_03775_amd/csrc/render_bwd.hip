@@ -112,8 +112,6 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             const float4 gg = s_g[w][j];
             const float4 cc = s_c[w][j];
             const float bb = s_b[w][j];
-            // natural-log conic entries for the derivatives of power
-            const float na2 = 2.f * kLn2 * gg.z, nb = kLn2 * gg.w, nc2 = 2.f * kLn2 * cc.x;
             float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
             bool any = false;
 #pragma unroll
@@ -150,9 +148,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 a_a = fmaf(dpx, dx, a_a);
                 a_b = fmaf(dpx, dy, a_b);
                 a_c = fmaf(dpy, dy, a_c);
-                // d power / d u = -(2 a' dx + b' dy), a' = -A/2, b' = -B
-                a_u = fmaf(-dp, fmaf(na2, dx, nb * dy), a_u);
-                a_v = fmaf(-dp, fmaf(nc2, dy, nb * dx), a_v);
+                // dL/du = -(2 a' Sx + b' Sy), dL/dv = -(2 c' Sy + b' Sx) with
+                // Sx = sum dp dx, Sy = sum dp dy (a' = -A/2, b' = -B, c' = -C/2);
+                // the conic is the record's, so the sums are taken first.
+                a_u += dpx;
+                a_v += dpy;
             }
             float* so = &s_o[w][j][row][0];
             if (any) {
@@ -172,9 +172,17 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         if (slot >= 0) {
             float* dst = ginst + 9 * slot;
             if (qm != 0u) {
+                float t9[9];
 #pragma unroll
                 for (int k = 0; k < 9; ++k)
-                    dst[k] = ((s_o[w][mine][0][k] + s_o[w][mine][1][k]) + s_o[w][mine][2][k]) + s_o[w][mine][3][k];
+                    t9[k] = ((s_o[w][mine][0][k] + s_o[w][mine][1][k]) + s_o[w][mine][2][k]) + s_o[w][mine][3][k];
+                // natural-log conic entries of this lane's record
+                const float na2 = 2.f * kLn2 * g.z, nb = kLn2 * g.w, nc2 = 2.f * kLn2 * c.x;
+                const float sx = t9[0], sy = t9[1];
+                t9[0] = -fmaf(na2, sx, nb * sy);
+                t9[1] = -fmaf(nc2, sy, nb * sx);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) dst[k] = t9[k];
             } else {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) dst[k] = 0.f;

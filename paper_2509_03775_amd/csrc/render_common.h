@@ -352,33 +352,53 @@ __device__ inline float blend_alpha(float dx, float dy, const float4& g, const f
     return og < kMaxAlpha ? og : kMaxAlpha;
 }
 
+// Minimum over the rectangle [x0,x1] x [y0,y1] of the positive-definite
+// quadratic form f(p) = (p-m)^T K (p-m), K = [[A, B], [B, C]]: zero if m is
+// inside, otherwise the least of the four edge minima (on an edge the form is
+// a 1-D quadratic, minimised at its clamped vertex).
+__device__ inline float rect_min_form(float A, float B, float C, float mx, float my, float x0, float x1, float y0,
+                                      float y1) {
+    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
+    const float iA = 1.f / A, iC = 1.f / C;
+    float best = 3.0e38f;
+    const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dx = xs[e] - mx;
+        const float dy = fminf(fmaxf(-B * dx * iC, y0 - my), y1 - my);
+        best = fminf(best, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
+        const float ey = ys[e] - my;
+        const float ex = fminf(fmaxf(-B * ey * iA, x0 - mx), x1 - mx);
+        best = fminf(best, A * ex * ex + 2.f * B * ex * ey + C * ey * ey);
+    }
+    return best;
+}
+
 // Which 8x8 quadrants of a 16x16 tile (pixel origin x0, y0; last valid pixel
 // xm, ym) can the record reach with alpha >= 1/255?  Bit k = quadrant
-// (k & 1, k >> 1).  Outside the axis-aligned box of the ellipse on which exact
-// alpha (on the stored record values) equals (1/255)(1 - 1e-3), exact alpha is
-// below that level, so the FP32 alpha of blend_alpha (relative error ~1e-6)
-// is below 1/255 and every such pair would be skipped anyway: skipping whole
-// quadrants outside the box changes no result.
+// (k & 1, k >> 1).  Exact alpha (on the stored record values) at a pixel p is
+// o exp(-f(p)/2) with f the conic form; it reaches lo = (1/255)(1 - 1e-3)
+// only where f <= rho = 2 ln(o/lo).  A quadrant whose pixel rectangle has
+// min f > rho (with a 1e-4 relative safety margin for this FP32 evaluation)
+// holds no pixel with exact alpha >= lo, so the FP32 alpha of blend_alpha
+// (relative error ~1e-6) stays below 1/255 there and every pair would be
+// skipped anyway: skipping such quadrants changes no result.
 __device__ inline uint32_t quadrant_mask(const float4& g, const float4& c, float x0, float y0, float xm, float ym) {
     const float lo = kMinAlpha * 0.999f;
     const float o = c.y;
     if (!(o > lo)) return 0u;
     const float A = -2.f * kLn2 * g.z, B = -kLn2 * g.w, C = -2.f * kLn2 * c.x;
-    const float det = A * C - B * B;
-    float hx = 3.0e38f, hy = 3.0e38f;
-    if (det > 0.f) {
-        const float rho = 2.f * __logf(o / lo);
-        hx = __builtin_sqrtf(rho * C / det) * 1.0001f + 1e-3f;
-        hy = __builtin_sqrtf(rho * A / det) * 1.0001f + 1e-3f;
+    if (!(A > 0.f && C > 0.f && A * C - B * B > 0.f)) return 0xfu;     // no claim: keep all
+    const float rho = 2.f * __logf(o / lo) * 1.0001f + 1e-4f;
+    uint32_t m = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float qx0 = x0 + 8.f * (float)(k & 1), qy0 = y0 + 8.f * (float)(k >> 1);
+        if (qx0 > xm || qy0 > ym) continue;
+        const float qx1 = fminf(qx0 + 7.f, xm), qy1 = fminf(qy0 + 7.f, ym);
+        if (rect_min_form(A, B, C, g.x, g.y, qx0, qx1, qy0, qy1) <= rho) m |= 1u << k;
     }
-    const float gx0 = g.x - hx, gx1 = g.x + hx, gy0 = g.y - hy, gy1 = g.y + hy;
-    const float xmid = x0 + 8.f, ymid = y0 + 8.f;
-    const bool cl = gx0 <= fminf(xmid - 1.f, xm) && gx1 >= x0;       // columns x0 .. x0+7
-    const bool cr = gx0 <= xm && gx1 >= xmid && xmid <= xm;          // columns x0+8 .. x0+15
-    const bool rt = gy0 <= fminf(ymid - 1.f, ym) && gy1 >= y0;
-    const bool rb = gy0 <= ym && gy1 >= ymid && ymid <= ym;
-    return (uint32_t)(cl && rt) | ((uint32_t)(cr && rt) << 1) | ((uint32_t)(cl && rb) << 2) |
-           ((uint32_t)(cr && rb) << 3);
+    return m;
 }
 
 // Map a workgroup index to the tile group it shades.  Order 1 groups
