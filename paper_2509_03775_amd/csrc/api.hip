@@ -17,7 +17,7 @@ hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, float
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_gather_depth(int64_t, const uint32_t*, const uint2*, const uint32_t*, uint2*, uint32_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
-                       const DevCounters*, uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+                       const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, const uint32_t*, int64_t, int32_t,
                              int32_t, const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
@@ -213,7 +213,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.radix_counts = take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(p.radix_blocks_max, 1));
     p.scan_blocks_max = (int64_t)scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * p.radix_blocks_max));
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
-    p.emit_off = take(4 * (size_t)R);
+    p.slot_off = take(4 * (size_t)R);
     p.ginst = take(4 * 9 * (size_t)cap);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
@@ -324,7 +324,9 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
     uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
     CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.rect_d),
-                        at<uint32_t>(ws, p.cnt_d), cnt, ik[1], iv[1], at<uint32_t>(ws, p.emit_off), st));
+                        at<uint32_t>(ws, p.cnt_d), cnt, ik[1], iv[1], st));
+    // backward gradient slots of each record, in record order
+    CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), nullptr, h.d.n_rec, at<uint32_t>(ws, p.slot_off), nullptr, bsum, st));
     int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, counts, bsum, st, &e);
     CGS_TRY(e);
     if (ib != h.inst_buf) return CGS_EHIP;
@@ -381,11 +383,11 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
     float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
                              at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue),
-                             at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.emit_off), grad_image, T_final, n_last,
+                             at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.slot_off), grad_image, T_final, n_last,
                              ginst, st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
-    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, ginst, at<uint32_t>(ws, p.emit_off),
+    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, ginst, at<uint32_t>(ws, p.slot_off),
                          at<uint32_t>(ws, p.ntiles), cnt, gth, st));
     CGS_TRY(mark(h, 6, st));
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};

@@ -78,7 +78,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range;
     size_t radix_counts, scan_bsum;
-    size_t emit_off, ginst, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t slot_off, ginst, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t radix_blocks_max, scan_blocks_max;
 };

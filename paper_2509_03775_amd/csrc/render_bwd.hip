@@ -15,8 +15,9 @@ namespace cgs {
 // r, g, b).  The lane's four pixels are summed in registers, each 16-lane row
 // by DPP shifts, and the four row partials of every record are added once per
 // batch by the lane that loaded the record.  The tile's total for a record
-// goes to that (tile, record) instance's own slot -- the record's emission
-// offset + the tile's row-major index in the record's rectangle -- with plain
+// goes to that (tile, record) instance's own slot -- the record's slot offset
+// (tile counts scanned in record order) + the tile's row-major index in the
+// record's rectangle -- with plain
 // stores: no atomics, and the per-record sum over its tiles is taken later in
 // a fixed order, so the backward is deterministic.  Instances the walk never
 // reaches (beyond every pixel's n_last) get zeros.
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                                                          const float4* __restrict__ rec_col,
                                                          const float* __restrict__ rec_blue,
                                                          const uint2* __restrict__ tile_rect,
-                                                         const uint32_t* __restrict__ emit_off,
+                                                         const uint32_t* __restrict__ slot_off,
                                                          const float* __restrict__ grad_image,
                                                          const float* __restrict__ T_final,
                                                          const int32_t* __restrict__ n_last,
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     auto slot_of = [&](uint32_t r) -> int64_t {
         const uint2 tr = tile_rect[r];
         const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rx1 = (int)(tr.y & 0xffffu);
-        return (int64_t)emit_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
+        return (int64_t)slot_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
     };
     const int row = lane >> 4;
     const bool row_end = (lane & 15) == 15;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
 template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
-                                               const uint32_t* __restrict__ emit_off,
+                                               const uint32_t* __restrict__ slot_off,
                                                const uint32_t* __restrict__ ntiles,
                                                const DevCounters* __restrict__ cnt, float* __restrict__ gtheta) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
@@ -239,11 +240,12 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         const int v = desc->view_list[sd.vfirst + vi];
         const ViewDesc& vd = desc->views[v];
         const int64_t r = vd.rec_off + g;
-        // dL/d(record) = sum over the record's tile instances, in emission order
+        // dL/d(record) = sum over the record's tile slots, in row-major tile order
+        // (slots of consecutive Gaussians are adjacent: coalesced reads)
         const uint32_t nt = binned ? ntiles[r] : 0u;
         if (nt == 0u) continue;
         float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        const float* gi = ginst + 9 * (int64_t)emit_off[r];
+        const float* gi = ginst + 9 * (int64_t)slot_off[r];
         for (uint32_t e = 0; e < nt; ++e)
 #pragma unroll
             for (int i = 0; i < 9; ++i) d[i] += gi[9 * e + i];

@@ -86,13 +86,11 @@ __global__ __launch_bounds__(256) void k_gather_depth(int64_t n_rec, const uint3
 // instance by a binary search over the wave's offsets in LDS), so writes are
 // coalesced and a record with many tiles does not stall its wave.  Instance
 // (record, tile) keys are the view's tile offset + the row-major tile index;
-// tiles of a record follow row-major order.  Also records each record's
-// emission offset for the backward.
+// tiles of a record follow row-major order.
 __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ sorted_rec,
                                               const uint32_t* __restrict__ offs, const uint2* __restrict__ rect_d,
                                               const uint32_t* __restrict__ cnt_d, const DevCounters* __restrict__ cnt,
-                                              uint32_t* __restrict__ inst_key, uint32_t* __restrict__ inst_val,
-                                              uint32_t* __restrict__ emit_off) {
+                                              uint32_t* __restrict__ inst_key, uint32_t* __restrict__ inst_val) {
     __shared__ uint32_t s_rel[4][64], s_w[4][64], s_base[4][64], s_tx[4][64], s_r[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * 64;
@@ -103,9 +101,7 @@ __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc
     uint32_t rel = 0, c = 0, r = 0;
     if (valid) {
         r = sorted_rec[j];
-        const uint32_t o = offs[j];
-        emit_off[r] = o;
-        rel = o - o0;
+        rel = offs[j] - o0;
         c = cnt_d[j];
     }
     uint32_t endrel = valid ? rel + c : 0u;
@@ -327,11 +323,11 @@ hipError_t launch_gather_depth(int64_t n_rec, const uint32_t* sorted_rec, const 
 
 hipError_t launch_emit(const BatchDesc* d_desc, int64_t n_rec, const uint32_t* sorted_rec, const uint32_t* offs,
                        const uint2* rect_d, const uint32_t* cnt_d, const DevCounters* cnt, uint32_t* ik, uint32_t* iv,
-                       uint32_t* eo, hipStream_t st) {
+                       hipStream_t st) {
     if (n_rec <= 0) return hipSuccess;
     const int64_t waves = (n_rec + 63) / 64;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, d_desc, sorted_rec, offs, rect_d,
-                       cnt_d, cnt, ik, iv, eo);
+                       cnt_d, cnt, ik, iv);
     return hipGetLastError();
 }
 
