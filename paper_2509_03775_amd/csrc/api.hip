@@ -15,7 +15,7 @@ namespace cgs {
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, float4*, float*, uint32_t*, uint2*,
                              uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
-hipError_t launch_gather_depth(int64_t, const uint32_t*, const uint2*, const uint32_t*, uint2*, uint32_t*, hipStream_t);
+hipError_t launch_gather_depth(int64_t, const uint32_t*, const uint2*, uint2*, uint32_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
                        const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
@@ -317,8 +317,8 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
                               st, &e);
     CGS_TRY(e);
     // instance offsets in depth order, capacity check, emission
-    CGS_TRY(launch_gather_depth(h.d.n_rec, dv[db], at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles),
-                                at<uint2>(ws, p.rect_d), at<uint32_t>(ws, p.cnt_d), st));
+    CGS_TRY(launch_gather_depth(h.d.n_rec, dv[db], at<uint2>(ws, p.tile_rect), at<uint2>(ws, p.rect_d),
+                                at<uint32_t>(ws, p.cnt_d), st));
     CGS_TRY(scan_u32(at<uint32_t>(ws, p.cnt_d), nullptr, h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));
     CGS_TRY(launch_capacity(cnt, h.d.capacity, d_info, st));
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};

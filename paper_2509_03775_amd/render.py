@@ -71,6 +71,46 @@ class DeviceScene:
         return d
 
 
+class DeviceScene2:
+    """The paper's state layout (Sec. 4.1, Fig. 4) on the GPU: an SR codebook
+    [|SR|, 7] (log-scale 3, quaternion 4), an SH codebook [|SH|, 3(d+1)^2], two
+    index arrays g2sr / g2sh and a per-Gaussian opacity logit."""
+
+    def __init__(self, means, idx_sr, idx_sh, sr, sh, opacity_logit, sh_degree: int):
+        assert means.dtype == torch.float32 and means.is_contiguous() and means.shape[1] == 3
+        for t in (idx_sr, idx_sh):
+            assert t.dtype == torch.int32 and t.is_contiguous() and t.shape[0] == means.shape[0]
+        assert sr.dtype == sh.dtype and sr.dtype in (torch.float32, torch.bfloat16)
+        assert sr.shape[1] == 7 and sh.shape[1] == 3 * (sh_degree + 1) ** 2
+        assert opacity_logit.dtype == torch.float32 and opacity_logit.shape[0] == means.shape[0]
+        self.means, self.idx_sr, self.idx_sh = means, idx_sr, idx_sh
+        self.sr, self.sh, self.opacity_logit, self.sh_degree = sr.contiguous(), sh.contiguous(), opacity_logit, sh_degree
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def descriptor(self) -> cgs.Scene:
+        dt = cgs.CGS_BF16 if self.sr.dtype == torch.bfloat16 else cgs.CGS_F32
+        d = cgs.Scene()
+        d.n = self.n
+        d.sh_degree = self.sh_degree
+        d.opacity_mode = 0
+        d.means = self.means.data_ptr()
+        d.idx_sr = self.idx_sr.data_ptr()
+        d.idx_sh = self.idx_sh.data_ptr()
+        d.sr = cgs.CbView(self.sr.data_ptr(), dt, 7, int(self.sr.shape[0]), 0, 0)
+        d.sh = cgs.CbView(self.sh.data_ptr(), dt, int(self.sh.shape[1]), int(self.sh.shape[0]), 0, 0)
+        d.opacity_logit = self.opacity_logit.data_ptr()
+        return d
+
+    def grad_buffers(self, device):
+        return (torch.empty_like(self.means),
+                torch.empty((self.sr.shape[0], 7), dtype=torch.float32, device=device),
+                torch.empty((self.sh.shape[0], self.sh.shape[1]), dtype=torch.float32, device=device),
+                torch.empty(self.n, dtype=torch.float32, device=device))
+
+
 def camera_struct(c: sc.Camera) -> cgs.Camera:
     out = cgs.Camera()
     out.width, out.height = int(c.width), int(c.height)
@@ -116,15 +156,33 @@ class Renderer:
         self.T_final = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
         self.n_last = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
         self.d_info = torch.zeros(4, dtype=torch.int64, device=self.device)
-        self.grad_means = [torch.empty_like(s.means) for s in self.scenes]
-        self.grad_cb = [torch.empty((s.k, s.r), dtype=torch.float32, device=self.device) for s in self.scenes]
+        self.grad_means, self.grad_cb, self.grad_sr, self.grad_sh, self.grad_opacity = [], [], [], [], []
         gr = []
-        for s, gm, gc in zip(self.scenes, self.grad_means, self.grad_cb):
+        for s in self.scenes:
             g = cgs.SceneGrads()
-            g.means = gm.data_ptr()
-            g.sr, g.sr_stride, g.sr_col0 = gc.data_ptr(), s.r, 0
-            g.sh, g.sh_stride, g.sh_col0 = gc.data_ptr(), s.r, 8
-            g.opacity = None
+            if isinstance(s, DeviceScene2):
+                gm, gsr, gsh, gop = s.grad_buffers(self.device)
+                g.means = gm.data_ptr()
+                g.sr, g.sr_stride, g.sr_col0 = gsr.data_ptr(), 7, 0
+                g.sh, g.sh_stride, g.sh_col0 = gsh.data_ptr(), int(gsh.shape[1]), 0
+                g.opacity = gop.data_ptr()
+                self.grad_means.append(gm)
+                self.grad_cb.append(None)
+                self.grad_sr.append(gsr)
+                self.grad_sh.append(gsh)
+                self.grad_opacity.append(gop)
+            else:
+                gm = torch.empty_like(s.means)
+                gc = torch.empty((s.k, s.r), dtype=torch.float32, device=self.device)
+                g.means = gm.data_ptr()
+                g.sr, g.sr_stride, g.sr_col0 = gc.data_ptr(), s.r, 0
+                g.sh, g.sh_stride, g.sh_col0 = gc.data_ptr(), s.r, 8
+                g.opacity = None
+                self.grad_means.append(gm)
+                self.grad_cb.append(gc)
+                self.grad_sr.append(None)
+                self.grad_sh.append(None)
+                self.grad_opacity.append(None)
             gr.append(g)
         self._grads = (cgs.SceneGrads * ns)(*gr)
         self.set_capacity(capacity)

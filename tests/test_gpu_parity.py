@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_2509_03775_amd import cgs, render, scenes as sc
 from harness import (GRAD_TOL, IMAGE_TOL, compare_view, full_pixels, grad_errors, oracle_grad_image,
-                     oracle_render, oracle_scene_grads, say)
+                     oracle_render, oracle_scene_grads, rel_l2, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -269,3 +269,70 @@ def test_loss_l1():
     L, g = oracle.loss_l1(a, b)
     assert abs(loss.item() - L) <= 1e-6 * L
     np.testing.assert_array_equal(grad.cpu().numpy(), g.astype(np.float32))
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_two_codebook_layout(bf16):
+    """The paper's state (Sec. 4.1): SR codebook [|SR|, 7], SH codebook
+    [|SH|, 48], indices g2sr / g2sh, per-Gaussian opacity; two segmented
+    reductions plus a per-Gaussian opacity gradient."""
+    say(f"[two codebooks] bf16={bf16}")
+    rng = np.random.default_rng(91 + int(bf16))
+    n, ksr, ksh, d = 15000, 300, 700, 3
+    W, H = 160, 120
+    means = sc.clustered_means(rng, n).astype(np.float32)
+    sr = np.zeros((ksr, 7))
+    sr[:, 0:3] = rng.normal(sc.screen_matched_mu(W), 0.5, (ksr, 3))
+    q = rng.standard_normal((ksr, 4))
+    sr[:, 3:7] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    sh = np.zeros((ksh, 48))
+    sh[:, 0:3] = rng.uniform(0, 1, (ksh, 3))
+    sh[:, 3:] = rng.normal(0, 0.05, (ksh, 45))
+    sr32, sh32 = sr.astype(np.float32), sh.astype(np.float32)
+    if bf16:
+        sr_bits, sh_bits = sc.f32_to_bf16_bits(sr32), sc.f32_to_bf16_bits(sh32)
+        sr32, sh32 = sc.bf16_bits_to_f32(sr_bits), sc.bf16_bits_to_f32(sh_bits)
+    logit = rng.standard_normal(n).astype(np.float32)
+    g2sr = rng.integers(0, ksr, n).astype(np.int32)
+    g2sh = rng.integers(0, ksh, n).astype(np.int32)
+    cam = sc.pinhole(W, H, (0.3, -0.2, -3.0))
+    target = rng.uniform(0, 1, (H, W, 3)).astype(np.float32)
+    rows = np.concatenate([sr32[g2sr], logit[:, None], sh32[g2sh]], 1).astype(np.float32)
+    host = sc.Scene(means, np.zeros(n, np.int32), np.zeros((1, 56), np.float32), d)
+    pix = full_pixels(cam)
+    base = oracle.render_view(host, cam, pix, rows32=rows)
+    L, g = oracle.loss_l1(base["color"].reshape(H, W, 3), target)
+    g = g.reshape(-1, 3)
+    g[base["ambiguous"]] = 0.0
+    g32 = g.astype(np.float32)
+    og = oracle.render_view(host, cam, pix, grad_color=g32.astype(np.float64), rows32=rows)
+    o_sr = oracle.codebook_grad_reduce(og["grad_rows"][:, :7], g2sr, ksr)
+    o_sh = oracle.codebook_grad_reduce(og["grad_rows"][:, 8:], g2sh, ksh)
+    o_op = og["grad_rows"][:, 7]
+
+    def dev(a, dt=None):
+        t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        return t
+    if bf16:
+        dsr = dev(sr_bits.view(np.int16)).view(torch.bfloat16)
+        dsh = dev(sh_bits.view(np.int16)).view(torch.bfloat16)
+    else:
+        dsr, dsh = dev(sr32), dev(sh32)
+    ds = render.DeviceScene2(dev(means), dev(g2sr), dev(g2sh), dsr, dsh, dev(logit), d)
+    r = render.Renderer([ds], [cam], [0])
+    r.fit_capacity()
+    r.forward()
+    torch.cuda.synchronize()
+    ec, et, mism, namb = compare_view(r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy(), cam,
+                                      pix, base)
+    say(f"  colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}")
+    assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
+    r.backward(torch.from_numpy(g32).cuda())
+    torch.cuda.synchronize()
+    errs = {"means": rel_l2(r.grad_means[0].cpu().numpy(), og["grad_means"]),
+            "sr": rel_l2(r.grad_sr[0].cpu().numpy(), o_sr),
+            "sh": rel_l2(r.grad_sh[0].cpu().numpy(), o_sh),
+            "opacity": rel_l2(r.grad_opacity[0].cpu().numpy(), o_op)}
+    say("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
