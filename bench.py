@@ -199,13 +199,88 @@ def blend_roofline(stage, ms, e_eval, e_blend):
             "ops_per_launch": ops}
 
 
+def step_bytes(wl: sc.Workload, n_inst: int) -> dict:
+    """Algorithmic HBM bytes of one step, per stage: what the method must
+    read and write once (codebook rows counted once per unique row; radix
+    passes at 20 B per item: key+value in and out plus the key histogram
+    read)."""
+    N = sum(s.n for s in wl.scenes)
+    Rrec = sum(wl.scenes[int(v)].n for v in wl.view_scene)
+    K = sum(s.k for s in wl.scenes)
+    RW = wl.scenes[0].r
+    b = 2 if wl.bf16 else 4
+    P = wl.n_pixels
+    M = n_inst
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in wl.cameras)
+    tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
+    row_passes = (max(1, (K - 1).bit_length()) + 7) // 8
+    out = {
+        "preprocess": N * 16 + K * RW * b + Rrec * 52,
+        "binning": 4 * 20 * Rrec + Rrec * 20 + Rrec * 12 + Rrec * 16 + M * 8 + tile_passes * 20 * M + Rrec * 8,
+        "blend_fwd": M * 40 + P * 20,
+        "loss": P * 36,
+        "blend_bwd": M * 40 + M * 36 + P * 24,
+        "chain": N * 16 + K * RW * b + Rrec * 8 + M * 36 + N * (12 + 4 * RW),
+        "codebook_reduce": N * 8 + row_passes * 20 * N + N * 4 * RW + K * 4 * RW,
+    }
+    out["total"] = sum(out.values())
+    return out
+
+
+def compare_forms(a: "Form", b: "Form"):
+    """Image and codebook-gradient difference between two forms of the same
+    scene (BF16 vs FP32 codebook storage: the quantisation effect)."""
+    ia = torch.cat([r.image for r in a.renderers]).double()
+    ib = torch.cat([r.image for r in b.renderers]).double()
+    ga = sum(g for r in a.renderers for g in r.grad_cb).double()
+    gb = sum(g for r in b.renderers for g in r.grad_cb).double()
+    return {"image_max_abs": float((ia - ib).abs().max()), "image_mean_abs": float((ia - ib).abs().mean()),
+            "codebook_grad_rel_l2": float(torch.linalg.norm(ga - gb) / torch.linalg.norm(gb))}
+
+
+def uncompressed_workload(wl: sc.Workload) -> sc.Workload:
+    """Same Gaussians with one codebook row per Gaussian (K = N, identity
+    indices): the uncompressed per-Gaussian-parameter baseline."""
+    scenes = []
+    for s in wl.scenes:
+        cb = np.ascontiguousarray(s.cb[s.idx])
+        bits = None if s.cb_bf16 is None else np.ascontiguousarray(s.cb_bf16[s.idx])
+        scenes.append(sc.Scene(s.means, np.arange(s.n, dtype=np.int32), cb, s.sh_degree, bits))
+    return sc.Workload(wl.name + ":uncompressed", scenes, wl.cameras, wl.view_scene, wl.targets, wl.bf16)
+
+
+def time_graph(form: "Form", steps: int) -> float:
+    """One step captured in a HIP graph, replayed `steps` times."""
+    form.step()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        form.step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        form.step()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=HEADLINE)
-    ap.add_argument("--extra-forms", default="fp32_plain,1m", help="comma list: fp32_plain, 1m, none")
+    ap.add_argument("--extra-forms", default="fp32_plain,1m,uncompressed,uneven16,graph",
+                    help="comma list of: fp32_plain, 1m, uncompressed, uneven16, graph; or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--waves-per-block", type=int, default=1)
@@ -244,15 +319,35 @@ def main():
     forms = {f"{'bf16' if wl.bf16 else 'fp32'}_batched:{args.workload}": value}
     n_inst = head.instances
     extras = [x for x in args.extra_forms.split(",") if x and x != "none"]
-    del head
-    torch.cuda.empty_cache()
+    extra_info = {}
+    nsteps = max(3, args.steps // 2)
+    if "graph" in extras:
+        log("[bench] timing the batched step as HIP graph replays")
+        extra_info["graph_ms_per_step"] = time_graph(head, nsteps)
+        forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_graph:{args.workload}"] = \
+            wl.n_pixels / (extra_info["graph_ms_per_step"] * 1e-3) / 1e6
     if "fp32_plain" in extras:
         log(f"[bench] timing {args.workload} plain fp32")
         wl32 = sc.make_workload(args.workload, bf16=False)
         f = Form(wl32, batched=False)
-        forms[f"fp32_plain:{args.workload}"] = wl32.n_pixels / (f.time(max(3, args.steps // 2), 2) * 1e-3) / 1e6
-        del f
+        forms[f"fp32_plain:{args.workload}"] = wl32.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
+        if wl.bf16:
+            head.step()
+            torch.cuda.synchronize()
+            extra_info["bf16_vs_fp32_codebook"] = compare_forms(head, f)
+        del f, wl32
         torch.cuda.empty_cache()
+    if "uncompressed" in extras:
+        log(f"[bench] timing {args.workload} uncompressed (K = N)")
+        wu = uncompressed_workload(wl)
+        f = Form(wu, batched=True)
+        ms_u = f.time(nsteps, 2)
+        forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_uncompressed:{args.workload}"] = wl.n_pixels / (ms_u * 1e-3) / 1e6
+        extra_info["codebook_speedup_vs_uncompressed"] = ms_u / ms
+        del f, wu
+        torch.cuda.empty_cache()
+    del head
+    torch.cuda.empty_cache()
     if "1m" in extras:
         name = "clusters1m_1600x1064"
         for bf in (True, False):
@@ -260,7 +355,17 @@ def main():
             w1 = sc.make_workload(name, bf16=bf)
             f = Form(w1, batched=bf)
             forms[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = \
-                w1.n_pixels / (f.time(max(3, args.steps // 2), 2) * 1e-3) / 1e6
+                w1.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
+            del f
+            torch.cuda.empty_cache()
+    if "uneven16" in extras:
+        name = "uneven16_512px"
+        for bf, batched in ((True, True), (False, False)):
+            log(f"[bench] timing {name} {'bf16 batched' if batched else 'fp32 plain (16 calls)'}")
+            w5 = sc.make_workload(name, bf16=bf)
+            f = Form(w5, batched=batched)
+            ms5 = time_graph(f, nsteps) if batched else f.time(nsteps, 2)
+            forms[f"{'bf16_batched_graph' if batched else 'fp32_plain'}:{name}"] = w5.n_pixels / (ms5 * 1e-3) / 1e6
             del f
             torch.cuda.empty_cache()
     cpu = None
@@ -268,6 +373,7 @@ def main():
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(wl, args.cpu_seconds)
     cam = wl.cameras[0]
+    sb = step_bytes(wl, n_inst)
     out = {
         "metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -280,6 +386,9 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "stages_ms": stages,
+        "hbm_roofline_step": {"algorithmic_bytes": sb["total"], "bytes_by_stage": sb,
+                              "frac": sb["total"] / HBM_PEAK / (ms * 1e-3)},
+        "extra": extra_info,
         "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst},
         "schedule": {"waves_per_block": args.waves_per_block, "tile_order": args.tile_order},
     }
