@@ -27,7 +27,7 @@ import torch
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_2509_03775_amd import cgs, render, scenes as sc  # noqa: E402
+from paper_2509_03775_amd import autotune, cgs, render, scenes as sc  # noqa: E402
 
 METRIC = "fwd+bwd rendered Mpixel/s at 1M/4M Gaussians, BF16-batched vs plain FP32"
 HEADLINE = "clusters4m_bf16_4x1957x1091"
@@ -283,8 +283,8 @@ def main():
                     help="comma list of: fp32_plain, 1m, uncompressed, uneven16, graph; or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--waves-per-block", type=int, default=1)
-    ap.add_argument("--tile-order", type=int, default=0)
+    ap.add_argument("--schedule", default="auto",
+                    help="blend schedule 'W,O' (waves per workgroup, tile order) or 'auto' to time the candidates")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (a kernel of known traffic "
                          "for scaling HBM counters)")
@@ -301,13 +301,22 @@ def main():
         n = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.arange(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read + {args.copy_calibration_mib} MiB written")
         del src, dst
     log(f"[bench] generating {args.workload}")
     wl = sc.make_workload(args.workload)
-    head = Form(wl, batched=True, waves_per_block=args.waves_per_block, tile_order=args.tile_order)
+    head = Form(wl, batched=True)
+    tuned = {}
+    if args.schedule == "auto":
+        log("[bench] timing the blend schedule candidates")
+        head.step()
+        sched, tuned = autotune.tune(head.renderers[0], head.grads[0], reps=3, use_cache=False)
+    else:
+        sched = tuple(int(x) for x in args.schedule.split(","))
+        head.renderers[0].set_schedule(*sched)
+    log(f"[bench] schedule waves_per_block={sched[0]} tile_order={sched[1]}")
     ev = HipEvents(args.steps * cgs.STAGE_EVENTS)
     log(f"[bench] timing {args.workload} batched: {args.steps} steps after {args.warmup} warmup")
     ms = head.time(args.steps, args.warmup, ev)
@@ -329,7 +338,7 @@ def main():
     if "fp32_plain" in extras:
         log(f"[bench] timing {args.workload} plain fp32")
         wl32 = sc.make_workload(args.workload, bf16=False)
-        f = Form(wl32, batched=False)
+        f = Form(wl32, batched=False, waves_per_block=sched[0], tile_order=sched[1])
         forms[f"fp32_plain:{args.workload}"] = wl32.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
         if wl.bf16:
             head.step()
@@ -340,7 +349,7 @@ def main():
     if "uncompressed" in extras:
         log(f"[bench] timing {args.workload} uncompressed (K = N)")
         wu = uncompressed_workload(wl)
-        f = Form(wu, batched=True)
+        f = Form(wu, batched=True, waves_per_block=sched[0], tile_order=sched[1])
         ms_u = f.time(nsteps, 2)
         forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_uncompressed:{args.workload}"] = wl.n_pixels / (ms_u * 1e-3) / 1e6
         extra_info["codebook_speedup_vs_uncompressed"] = ms_u / ms
@@ -353,7 +362,7 @@ def main():
         for bf in (True, False):
             log(f"[bench] timing {name} {'bf16 batched' if bf else 'fp32 plain'}")
             w1 = sc.make_workload(name, bf16=bf)
-            f = Form(w1, batched=bf)
+            f = Form(w1, batched=bf, waves_per_block=sched[0], tile_order=sched[1])
             forms[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = \
                 w1.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
             del f
@@ -363,7 +372,7 @@ def main():
         for bf, batched in ((True, True), (False, False)):
             log(f"[bench] timing {name} {'bf16 batched' if batched else 'fp32 plain (16 calls)'}")
             w5 = sc.make_workload(name, bf16=bf)
-            f = Form(w5, batched=batched)
+            f = Form(w5, batched=batched, waves_per_block=sched[0], tile_order=sched[1])
             ms5 = time_graph(f, nsteps) if batched else f.time(nsteps, 2)
             forms[f"{'bf16_batched_graph' if batched else 'fp32_plain'}:{name}"] = w5.n_pixels / (ms5 * 1e-3) / 1e6
             del f
@@ -390,7 +399,7 @@ def main():
                               "frac": sb["total"] / HBM_PEAK / (ms * 1e-3)},
         "extra": extra_info,
         "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst},
-        "schedule": {"waves_per_block": args.waves_per_block, "tile_order": args.tile_order},
+        "schedule": {"waves_per_block": sched[0], "tile_order": sched[1], "candidates_ms": tuned},
     }
     print(json.dumps(out), flush=True)
 

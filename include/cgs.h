@@ -117,11 +117,14 @@ typedef struct {
  *   records 4 just before the backward blend, 5 after it, 6 after the
  *   per-Gaussian chain rule, 7 after the codebook reduction.  All on `stream`.
  * n_blend: device int32 [P] or NULL; when set the forward also writes the
- *   number of Gaussians blended into each pixel (a slower instrumented blend). */
+ *   number of Gaussians blended into each pixel (a slower instrumented blend).
+ * The schedule changes only the order work is issued in, never a result; the
+ * backward must be given the same tile_order as the forward whose workspace it
+ * reads (order 2 reuses the tile permutation the forward left there). */
 enum { CGS_STAGE_EVENTS = 8 };
 typedef struct {
     int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup: 1 (default), 2 or 4 */
-    int32_t tile_order;              /* 0: row-major tiles, 1: XCD-grouped order */
+    int32_t tile_order;              /* 0: row-major tiles, 1: XCD-grouped, 2: heaviest tile lists first */
     int32_t reserved[2];
     void** stage_events;
     int32_t* n_blend;

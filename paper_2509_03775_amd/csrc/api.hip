@@ -57,6 +57,7 @@ struct Host {
     int inst_buf;          // buffer pair holding the tile-sorted instances
     int dsort_buf;         // buffer pair holding the depth-sorted records
     int tile_bits;
+    int tperm_buf;         // buffer pair holding the heavy-first tile order
     bool fused;            // every scene uses the single-codebook layout
     hipEvent_t* events;    // optional stage events
     int32_t* n_blend;      // optional per-pixel blended count
@@ -183,10 +184,12 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     h->wpb = (sch && (sch->blend_waves_per_block == 2 || sch->blend_waves_per_block == 4)) ? sch->blend_waves_per_block
                                                                                             : 1;
     d.tile_order = sch ? sch->tile_order : 0;
+    if (d.tile_order < 0 || d.tile_order > 2) return CGS_EINVAL;
     h->events = sch ? reinterpret_cast<hipEvent_t*>(sch->stage_events) : nullptr;
     h->n_blend = sch ? sch->n_blend : nullptr;
     h->tile_bits = bits_for(d.n_tiles);
     h->inst_buf = (passes_for(h->tile_bits) - 1) & 1;
+    h->tperm_buf = (passes_for(16) - 1) & 1;
     h->dsort_buf = (passes_for(31) - 1) & 1;
 
     // workspace plan
@@ -208,6 +211,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.cnt_d = take(4 * (size_t)R);
     for (int i = 0; i < 2; ++i) { p.inst_key[i] = take(4 * (size_t)cap); p.inst_val[i] = take(4 * (size_t)cap); }
     p.tile_range = take(8 * (size_t)T);
+    for (int i = 0; i < 2; ++i) { p.tperm_key[i] = take(4 * (size_t)T); p.tperm_val[i] = take(4 * (size_t)T); }
     const int64_t nmax = std::max(std::max(R, cap), G);
     p.radix_blocks_max = (nmax + kSortTile - 1) / kSortTile;
     p.radix_counts = take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(p.radix_blocks_max, 1));
@@ -304,6 +308,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
     uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
     CGS_TRY(mark(h, 0, st));
+    h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, at<float4>(ws, p.rec_geom),
                               at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), at<uint32_t>(ws, p.depth_key),
@@ -331,6 +336,14 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(e);
     if (ib != h.inst_buf) return CGS_EHIP;
     CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
+    if (h.d.tile_order == 2) {
+        uint32_t* tk[2] = {at<uint32_t>(ws, p.tperm_key[0]), at<uint32_t>(ws, p.tperm_key[1])};
+        uint32_t* tv[2] = {at<uint32_t>(ws, p.tperm_val[0]), at<uint32_t>(ws, p.tperm_val[1])};
+        CGS_TRY(tile_len_keys(at<uint32_t>(ws, p.tile_range), h.d.n_tiles, tk[1], st));
+        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, 16, counts, bsum, st, &e);
+        CGS_TRY(e);
+        if (tb != h.tperm_buf) return CGS_EHIP;
+    }
     CGS_TRY(mark(h, 2, st));
     CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
                              at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), image,
@@ -378,6 +391,7 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
     unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
     uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
     DevCounters* cnt = at<DevCounters>(ws, p.counters);
+    h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(mark(h, 4, st));
     float* ginst = at<float>(ws, p.ginst);

@@ -55,6 +55,7 @@ struct BatchDesc {
     int32_t tile_order;
     int32_t vec_rows;       // every codebook row is 16-byte aligned: vector loads allowed
     int32_t pad_;
+    const uint32_t* tile_perm;   // tile order 2: tiles by descending list length
     int64_t n_rec, n_gauss, n_tiles, n_pix, capacity;
     int64_t sr_rows_total, sh_rows_total;
     int32_t view_list[CGS_MAX_VIEWS];   // views grouped by scene
@@ -76,7 +77,7 @@ struct WsPlan {
     size_t dsort_key[2], dsort_val[2];
     size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
-    size_t tile_range;
+    size_t tile_range, tperm_key[2], tperm_val[2];
     size_t radix_counts, scan_bsum;
     size_t slot_off, ginst, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
@@ -203,6 +204,8 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
                      const unsigned long long* n_dev, int nbits, uint32_t* counts, unsigned long long* bsum,
                      hipStream_t st, hipError_t* err);
+
+hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key, hipStream_t st);
 
 hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                        int64_t n_tiles, uint32_t* ranges, hipStream_t st);

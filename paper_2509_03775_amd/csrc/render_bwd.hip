@@ -40,7 +40,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ uint32_t s_p[WPB][64];
     __shared__ float s_o[WPB][64][4][9];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t tile = tile_of_block(desc, blockIdx.x, gridDim.x) * WPB + w;
+    const int64_t tile = tile_index(desc, blockIdx.x, gridDim.x, w, WPB);
     if (tile >= desc->n_tiles) return;
     const int v = find_view_by_tile(desc, tile);
     const ViewDesc& vd = desc->views[v];

@@ -401,16 +401,23 @@ __device__ inline uint32_t quadrant_mask(const float4& g, const float4& c, float
     return m;
 }
 
-// Map a workgroup index to the tile group it shades.  Order 1 groups
+// The tile a wavefront shades.  Order 0: row-major.  Order 1 groups
 // consecutive tiles on one XCD: the dispatcher deals workgroups to the 8 XCDs
-// round-robin, so workgroup b runs on XCD b % 8; we hand XCD x a contiguous
-// range of tile groups so neighbouring tiles (which share Gaussians) hit the
-// same L2.
-__device__ inline int64_t tile_of_block(const BatchDesc* d, int64_t b, int64_t nb) {
-    if (d->tile_order != 1) return b;
-    const int64_t q = nb / 8, rm = nb % 8;
-    const int64_t x = b % 8, k = b / 8;
-    return x * q + (x < rm ? x : rm) + k;
+// round-robin, so workgroup b runs on XCD b % 8; XCD x gets a contiguous range
+// of tile groups so neighbouring tiles (which share Gaussians) hit the same
+// L2.  Order 2: heaviest tiles first (tiles sorted by descending list length),
+// so the longest lists start early and do not form the tail of the launch.
+__device__ inline int64_t tile_index(const BatchDesc* d, int64_t b, int64_t nb, int w, int wpb) {
+    if (d->tile_order == 2) {
+        const int64_t i = b * wpb + w;
+        return i < d->n_tiles ? (int64_t)d->tile_perm[i] : d->n_tiles;
+    }
+    if (d->tile_order == 1) {
+        const int64_t q = nb / 8, rm = nb % 8;
+        const int64_t x = b % 8, k = b / 8;
+        b = x * q + (x < rm ? x : rm) + k;
+    }
+    return b * wpb + w;
 }
 
 }  // namespace cgs

@@ -312,6 +312,21 @@ __global__ void k_tile_ranges(const uint32_t* sorted, const unsigned long long* 
     ranges[2 * t + 1] = (uint32_t)lower((uint64_t)t + 1);
 }
 
+// Sort key of each tile for the heavy-first order: 0xffff - min(length, 0xffff).
+__global__ void k_tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    key[t] = 0xffffu - (len < 0xffffu ? len : 0xffffu);
+}
+
+hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_len_keys, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st, ranges, n_tiles,
+                       key);
+    return hipGetLastError();
+}
+
 hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                        int64_t n_tiles, uint32_t* ranges, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;

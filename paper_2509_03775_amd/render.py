@@ -187,6 +187,16 @@ class Renderer:
         self._grads = (cgs.SceneGrads * ns)(*gr)
         self.set_capacity(capacity)
 
+    def set_schedule(self, waves_per_block: int, tile_order: int) -> None:
+        """Change the blend launch schedule (issue order only; results are
+        bitwise unchanged)."""
+        self._sched.blend_waves_per_block = int(waves_per_block)
+        self._sched.tile_order = int(tile_order)
+
+    @property
+    def schedule(self):
+        return int(self._sched.blend_waves_per_block or 1), int(self._sched.tile_order)
+
     def set_capacity(self, capacity: int) -> None:
         self.capacity = int(capacity)
         self.batch.instance_capacity = self.capacity

@@ -146,6 +146,29 @@ def test_determinism():
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("kind", ["scenes3", "views3"])
+def test_schedule_invariance(kind):
+    """Waves per workgroup and tile order change only the issue order: every
+    output (image, T, n_last, every gradient) is bitwise the same."""
+    wl = small_workload(kind)
+    g = torch.from_numpy(np.random.default_rng(6).standard_normal((sum(c.width * c.height for c in wl.cameras), 3))
+                         .astype(np.float32) * 1e-5).cuda()
+    ref = None
+    for wpb, order in ((1, 0), (2, 1), (4, 2), (1, 2), (2, 2)):
+        say(f"[schedule] {kind} waves_per_block={wpb} tile_order={order}")
+        r = gpu_renderer(wl, waves_per_block=wpb, tile_order=order)
+        r.forward()
+        _, gcb = r.backward(g)
+        torch.cuda.synchronize()
+        out = [r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()]
+        out += [x.cpu().numpy() for x in gcb] + [x.cpu().numpy() for x in r.grad_means]
+        if ref is None:
+            ref = out
+            continue
+        for a, b in zip(ref, out):
+            np.testing.assert_array_equal(a, b)
+
+
 def _bin_inputs(seed, n, tx, ty, V, ties=True):
     rng = np.random.default_rng(seed)
     if ties:
