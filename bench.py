@@ -139,19 +139,34 @@ def stage_times(ev: HipEvents, steps):
     return out
 
 
+def walked_instances(r: render.Renderer) -> int:
+    """Instances the blends must read: per tile, list positions up to the
+    largest n_last of its pixels (front-to-back termination)."""
+    total = 0
+    for v, cam in enumerate(r.cameras):
+        nl = r.n_last[int(r.pix_off[v]):int(r.pix_off[v + 1])].view(cam.height, cam.width).to(torch.float32)
+        th, tw = (cam.height + 15) // 16, (cam.width + 15) // 16
+        pad = torch.zeros((th * 16, tw * 16), dtype=torch.float32, device=nl.device)
+        pad[:cam.height, :cam.width] = nl
+        total += int(torch.amax(pad.view(th, 16, tw, 16), dim=(1, 3)).to(torch.int64).sum().item())
+    return total
+
+
 def pair_counts(form: Form):
-    """Pairs the backward evaluates (sum of n_last) and pairs blended."""
-    e_eval = e_blend = 0
+    """Pairs the backward evaluates (sum of n_last), pairs blended and
+    instances walked."""
+    e_eval = e_blend = walked = 0
     for r in form.renderers:
         r.forward()
         e_eval += int(r.n_last.to(torch.int64).sum().item())
+        walked += walked_instances(r)
         nb = torch.zeros(r.n_pixels, dtype=torch.int32, device="cuda")
         r._sched.n_blend = nb.data_ptr()
         r.forward()
         torch.cuda.synchronize()
         r._sched.n_blend = None
         e_blend += int(nb.to(torch.int64).sum().item())
-    return e_eval, e_blend
+    return e_eval, e_blend, walked
 
 
 def cpu_baseline(wl: sc.Workload, target_s: float):
@@ -199,11 +214,15 @@ def blend_roofline(stage, ms, e_eval, e_blend):
             "ops_per_launch": ops}
 
 
-def step_bytes(wl: sc.Workload, n_inst: int) -> dict:
+def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     """Algorithmic HBM bytes of one step, per stage: what the method must
     read and write once (codebook rows counted once per unique row; radix
     passes at 20 B per item: key+value in and out plus the key histogram
-    read)."""
+    read).  The blends read only the walked instances W (positions before
+    the tile's termination): a 4 B record id plus the record's 36 B of blend
+    data each; the backward adds the record's tile rectangle and slot offset
+    (12 B) and writes a 36 B gradient slot; the chain rule reads those slots
+    back."""
     N = sum(s.n for s in wl.scenes)
     Rrec = sum(wl.scenes[int(v)].n for v in wl.view_scene)
     K = sum(s.k for s in wl.scenes)
@@ -217,10 +236,10 @@ def step_bytes(wl: sc.Workload, n_inst: int) -> dict:
     out = {
         "preprocess": N * 16 + K * RW * b + Rrec * 52,
         "binning": 4 * 20 * Rrec + Rrec * 20 + Rrec * 12 + Rrec * 16 + M * 8 + tile_passes * 20 * M + Rrec * 8,
-        "blend_fwd": M * 40 + P * 20,
+        "blend_fwd": walked * 40 + P * 20,
         "loss": P * 36,
-        "blend_bwd": M * 40 + M * 36 + P * 24,
-        "chain": N * 16 + K * RW * b + Rrec * 8 + M * 36 + N * (12 + 4 * RW),
+        "blend_bwd": walked * (40 + 12 + 36) + P * 24 + tiles * 8,
+        "chain": N * 16 + K * RW * b + Rrec * 20 + walked * 36 + tiles * 8 + N * (12 + 4 * RW),
         "codebook_reduce": N * 8 + row_passes * 20 * N + N * 4 * RW + K * 4 * RW,
     }
     out["total"] = sum(out.values())
@@ -301,7 +320,7 @@ def main():
         n = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.arange(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read + {args.copy_calibration_mib} MiB written")
         del src, dst
@@ -322,7 +341,7 @@ def main():
     ms = head.time(args.steps, args.warmup, ev)
     stages = stage_times(ev, args.steps)
     value = wl.n_pixels / (ms * 1e-3) / 1e6
-    e_eval, e_blend = pair_counts(head)
+    e_eval, e_blend, walked = pair_counts(head)
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
     roof = blend_roofline(dom, stages[dom], e_eval, e_blend)
     forms = {f"{'bf16' if wl.bf16 else 'fp32'}_batched:{args.workload}": value}
@@ -382,7 +401,7 @@ def main():
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(wl, args.cpu_seconds)
     cam = wl.cameras[0]
-    sb = step_bytes(wl, n_inst)
+    sb = step_bytes(wl, n_inst, walked)
     out = {
         "metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -398,7 +417,7 @@ def main():
         "hbm_roofline_step": {"algorithmic_bytes": sb["total"], "bytes_by_stage": sb,
                               "frac": sb["total"] / HBM_PEAK / (ms * 1e-3)},
         "extra": extra_info,
-        "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst},
+        "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst, "walked_instances": walked},
         "schedule": {"waves_per_block": sched[0], "tile_order": sched[1], "candidates_ms": tuned},
     }
     print(json.dumps(out), flush=True)

@@ -221,14 +221,15 @@ cgs_status cgs_loss_l1(const float* image, const float* target, int64_t n, float
 /* Offsets (bytes from the workspace base) of the forward's intermediate
  * arrays for a batch, for inspection and tests.  Any pointer may be NULL.
  * records: R = sum over views of the view's scene size, record r of view v is
- *   Gaussian r - rec_off(v) of that scene; rec_geom float4 [R] (u, v, -A/2,
- *   -B) and rec_col float4 [R] (-C/2, opacity, r, g), rec_blue float [R]
- *   (A, B, C the conic, inverse of Sigma2D); depth_key uint32 [R] (0x7f800000
- *   when culled); tile_rect uint32[R][2] ((x0 | y0 << 16), (x1 | y1 << 16));
+ *   Gaussian r - rec_off(v) of that scene; records float4 [R][4], 64 B each:
+ *   (u, v, -A/2 L, -B L), (-C/2 L, opacity, red, green), (blue, tile_rect[0]
+ *   bits, tile_rect[1] bits, 0), padding -- A, B, C the conic (inverse of
+ *   Sigma2D), L = log2(e); depth_key uint32 [R] (0x7f800000 when culled);
+ *   tile_rect uint32[R][2] ((x0 | y0 << 16), (x1 | y1 << 16));
  * inst_rec uint32 [capacity] record of each sorted instance; tile_range
  *   uint32 [tiles][2]. */
 typedef struct {
-    size_t rec_geom, rec_col, rec_blue, depth_key, tile_rect, inst_rec, tile_range;
+    size_t records, depth_key, tile_rect, inst_rec, tile_range;
     int64_t n_records, n_tiles;
 } cgs_ws_layout;
 cgs_status cgs_workspace_layout(const cgs_batch* batch, cgs_ws_layout* out);

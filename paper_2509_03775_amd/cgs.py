@@ -58,7 +58,7 @@ class Batch(ctypes.Structure):
 
 
 class WsLayout(ctypes.Structure):
-    _fields_ = [("rec_geom", c_size_t), ("rec_col", c_size_t), ("rec_blue", c_size_t),
+    _fields_ = [("records", c_size_t),
                 ("depth_key", c_size_t), ("tile_rect", c_size_t), ("inst_rec", c_size_t),
                 ("tile_range", c_size_t), ("n_records", c_int64), ("n_tiles", c_int64)]
 

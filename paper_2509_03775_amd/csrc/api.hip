@@ -12,8 +12,8 @@
 namespace cgs {
 
 // launchers defined in the other translation units
-hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, float4*, float*, uint32_t*, uint2*,
-                             uint32_t*, hipStream_t);
+hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*,
+                             hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_gather_depth(int64_t, const uint32_t*, const uint2*, uint2*, uint32_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
@@ -24,12 +24,12 @@ hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, c
 hipError_t launch_plain_keys(const uint32_t*, const uint32_t*, const uint32_t*, const DevCounters*, int64_t,
                              uint64_t*, uint32_t*, hipStream_t);
 hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            const float4*, const float*, float*, float*, int32_t*, int32_t*, hipStream_t);
+                            float*, float*, int32_t*, int32_t*, hipStream_t);
 hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            const float4*, const float*, const uint2*, const uint32_t*, const float*, const float*,
-                            const int32_t*, float*, hipStream_t);
+                            const uint32_t*, const uint32_t*, const float*, const float*, const int32_t*, float*,
+                            uint2*, hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const uint32_t*, const uint32_t*,
-                        const DevCounters*, float*, hipStream_t);
+                        const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
@@ -199,9 +199,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
     p.desc = take(sizeof(BatchDesc));
     p.counters = take(sizeof(DevCounters));
-    p.rec_geom = take(16 * (size_t)R);
-    p.rec_col = take(16 * (size_t)R);
-    p.rec_blue = take(4 * (size_t)R);
+    p.rec = take(16 * kRecF4 * (size_t)R);
     p.depth_key = take(4 * (size_t)R);
     p.tile_rect = take(8 * (size_t)R);
     p.ntiles = take(4 * (size_t)R);
@@ -211,6 +209,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.cnt_d = take(4 * (size_t)R);
     for (int i = 0; i < 2; ++i) { p.inst_key[i] = take(4 * (size_t)cap); p.inst_val[i] = take(4 * (size_t)cap); }
     p.tile_range = take(8 * (size_t)T);
+    p.tile_cut = take(8 * (size_t)T);
     for (int i = 0; i < 2; ++i) { p.tperm_key[i] = take(4 * (size_t)T); p.tperm_val[i] = take(4 * (size_t)T); }
     const int64_t nmax = std::max(std::max(R, cap), G);
     p.radix_blocks_max = (nmax + kSortTile - 1) / kSortTile;
@@ -281,9 +280,7 @@ cgs_status cgs_workspace_layout(const cgs_batch* batch, cgs_ws_layout* out) {
     cgs_status s = plan_batch(batch, &h);
     if (s != CGS_OK) return s;
     if (!out) return CGS_EINVAL;
-    out->rec_geom = h.p.rec_geom;
-    out->rec_col = h.p.rec_col;
-    out->rec_blue = h.p.rec_blue;
+    out->records = h.p.rec;
     out->depth_key = h.p.depth_key;
     out->tile_rect = h.p.tile_rect;
     out->inst_rec = h.p.inst_val[h.inst_buf];
@@ -310,8 +307,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(mark(h, 0, st));
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
-    CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, at<float4>(ws, p.rec_geom),
-                              at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), at<uint32_t>(ws, p.depth_key),
+    CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), st));
     CGS_TRY(mark(h, 1, st));
     // depth order of every record (stable: ties keep record order)
@@ -346,8 +342,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     }
     CGS_TRY(mark(h, 2, st));
     CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
-                             at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue), image,
-                             T_final, n_last, h.n_blend, st));
+                             at<float4>(ws, p.rec), image, T_final, n_last, h.n_blend, st));
     CGS_TRY(mark(h, 3, st));
     return CGS_OK;
 }
@@ -396,13 +391,13 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
     CGS_TRY(mark(h, 4, st));
     float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
-                             at<float4>(ws, p.rec_geom), at<float4>(ws, p.rec_col), at<float>(ws, p.rec_blue),
-                             at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.slot_off), grad_image, T_final, n_last,
-                             ginst, st));
+                             at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key), at<uint32_t>(ws, p.slot_off),
+                             grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
     CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, ginst, at<uint32_t>(ws, p.slot_off),
-                         at<uint32_t>(ws, p.ntiles), cnt, gth, st));
+                         at<uint32_t>(ws, p.ntiles), at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key),
+                         at<uint2>(ws, p.tile_cut), cnt, gth, st));
     CGS_TRY(mark(h, 6, st));
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
     uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};

@@ -19,6 +19,11 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kReduceChunk = 64;        // sorted positions owned by one reduction wavefront
 constexpr int kMaxRowWidth = 8 + 48;    // ls3 q4 logit1 + degree-3 SH
 constexpr uint32_t kCulledKey = 0x7f800000u;   // +inf bits: sorts after every depth
+// One blend record per (view, Gaussian): 64 B, i.e. four float4 at rec[4r]:
+//   [0] (u, v, -A/2 log2e, -B log2e)   [1] (-C/2 log2e, opacity, red, green)
+//   [2] (blue, tile rect lo, tile rect hi, 0)   [3] unused padding
+// so the blends' gather of a record is one 64-byte segment.
+constexpr int kRecF4 = 4;
 
 // ---------------------------------------------------------------- descriptors
 struct ViewDesc {
@@ -73,11 +78,11 @@ struct DevCounters {
 // ---------------------------------------------------------- workspace plan
 struct WsPlan {
     size_t desc, counters;
-    size_t rec_geom, rec_col, rec_blue, depth_key, tile_rect, ntiles;
+    size_t rec, depth_key, tile_rect, ntiles;
     size_t dsort_key[2], dsort_val[2];
     size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
-    size_t tile_range, tperm_key[2], tperm_val[2];
+    size_t tile_range, tile_cut, tperm_key[2], tperm_val[2];
     size_t radix_counts, scan_bsum;
     size_t slot_off, ginst, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;

@@ -20,20 +20,19 @@ namespace cgs {
 // record's rectangle -- with plain
 // stores: no atomics, and the per-record sum over its tiles is taken later in
 // a fixed order, so the backward is deterministic.  Instances the walk never
-// reaches (beyond every pixel's n_last) get zeros.
+// reaches (beyond every pixel's n_last) are not touched: the tile's cut,
+// written here, tells the chain-rule kernel which slots hold values.
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
-                                                         const float4* __restrict__ rec_geom,
-                                                         const float4* __restrict__ rec_col,
-                                                         const float* __restrict__ rec_blue,
-                                                         const uint2* __restrict__ tile_rect,
+                                                         const float4* __restrict__ rec,
+                                                         const uint32_t* __restrict__ depth_key,
                                                          const uint32_t* __restrict__ slot_off,
                                                          const float* __restrict__ grad_image,
                                                          const float* __restrict__ T_final,
                                                          const int32_t* __restrict__ n_last,
-                                                         float* __restrict__ ginst) {
+                                                         float* __restrict__ ginst, uint2* __restrict__ tile_cut) {
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
@@ -75,11 +74,18 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     const uint32_t start = ranges[2 * tile];
     const uint32_t len = ranges[2 * tile + 1] - start;
     if (maxlast > len) maxlast = len;     // n_last inconsistent with this binning: stay in the list
-    auto slot_of = [&](uint32_t r) -> int64_t {
-        const uint2 tr = tile_rect[r];
-        const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rx1 = (int)(tr.y & 0xffffu);
-        return (int64_t)slot_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
-    };
+    // The walk covers list positions [0, maxlast).  Lists are ordered by
+    // (depth key, record), so the first position it does not reach is named
+    // by that pair; the chain-rule kernel reads only slots ordered before it
+    // and the slots beyond are never written.
+    if (lane == 0) {
+        uint2 cut = make_uint2(0xffffffffu, 0xffffffffu);
+        if (maxlast < len) {
+            const uint32_t c = inst_rec[start + maxlast];
+            cut = make_uint2(depth_key[c], c);
+        }
+        tile_cut[tile] = cut;
+    }
     const int row = lane >> 4;
     const bool row_end = (lane & 15) == 15;
     for (int64_t bend = maxlast; bend > 0; bend -= 64) {
@@ -91,10 +97,13 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         float bl = 0.f;
         if (li < bend) {
             const uint32_t r = inst_rec[start + li];
-            g = rec_geom[r];
-            c = rec_col[r];
-            bl = rec_blue[r];
-            slot = slot_of(r);
+            g = rec[kRecF4 * (int64_t)r + 0];
+            c = rec[kRecF4 * (int64_t)r + 1];
+            const float4 x = rec[kRecF4 * (int64_t)r + 2];
+            bl = x.x;
+            const uint32_t rlo = __float_as_uint(x.y), rhi = __float_as_uint(x.z);
+            const int rx0 = (int)(rlo & 0xffffu), ry0 = (int)(rlo >> 16), rx1 = (int)(rhi & 0xffffu);
+            slot = (int64_t)slot_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
             qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
         }
         const uint64_t km = __ballot(qm != 0u);
@@ -191,15 +200,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         }
         wave_sync();
     }
-    // list positions no pixel of this tile reached: zero gradient
-    for (uint32_t li = maxlast + (uint32_t)lane; li < len; li += 64) {
-        float* dst = ginst + 9 * slot_of(inst_rec[start + li]);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) dst[k] = 0.f;
-    }
 }
 
 // ------------------------------------------------------------ chain rule
+__device__ const float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
 // One thread per Gaussian: recompute the projection of every view of its
 // scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
 // the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
@@ -207,6 +212,9 @@ template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
                                                const uint32_t* __restrict__ slot_off,
                                                const uint32_t* __restrict__ ntiles,
+                                               const uint2* __restrict__ tile_rect,
+                                               const uint32_t* __restrict__ depth_key,
+                                               const uint2* __restrict__ tile_cut,
                                                const DevCounters* __restrict__ cnt, float* __restrict__ gtheta) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -240,15 +248,43 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         const int v = desc->view_list[sd.vfirst + vi];
         const ViewDesc& vd = desc->views[v];
         const int64_t r = vd.rec_off + g;
-        // dL/d(record) = sum over the record's tile slots, in row-major tile order
-        // (slots of consecutive Gaussians are adjacent: coalesced reads)
+        // dL/d(record) = sum over the record's tile slots, in row-major tile
+        // order (slots of consecutive Gaussians are adjacent: coalesced
+        // reads), over the tiles whose backward walk reached the record:
+        // (depth key, record) ordered before the tile's cut
         const uint32_t nt = binned ? ntiles[r] : 0u;
         if (nt == 0u) continue;
         float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const float* gi = ginst + 9 * (int64_t)slot_off[r];
-        for (uint32_t e = 0; e < nt; ++e)
+        const uint2 tr = tile_rect[r];
+        const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rw = (int)(tr.y & 0xffffu) - rx0;
+        const uint32_t key = depth_key[r];
+        const uint2* cut = tile_cut + vd.tile_off + (int64_t)ry0 * vd.tiles_x + rx0;
+        int ex = 0;
+        int64_t erow = 0;
+        // four slots at a time: their cuts, then their values, are loaded
+        // together (a slot not reached reads zeros from kZeroSlot)
+        for (uint32_t e0 = 0; e0 < nt; e0 += 4) {
+            uint2 c[4];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] += gi[9 * e + i];
+            for (int j = 0; j < 4; ++j) {
+                c[j] = make_uint2(0u, 0u);
+                if (e0 + j < nt) {
+                    c[j] = cut[erow + ex];
+                    if (++ex == rw) { ex = 0; erow += vd.tiles_x; }
+                }
+            }
+            const float* src[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool reached = e0 + j < nt && (key < c[j].x || (key == c[j].x && (uint32_t)r < c[j].y));
+                src[j] = reached ? gi + 9 * (e0 + j) : kZeroSlot;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) d[i] += src[j][i];
+        }
         bool nz = false;
 #pragma unroll
         for (int i = 0; i < 9; ++i) nz |= d[i] != 0.f;
@@ -567,29 +603,29 @@ __global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
-                            const uint32_t* inst_rec, const float4* rg, const float4* rc, const float* rb,
-                            const uint2* tr, const uint32_t* eo, const float* grad_image, const float* T_final,
-                            const int32_t* n_last, float* ginst, hipStream_t st) {
+                            const uint32_t* inst_rec, const float4* rec, const uint32_t* dk, const uint32_t* eo,
+                            const float* grad_image, const float* T_final, const int32_t* n_last, float* ginst,
+                            uint2* cut, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (wpb == 1) {
-        hipLaunchKernelGGL(k_blend_bwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rg, rc,
-                           rb, tr, eo, grad_image, T_final, n_last, ginst);
+        hipLaunchKernelGGL(k_blend_bwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rec,
+                           dk, eo, grad_image, T_final, n_last, ginst, cut);
     } else if (wpb == 2) {
         hipLaunchKernelGGL(k_blend_bwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
-                           inst_rec, rg, rc, rb, tr, eo, grad_image, T_final, n_last, ginst);
+                           inst_rec, rec, dk, eo, grad_image, T_final, n_last, ginst, cut);
     } else {
         hipLaunchKernelGGL(k_blend_bwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
-                           inst_rec, rg, rc, rb, tr, eo, grad_image, T_final, n_last, ginst);
+                           inst_rec, rec, dk, eo, grad_image, T_final, n_last, ginst, cut);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, const float* ginst,
-                        const uint32_t* eo, const uint32_t* nt, const DevCounters* cnt, float* gtheta,
-                        hipStream_t st) {
+                        const uint32_t* eo, const uint32_t* nt, const uint2* tr, const uint32_t* dk, const uint2* cut,
+                        const DevCounters* cnt, float* gtheta, hipStream_t st) {
     if (n_gauss <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
-#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, ginst, eo, nt, cnt, gtheta)
+#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, ginst, eo, nt, tr, dk, cut, cnt, gtheta)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_CH(CGS_F32, 0); break; case 1: CGS_CH(CGS_F32, 1); break;
                        case 2: CGS_CH(CGS_F32, 2); break; default: CGS_CH(CGS_F32, 3); break; }

@@ -10,8 +10,7 @@ namespace cgs {
 // ---------------------------------------------------------------- preprocess
 template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict__ desc,
-                                                    float4* __restrict__ rec_geom, float4* __restrict__ rec_col,
-                                                    float* __restrict__ rec_blue, uint32_t* __restrict__ depth_key,
+                                                    float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,9 +35,10 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
             depth_key[r] = kCulledKey;
             tile_rect[r] = make_uint2(0u, 0u);
             ntiles[r] = 0u;
-            rec_geom[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec_col[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec_blue[r] = 0.f;
+            rec[kRecF4 * r + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[kRecF4 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[kRecF4 * r + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[kRecF4 * r + 3] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
         float A, B, C;
@@ -46,11 +46,14 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         float col[3];
         sh_colour<SHD>(vd, gp, col, nullptr);
         depth_key[r] = __float_as_uint(vp.zc);
-        tile_rect[r] = make_uint2((uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16), (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16));
+        const uint32_t rlo = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16);
+        const uint32_t rhi = (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16);
+        tile_rect[r] = make_uint2(rlo, rhi);
         ntiles[r] = (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0));
-        rec_geom[r] = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
-        rec_col[r] = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
-        rec_blue[r] = col[2];
+        rec[kRecF4 * r + 0] = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
+        rec[kRecF4 * r + 1] = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
+        rec[kRecF4 * r + 2] = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), 0.f);
+        rec[kRecF4 * r + 3] = make_float4(0.f, 0.f, 0.f, 0.f);   // whole 64-byte lines are written
         (void)NCO;
     }
 }
@@ -192,9 +195,7 @@ template <int WPB, bool STATS>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
-                                                         const float4* __restrict__ rec_geom,
-                                                         const float4* __restrict__ rec_col,
-                                                         const float* __restrict__ rec_blue,
+                                                         const float4* __restrict__ rec,
                                                          float* __restrict__ image, float* __restrict__ T_final,
                                                          int32_t* __restrict__ n_last, int32_t* __restrict__ n_blend) {
     __shared__ float4 s_g[WPB][64];
@@ -231,10 +232,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
         float4 g, c;
         float bl = 0.f;
         if (idx < end) {
-            const uint32_t r = inst_rec[idx];
-            g = rec_geom[r];
-            c = rec_col[r];
-            bl = rec_blue[r];
+            const int64_t r = inst_rec[idx];
+            g = rec[kRecF4 * r + 0];
+            c = rec[kRecF4 * r + 1];
+            bl = rec[kRecF4 * r + 2].x;
             qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
         }
         const uint64_t km = __ballot(qm != 0u);
@@ -293,11 +294,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, float4* rg, float4* rc,
-                             float* rb, uint32_t* dk, uint2* tr, uint32_t* nt, hipStream_t st) {
+hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, float4* rec,
+                             uint32_t* dk, uint2* tr, uint32_t* nt, hipStream_t st) {
     if (n_gauss <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
-#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rg, rc, rb, dk, tr, nt)
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
                        case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }
@@ -356,11 +357,11 @@ hipError_t launch_plain_keys(const uint32_t* stile, const uint32_t* sgid, const 
 }
 
 hipError_t launch_blend_fwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
-                            const uint32_t* inst_rec, const float4* rg, const float4* rc, const float* rb,
+                            const uint32_t* inst_rec, const float4* rec,
                             float* image, float* T_final, int32_t* n_last, int32_t* n_blend, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
 #define CGS_BF(W, S) hipLaunchKernelGGL((k_blend_fwd<W, S>), dim3((unsigned)((n_tiles + W - 1) / W)), dim3(W * 64), \
-                                        0, st, d_desc, ranges, inst_rec, rg, rc, rb, image, T_final, n_last, n_blend)
+                                        0, st, d_desc, ranges, inst_rec, rec, image, T_final, n_last, n_blend)
     if (n_blend) {
         if (wpb == 1) CGS_BF(1, true); else if (wpb == 2) CGS_BF(2, true); else CGS_BF(4, true);
     } else {

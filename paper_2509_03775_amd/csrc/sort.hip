@@ -126,11 +126,17 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_down(const uint32_t* in, co
     __shared__ uint32_t s_wave[kSortBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     uint32_t carry = (uint32_t)bsum[blockIdx.x];
+    uint32_t v[kSortItems];      // all loads issued before the first barrier
+#pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        int64_t j = base + (int64_t)i * kSortBlock + threadIdx.x;
-        uint32_t v = j < n ? scan_load(in, perm, j) : 0u;
+        const int64_t j = base + (int64_t)i * kSortBlock + threadIdx.x;
+        v[i] = j < n ? scan_load(in, perm, j) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t j = base + (int64_t)i * kSortBlock + threadIdx.x;
         uint32_t tot;
-        uint32_t ex = block_excl_scan(v, s_wave, &tot);
+        const uint32_t ex = block_excl_scan(v[i], s_wave, &tot);
         if (j < n) out[j] = carry + ex;
         carry += tot;
     }
@@ -156,12 +162,15 @@ __device__ inline int64_t live_count(int64_t n_max, const unsigned long long* n_
     return (int64_t)v < n_max ? (int64_t)v : n_max;
 }
 
-// Mask of active lanes whose digit equals this lane's.
-__device__ inline uint64_t match_digit(uint32_t d, int nbits) {
+// Mask of active lanes whose digit (< 2^kRadixBits) equals this lane's:
+// one ballot per digit bit (bits above a narrower pass's width are zero and
+// match trivially).
+__device__ inline uint64_t match_digit(uint32_t d) {
     uint64_t peers = __ballot(1);
-    for (int b = 0; b < nbits; ++b) {
-        uint32_t bit = (d >> b) & 1u;
-        uint64_t bal = __ballot(bit);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const uint32_t bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
         peers &= bit ? bal : ~bal;
     }
     return peers;
@@ -178,11 +187,18 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t* keys,
     const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / 4);
     const uint32_t mask = (1u << nbits) - 1u;
     if ((int64_t)blockIdx.x * kSortTile < n) {
+        uint32_t k_[kSortItems];     // all loads issued before the first LDS update
+#pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
-            int64_t j = base + i * 64 + lane;
+            const int64_t j = base + i * 64 + lane;
+            k_[i] = j < n ? keys[j] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const int64_t j = base + i * 64 + lane;
             if (j < n) {
-                uint32_t d = (keys[j] >> shift) & mask;
-                uint64_t peers = match_digit(d, nbits);
+                const uint32_t d = (k_[i] >> shift) & mask;
+                const uint64_t peers = match_digit(d);
                 if (popc_below(peers) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
             }
         }
@@ -216,16 +232,21 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint32_t* ke
     const uint32_t mask = (1u << nbits) - 1u;
     uint32_t k_[kSortItems], v_[kSortItems];
     uint32_t rank[kSortItems];
+    // all loads issued before the first LDS update
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const int64_t j = base + i * 64 + lane;
+        k_[i] = j < n ? keys_in[j] : 0u;
+        v_[i] = j < n ? (vals_in ? vals_in[j] : (uint32_t)j) : 0u;
+    }
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         int64_t j = base + i * 64 + lane;
         rank[i] = 0xffffffffu;
         if (j < n) {
-            uint32_t key = keys_in[j];
-            k_[i] = key;
-            v_[i] = vals_in ? vals_in[j] : (uint32_t)j;
+            const uint32_t key = k_[i];
             uint32_t d = (key >> shift) & mask;
-            uint64_t peers = match_digit(d, nbits);
+            uint64_t peers = match_digit(d);
             uint32_t below = popc_below(peers);
             uint32_t run = cnt[w][d];
             rank[i] = run + below;
