@@ -16,6 +16,7 @@ single GPU.
 """
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,36 @@ HBM_PEAK = 8.0e12                       # bytes/s
 # count) and 30 in the backward (T recovery 2, weight 1, colour grads 3,
 # alpha grad 7, background update 3, opacity grad 2, power grads 12).
 OPS_ALPHA, OPS_FWD_BLEND, OPS_BWD_BLEND = 11, 8, 30
+
+# HBM bytes per launch of the blend kernels on the headline workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the same counter read for a 512 MiB torch.neg copy (FETCH
+# 2.0, WRITE 1.0).  A figure holds only for the kernel sources and schedule it
+# was taken on: the first 16 hex digits of the SHA-256 of those sources.
+KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", "render_common.h", "cgs_internal.h"),
+                  "k_blend_fwd": ("render_fwd.hip", "render_common.h", "cgs_internal.h")}
+MEASURED_TRAFFIC = {
+    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "a8b46ae67f5f75d4", "read": 3241930418, "write": 729442112},
+    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "05d29d67d967991e", "read": 1542154568, "write": 217980640},
+}
+
+
+def sources_digest(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2509_03775_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, schedule) -> "int | None":
+    """Counter-measured HBM bytes per launch, or None when no figure was
+    taken for this kernel, workload and schedule or the kernel has changed
+    since."""
+    m = MEASURED_TRAFFIC.get((kernel, workload, tuple(schedule)))
+    if m is None or m["sources"] != sources_digest(kernel):
+        return None
+    return m["read"] + m["write"]
 
 
 def log(msg):
@@ -203,15 +234,16 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
                       f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}
 
 
-def blend_roofline(stage, ms, e_eval, e_blend):
+def blend_roofline(stage, ms, e_eval, e_blend, workload, schedule):
     if stage == "blend_fwd":
         ops = OPS_ALPHA * e_eval + OPS_FWD_BLEND * e_blend
     else:
         ops = OPS_ALPHA * e_eval + OPS_BWD_BLEND * e_blend
     ach = ops / (ms * 1e-3)
+    kernel = "k_blend_bwd" if stage == "blend_bwd" else "k_blend_fwd"
     return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
-            "frac": ach / VALU_PEAK, "traffic": None, "kernel": "k_blend_bwd" if stage == "blend_bwd" else "k_blend_fwd",
-            "ops_per_launch": ops}
+            "frac": ach / VALU_PEAK, "traffic": measured_traffic(kernel, workload, schedule), "kernel": kernel,
+            "ops_per_launch": ops, "launch_ms": ms}
 
 
 def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
@@ -343,7 +375,7 @@ def main():
     value = wl.n_pixels / (ms * 1e-3) / 1e6
     e_eval, e_blend, walked = pair_counts(head)
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
-    roof = blend_roofline(dom, stages[dom], e_eval, e_blend)
+    roof = blend_roofline(dom, stages[dom], e_eval, e_blend, args.workload, sched)
     forms = {f"{'bf16' if wl.bf16 else 'fp32'}_batched:{args.workload}": value}
     n_inst = head.instances
     extras = [x for x in args.extra_forms.split(",") if x and x != "none"]
