@@ -28,8 +28,8 @@ hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, const uint32_t*, con
 hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
                             const uint32_t*, const uint32_t*, const float*, const float*, const int32_t*, float*,
                             uint2*, hipStream_t);
-hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const uint32_t*, const uint32_t*,
-                        const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, hipStream_t);
+hipError_t launch_chain(const BatchDesc*, int, int, int64_t, int64_t, const float*, const uint32_t*, const uint32_t*,
+                        const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, float*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
@@ -86,7 +86,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     d.row_width = 8 + 3 * nco;
     h->opacity_mode = s0.opacity_mode;
     h->fused = true;
-    int64_t goff = 0, sroff = 0, shoff = 0;
+    int64_t goff = 0, sroff = 0, shoff = 0, gwaves = 0;
     for (int s = 0; s < b->n_scenes; ++s) {
         const cgs_scene& sc = b->scenes[s];
         if (sc.n < 0) return CGS_EINVAL;
@@ -106,6 +106,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         SceneDesc& sd = d.scenes[s];
         sd.n = sc.n;
         sd.g_off = goff;
+        sd.wave_off = gwaves;
+        gwaves += (sc.n + kWave - 1) / kWave;
         sd.sr_rows = sc.sr.rows;
         sd.sh_rows = sc.sh.rows;
         sd.sr_row_off = sroff;
@@ -129,6 +131,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         shoff += sc.sh.rows;
     }
     d.n_gauss = goff;
+    d.n_gauss_waves = gwaves;
     {   // 16-byte vector loads of whole rows: degree-3 rows, opacity in the SR row, aligned windows
         const size_t esz = d.dtype == CGS_BF16 ? 2 : 4;
         bool vec = s0.sh_degree == 3 && h->opacity_mode == 1;
@@ -145,7 +148,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     d.sh_rows_total = shoff;
     if (goff >= ((int64_t)1 << 32) || sroff >= ((int64_t)1 << 32) || shoff >= ((int64_t)1 << 32)) return CGS_EINVAL;
     h->rows_total = std::max(sroff, shoff);
-    int64_t roff = 0, toff = 0, poff = 0;
+    int64_t roff = 0, toff = 0, poff = 0, rwaves = 0;
     for (int v = 0; v < b->n_views; ++v) {
         const cgs_camera& c = b->cameras[v];
         const int s = b->view_scene[v];
@@ -161,6 +164,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         vd.tile_off = toff;
         vd.pix_off = poff;
         vd.rec_off = roff;
+        vd.rec_wave_off = rwaves;
+        rwaves += (b->scenes[s].n + kWave - 1) / kWave;
         vd.fx = c.fx; vd.fy = c.fy; vd.cx = c.cx; vd.cy = c.cy;
         memcpy(vd.Rt, c.Rt, sizeof(vd.Rt));
         memcpy(vd.campos, c.campos, sizeof(vd.campos));
@@ -170,6 +175,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         poff += (int64_t)c.width * c.height;
     }
     d.n_rec = roff;
+    d.n_rec_waves = rwaves;
     d.n_tiles = toff;
     d.n_pix = poff;
     if (roff >= ((int64_t)1 << 32) || toff >= ((int64_t)1 << 31)) return CGS_EINVAL;
@@ -218,6 +224,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
     p.slot_off = take(4 * (size_t)R);
     p.ginst = take(4 * 9 * (size_t)cap);
+    p.rec_grad = take(4 * 9 * (size_t)R);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
     p.row_start = take(8 * (size_t)(h->rows_total + 1));
@@ -307,7 +314,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(mark(h, 0, st));
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
-    CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
+    CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), st));
     CGS_TRY(mark(h, 1, st));
     // depth order of every record (stable: ties keep record order)
@@ -395,9 +402,9 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
                              grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
-    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss, ginst, at<uint32_t>(ws, p.slot_off),
+    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.slot_off),
                          at<uint32_t>(ws, p.ntiles), at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key),
-                         at<uint2>(ws, p.tile_cut), cnt, gth, st));
+                         at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), gth, st));
     CGS_TRY(mark(h, 6, st));
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
     uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};

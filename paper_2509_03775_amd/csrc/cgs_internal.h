@@ -30,6 +30,7 @@ struct ViewDesc {
     int32_t W, H, tiles_x, tiles_y;
     int32_t scene, pad0;
     int64_t tile_off, pix_off, rec_off;
+    int64_t rec_wave_off;   // wavefronts before this view when records are split view-aligned
     float fx, fy, cx, cy;
     float Rt[12];
     float campos[3];
@@ -38,6 +39,7 @@ struct ViewDesc {
 
 struct SceneDesc {
     int64_t n, g_off;
+    int64_t wave_off;       // wavefronts before this scene when Gaussians are split scene-aligned
     int64_t sr_rows, sh_rows, sr_row_off, sh_row_off;
     const float* means;
     const int32_t* idx_sr;
@@ -63,6 +65,7 @@ struct BatchDesc {
     const uint32_t* tile_perm;   // tile order 2: tiles by descending list length
     int64_t n_rec, n_gauss, n_tiles, n_pix, capacity;
     int64_t sr_rows_total, sh_rows_total;
+    int64_t n_gauss_waves, n_rec_waves;   // scene-aligned / view-aligned wavefront counts
     int32_t view_list[CGS_MAX_VIEWS];   // views grouped by scene
     ViewDesc views[CGS_MAX_VIEWS];
     SceneDesc scenes[CGS_MAX_SCENES];
@@ -84,7 +87,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, tperm_key[2], tperm_val[2];
     size_t radix_counts, scan_bsum;
-    size_t slot_off, ginst, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t slot_off, ginst, rec_grad, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t radix_blocks_max, scan_blocks_max;
 };
@@ -136,6 +139,9 @@ __device__ inline float row16_sum(float v) {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
     x = __float_as_int(v);
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    // keep the last add next to its shift (one DPP add) instead of letting it
+    // sink into the caller's lane-15 branch as a separate move and add
+    __asm__ volatile("" : "+v"(v));
     return v;
 }
 
@@ -162,6 +168,33 @@ template <int DT>
 __device__ inline float load_cb(const void* p, int64_t i) {
     if constexpr (DT == CGS_BF16) return bf16_to_f32(static_cast<const uint16_t*>(p)[i]);
     else return static_cast<const float*>(p)[i];
+}
+
+// Wavefront index within the launch, wave-uniform (scalar) by construction.
+__device__ inline int64_t wave_id(int waves_per_block) {
+    return (int64_t)blockIdx.x * waves_per_block + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// Per-Gaussian kernels give each wavefront 64 Gaussians of one scene, so
+// the scene (and its views) are wave-uniform and their descriptors are read
+// with scalar loads.  Last scene whose first wavefront is <= w.
+__device__ inline int find_scene_by_wave(const BatchDesc* d, int64_t w) {
+    int lo = 0, hi = d->n_scenes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d->scenes[mid].wave_off <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Same for per-record kernels: 64 records of one view per wavefront.
+__device__ inline int find_view_by_wave(const BatchDesc* d, int64_t w) {
+    int lo = 0, hi = d->n_views - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d->views[mid].rec_wave_off <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 __device__ inline int find_scene(const BatchDesc* d, int64_t g) {

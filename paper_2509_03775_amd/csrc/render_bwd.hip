@@ -39,7 +39,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ uint32_t s_p[WPB][64];
     __shared__ float s_o[WPB][64][4][9];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t tile = tile_index(desc, blockIdx.x, gridDim.x, w, WPB);
+    const int64_t tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
     if (tile >= desc->n_tiles) return;
     const int v = find_view_by_tile(desc, tile);
     const ViewDesc& vd = desc->views[v];
@@ -202,59 +202,30 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     }
 }
 
-// ------------------------------------------------------------ chain rule
+// ------------------------------------------------------- record gradients
+// One thread per (view, Gaussian) record: dL/d(record) = the sum of the
+// record's tile slots, in row-major tile order (slots of consecutive records
+// are adjacent: coalesced reads), over the tiles whose backward walk reached
+// the record -- (depth key, record) ordered before the tile's cut.  Written
+// as 9 floats per record; zeros when no tile reached it.
 __device__ const float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
-// One thread per Gaussian: recompute the projection of every view of its
-// scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
-// the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
-template <int DT, int SHD>
-__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
-                                               const uint32_t* __restrict__ slot_off,
-                                               const uint32_t* __restrict__ ntiles,
-                                               const uint2* __restrict__ tile_rect,
-                                               const uint32_t* __restrict__ depth_key,
-                                               const uint2* __restrict__ tile_cut,
-                                               const DevCounters* __restrict__ cnt, float* __restrict__ gtheta) {
-    constexpr int NCO = (SHD + 1) * (SHD + 1);
-    const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gg >= desc->n_gauss) return;
-    const int s = find_scene(desc, gg);
-    const SceneDesc& sd = desc->scenes[s];
-    const int64_t g = gg - sd.g_off;
-    const int RW = desc->row_width;
-
-    GaussParams gp;
-    float* out = gtheta + gg * RW;
-    if (!load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0)) {
-        for (int i = 0; i < RW; ++i) out[i] = 0.f;
-        if (sd.g_means) { sd.g_means[3 * g] = 0.f; sd.g_means[3 * g + 1] = 0.f; sd.g_means[3 * g + 2] = 0.f; }
-        if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = 0.f;
-        return;
-    }
-    GaussShape sh;
-    gaussian_shape(gp, sh);
-    const float opac = 1.0f / (1.0f + __expf(-gp.logit));
-
-    float dmu[3] = {0.f, 0.f, 0.f};
-    float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-    float dk[48];
-#pragma unroll
-    for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
-    float dop = 0.f;
-    const bool binned = cnt->n_inst_ok != 0ull;
-
-    for (int vi = 0; vi < sd.vcount; ++vi) {
-        const int v = desc->view_list[sd.vfirst + vi];
-        const ViewDesc& vd = desc->views[v];
-        const int64_t r = vd.rec_off + g;
-        // dL/d(record) = sum over the record's tile slots, in row-major tile
-        // order (slots of consecutive Gaussians are adjacent: coalesced
-        // reads), over the tiles whose backward walk reached the record:
-        // (depth key, record) ordered before the tile's cut
-        const uint32_t nt = binned ? ntiles[r] : 0u;
-        if (nt == 0u) continue;
-        float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+__global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
+                                                  const uint32_t* __restrict__ slot_off,
+                                                  const uint32_t* __restrict__ ntiles,
+                                                  const uint2* __restrict__ tile_rect,
+                                                  const uint32_t* __restrict__ depth_key,
+                                                  const uint2* __restrict__ tile_cut,
+                                                  const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad) {
+    const int64_t wv = wave_id(4);
+    if (wv >= desc->n_rec_waves) return;
+    const ViewDesc& vd = desc->views[find_view_by_wave(desc, wv)];
+    const int64_t i = (wv - vd.rec_wave_off) * kWave + (threadIdx.x & 63);
+    if (i >= desc->scenes[vd.scene].n) return;
+    const int64_t r = vd.rec_off + i;
+    float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const uint32_t nt = cnt->n_inst_ok != 0ull ? ntiles[r] : 0u;
+    if (nt != 0u) {
         const float* gi = ginst + 9 * (int64_t)slot_off[r];
         const uint2 tr = tile_rect[r];
         const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rw = (int)(tr.y & 0xffffu) - rx0;
@@ -285,6 +256,63 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
 #pragma unroll
                 for (int i = 0; i < 9; ++i) d[i] += src[j][i];
         }
+    }
+    float* out = rec_grad + 9 * r;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = d[i];
+}
+
+// ------------------------------------------------------------ chain rule
+// One thread per Gaussian: recompute the projection of every view of its
+// scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
+// the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
+template <int DT, int SHD>
+__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ rec_grad,
+                                               float* __restrict__ gtheta) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    const int64_t wv = wave_id(4);
+    if (wv >= desc->n_gauss_waves) return;
+    const SceneDesc& sd = desc->scenes[find_scene_by_wave(desc, wv)];
+    const int64_t g = (wv - sd.wave_off) * kWave + (threadIdx.x & 63);
+    if (g >= sd.n) return;
+    const int64_t gg = sd.g_off + g;
+    const int RW = desc->row_width;
+
+    GaussParams gp;
+    float* out = gtheta + gg * RW;
+    if (!load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0)) {
+        for (int i = 0; i < RW; ++i) out[i] = 0.f;
+        if (sd.g_means) { sd.g_means[3 * g] = 0.f; sd.g_means[3 * g + 1] = 0.f; sd.g_means[3 * g + 2] = 0.f; }
+        if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = 0.f;
+        return;
+    }
+    GaussShape sh;
+    gaussian_shape(gp, sh);
+    const float opac = 1.0f / (1.0f + __expf(-gp.logit));
+
+    float dmu[3] = {0.f, 0.f, 0.f};
+    float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float dk[48];
+#pragma unroll
+    for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
+    float dop = 0.f;
+    // dL/d(record) of the next view is loaded while this view's math runs
+    float dn[9];
+    auto load_rec = [&](int vi, float* out9) {
+        const int64_t r = desc->views[desc->view_list[sd.vfirst + vi]].rec_off + g;
+        const float* src = rec_grad + 9 * r;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out9[i] = src[i];
+    };
+    if (sd.vcount > 0) load_rec(0, dn);
+
+    for (int vi = 0; vi < sd.vcount; ++vi) {
+        const int v = desc->view_list[sd.vfirst + vi];
+        const ViewDesc& vd = desc->views[v];
+        float d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = dn[i];
+        if (vi + 1 < sd.vcount) load_rec(vi + 1, dn);
         bool nz = false;
 #pragma unroll
         for (int i = 0; i < 9; ++i) nz |= d[i] != 0.f;
@@ -620,12 +648,15 @@ hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, c
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, const float* ginst,
-                        const uint32_t* eo, const uint32_t* nt, const uint2* tr, const uint32_t* dk, const uint2* cut,
-                        const DevCounters* cnt, float* gtheta, hipStream_t st) {
-    if (n_gauss <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
-#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, ginst, eo, nt, tr, dk, cut, cnt, gtheta)
+hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, int64_t n_rec_waves,
+                        const float* ginst, const uint32_t* eo, const uint32_t* nt, const uint2* tr, const uint32_t* dk,
+                        const uint2* cut, const DevCounters* cnt, float* rec_grad, float* gtheta, hipStream_t st) {
+    if (n_rec_waves > 0)
+        hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
+                           nt, tr, dk, cut, cnt, rec_grad);
+    if (n_gauss_waves <= 0) return hipGetLastError();
+    dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
+#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, gtheta)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_CH(CGS_F32, 0); break; case 1: CGS_CH(CGS_F32, 1); break;
                        case 2: CGS_CH(CGS_F32, 2); break; default: CGS_CH(CGS_F32, 3); break; }

@@ -13,11 +13,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
                                                     float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
-    const int64_t gg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gg >= desc->n_gauss) return;
-    const int s = find_scene(desc, gg);
-    const SceneDesc& sd = desc->scenes[s];
-    const int64_t g = gg - sd.g_off;
+    const int64_t wv = wave_id(4);
+    if (wv >= desc->n_gauss_waves) return;
+    const SceneDesc& sd = desc->scenes[find_scene_by_wave(desc, wv)];
+    const int64_t g = (wv - sd.wave_off) * kWave + (threadIdx.x & 63);
+    if (g >= sd.n) return;
 
     GaussParams gp;
     const bool valid = load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     __shared__ float s_b[WPB][64];
     __shared__ uint32_t s_p[WPB][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t tile = tile_index(desc, blockIdx.x, gridDim.x, w, WPB);
+    const int64_t tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
     if (tile >= desc->n_tiles) return;
     const int v = find_view_by_tile(desc, tile);
     const ViewDesc& vd = desc->views[v];
@@ -294,10 +294,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss, float4* rec,
+hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, float4* rec,
                              uint32_t* dk, uint2* tr, uint32_t* nt, hipStream_t st) {
-    if (n_gauss <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n_gauss + 255) / 256)), blk(256);
+    if (n_gauss_waves <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
 #define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
