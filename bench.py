@@ -225,9 +225,14 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
         oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
         return time.perf_counter() - t0, pix.shape[0], ntiles
 
-    t1, _, _ = run(2)
-    n = int(max(2, min(512, 2 * target_s / max(t1, 1e-3))))
+    # each call projects the whole scene once (a fixed cost) and then
+    # composites its tiles; grow the tile count until one call takes about
+    # target_s, so the fixed cost is spread as it would be over a larger sample
+    n = 2
     dt, npix, ntiles = run(n)
+    while dt < 0.5 * target_s and n < 4096:
+        n = int(min(4096, max(2 * n, n * 0.9 * target_s / max(dt, 1e-3))))
+        dt, npix, ntiles = run(n)
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return {"value": npix / dt / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
