@@ -179,6 +179,70 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image,
                                const cgs_scene_grads* grads,
                                void* ws, size_t ws_bytes, int64_t* d_info, void* stream);
 
+/* SGLD step sizes and noise stream of the parameter-update transition
+ * (Sec. 2.3's SGLD rule; Sec. 4.4 and App. A.1: theta' = theta + (eps/2)
+ * grad log p + sqrt(eps) eta with log p = -L, one eps per parameter kind).
+ * eps_* >= 0 (0 leaves that kind unchanged); eta ~ N(0, 1) from the
+ * counter-based generator described at cgs_sgld_normals, keyed by `seed`,
+ * `step` selecting the stream of one training step. */
+typedef struct {
+    float eps_means, eps_opacity, eps_sr, eps_sh;
+    uint64_t seed;
+    uint32_t step;
+    uint32_t pad_;
+} cgs_sgld;
+
+/* FP32 parameters an SGLD update writes, per scene (device pointers):
+ * means [n,3]; opacity_logit [n] (opacity_mode 0, else NULL); sr: rows whose
+ * columns sr_col0 .. hold ls3 q4 (and the opacity logit when opacity_mode is
+ * 1); sh: rows whose columns sh_col0 .. hold the 3(d+1)^2 SH coefficients.
+ * They may be the scene's own FP32 arrays (updated in place); otherwise the
+ * scene's arrays the renderer reads are refreshed from the updated values
+ * (BF16 codebooks by round-to-nearest-even). */
+typedef struct {
+    float* means;
+    float* opacity_logit;
+    float* sr; int32_t sr_stride; int32_t sr_col0;
+    float* sh; int32_t sh_stride; int32_t sh_col0;
+} cgs_scene_params;
+
+/* cgs_render_backward followed by one SGLD step of every parameter, fused
+ * into the chain-rule epilogue (means, per-Gaussian opacity) and the codebook
+ * reduction epilogue (codebook rows, rows no Gaussian maps to included), so
+ * neither the gradients nor the parameters make another pass through HBM:
+ *   theta <- theta - (eps/2) dL/dtheta + sqrt(eps) eta.
+ * Gradients are still written to `grads`.  Step sizes per row-layout column:
+ * ls and q eps_sr, the logit eps_opacity, SH eps_sh.  Noise streams (see
+ * cgs_sgld_normals): Gaussian g of scene s uses counter index g, tag
+ * 0x10000 s, normals 0-2 for the mean and 3 for the per-Gaussian logit;
+ * codebook row k, row-layout column c uses index 16 k + c / 4, tag
+ * 0x10000 s + 1, normal c % 4.  The parameters must not alias the gradient
+ * buffers.  params: host array [n_scenes].  Deterministic. */
+cgs_status cgs_render_backward_sgld(const cgs_batch* batch, const float* grad_image, const float* T_final,
+                                    const int32_t* n_last, const cgs_scene_grads* grads, const cgs_sgld* sgld,
+                                    const cgs_scene_params* params, void* ws, size_t ws_bytes, int64_t* d_info,
+                                    void* stream);
+
+/* The SGLD noise generator on its own: for i < n, counter (index0 + i as
+ * 64-bit lo, hi; tag; step) under key seed (lo, hi) through Philox4x32-10
+ * (Salmon et al., SC 2011); words [n][4] (device, may be NULL) receive the raw
+ * output, z [n][4] (device) the Box-Muller normals of the pairs (w0, w1) and
+ * (w2, w3): u = ((w >> 9) + 1/2) 2^-23, z = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b). */
+cgs_status cgs_sgld_normals(int64_t n, uint64_t index0, uint32_t tag, uint32_t step, uint64_t seed, float* z,
+                            uint32_t* words, void* stream);
+
+/* Reconstruction loss of Eq. 4 over a batch of views and its gradient:
+ * L = (1 - lambda) L1 + lambda (1 - mean SSIM), both means over every pixel
+ * and channel of the batch.  SSIM (Wang et al. 2004): 11x11 Gaussian window
+ * of sigma 1.5 (normalised), C1 = 0.01^2, C2 = 0.03^2, local statistics by
+ * same-size convolution with zero padding, per channel.  image, target, grad:
+ * device [P,3] in the renderer's layout (views concatenated, row-major);
+ * hw: host int32 [n_views][2] (height, width); loss: device float[1]; grad is
+ * written.  0 <= lambda <= 1.  Workspace: cgs_loss_recon_workspace_bytes. */
+size_t cgs_loss_recon_workspace_bytes(int32_t n_views, const int32_t* hw);
+cgs_status cgs_loss_recon(const float* image, const float* target, int32_t n_views, const int32_t* hw,
+                          float lambda_ssim, float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
+
 /* Codebook gradient reduction (Sec. 2.2 / 4.1: a Gaussian's parameters are
  * its codebook row, so a row's gradient is the sum over the Gaussians mapped
  * to it): grad_cb[k, c] = sum_{i : idx[i] == k} g[i * ld + c], c < d.

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip"]
+SOURCES = ["api.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip", "train.hip"]
 LIB = os.path.join(HERE, "libcgs.so")
 ARCH = os.environ.get("CGS_OFFLOAD_ARCH", "gfx950")
 
@@ -19,7 +19,7 @@ ARCH = os.environ.get("CGS_OFFLOAD_ARCH", "gfx950")
 def hipcc_cmd(out: str, extra=()):
     return (["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", out]
+             "-Wl,-z,defs", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", out]
             + list(extra) + [os.path.join(CSRC, s) for s in SOURCES])
 
 

@@ -18,7 +18,8 @@ MAX_VIEWS = MAX_SCENES = 64
 EXPORTS = ("cgs_workspace_bytes", "cgs_render_forward", "cgs_render_backward",
            "cgs_codebook_grad_reduce_workspace_bytes", "cgs_codebook_grad_reduce",
            "cgs_bin_tiles_workspace_bytes", "cgs_bin_tiles", "cgs_loss_l1_workspace_bytes",
-           "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version")
+           "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version",
+           "cgs_render_backward_sgld", "cgs_sgld_normals", "cgs_loss_recon_workspace_bytes", "cgs_loss_recon")
 
 
 class Camera(ctypes.Structure):
@@ -63,6 +64,18 @@ class WsLayout(ctypes.Structure):
                 ("tile_range", c_size_t), ("n_records", c_int64), ("n_tiles", c_int64)]
 
 
+class Sgld(ctypes.Structure):
+    _fields_ = [("eps_means", ctypes.c_float), ("eps_opacity", ctypes.c_float), ("eps_sr", ctypes.c_float),
+                ("eps_sh", ctypes.c_float), ("seed", ctypes.c_uint64), ("step", ctypes.c_uint32),
+                ("pad_", ctypes.c_uint32)]
+
+
+class SceneParams(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("opacity_logit", c_void_p),
+                ("sr", c_void_p), ("sr_stride", c_int32), ("sr_col0", c_int32),
+                ("sh", c_void_p), ("sh_stride", c_int32), ("sh_col0", c_int32)]
+
+
 _LIB = None
 
 
@@ -96,6 +109,17 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cgs_loss_l1_workspace_bytes.restype = c_size_t
     L.cgs_loss_l1.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.cgs_loss_l1.restype = c_int32
+    L.cgs_render_backward_sgld.argtypes = [pb, c_void_p, c_void_p, c_void_p, POINTER(SceneGrads), POINTER(Sgld),
+                                           POINTER(SceneParams), c_void_p, c_size_t, c_void_p, c_void_p]
+    L.cgs_render_backward_sgld.restype = c_int32
+    L.cgs_sgld_normals.argtypes = [c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                   c_void_p, c_void_p, c_void_p]
+    L.cgs_sgld_normals.restype = c_int32
+    L.cgs_loss_recon_workspace_bytes.argtypes = [c_int32, POINTER(c_int32)]
+    L.cgs_loss_recon_workspace_bytes.restype = c_size_t
+    L.cgs_loss_recon.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32), ctypes.c_float, c_void_p, c_void_p,
+                                 c_void_p, c_size_t, c_void_p]
+    L.cgs_loss_recon.restype = c_int32
     L.cgs_workspace_layout.argtypes = [pb, POINTER(WsLayout)]
     L.cgs_workspace_layout.restype = c_int32
     L.cgs_status_str.argtypes = [c_int32]
@@ -165,6 +189,31 @@ def loss_l1_workspace_bytes(n: int) -> int:
 
 def loss_l1(image, target, n, grad, loss, ws, ws_bytes, stream) -> None:
     check("cgs_loss_l1", load().cgs_loss_l1(image, target, n, grad, loss, ws, ws_bytes, stream))
+
+
+def render_backward_sgld(batch: Batch, grad_image, T_final, n_last, grads, sgld: Sgld, params, ws, ws_bytes,
+                         d_info, stream) -> None:
+    check("cgs_render_backward_sgld", load().cgs_render_backward_sgld(ctypes.byref(batch), grad_image, T_final,
+                                                                      n_last, grads, ctypes.byref(sgld), params, ws,
+                                                                      ws_bytes, d_info, stream))
+
+
+def sgld_normals(n, index0, tag, step, seed, z, words, stream) -> None:
+    check("cgs_sgld_normals", load().cgs_sgld_normals(n, index0, tag, step, seed, z, words, stream))
+
+
+def _hw_array(hw):
+    flat = [int(v) for pair in hw for v in pair]
+    return (c_int32 * len(flat))(*flat)
+
+
+def loss_recon_workspace_bytes(hw) -> int:
+    return load().cgs_loss_recon_workspace_bytes(len(hw), _hw_array(hw))
+
+
+def loss_recon(image, target, hw, lambda_ssim, grad, loss, ws, ws_bytes, stream) -> None:
+    check("cgs_loss_recon", load().cgs_loss_recon(image, target, len(hw), _hw_array(hw), lambda_ssim, grad, loss,
+                                                  ws, ws_bytes, stream))
 
 
 def workspace_layout(batch: Batch) -> WsLayout:

@@ -36,6 +36,9 @@ hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int,
 hipError_t launch_gather_keys(const int32_t*, const int32_t*, int64_t, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_copy_keys(const int32_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_l1(const float*, const float*, int64_t, float*, float*, float*, int, hipStream_t);
+hipError_t launch_loss_recon(const LossViews&, const float*, const float*, float, float*, float*, float*, double*,
+                             hipStream_t);
+hipError_t launch_normals(int64_t, uint64_t, uint32_t, uint32_t, uint64_t, float*, uint32_t*, hipStream_t);
 
 namespace {
 
@@ -354,14 +357,47 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     return CGS_OK;
 }
 
-cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, const float* T_final,
-                               const int32_t* n_last, const cgs_scene_grads* grads, void* ws, size_t ws_bytes,
-                               int64_t* d_info, void* stream) {
-    (void)d_info;
+namespace {
+
+// Backward shared by the plain entry point and the one with the fused SGLD
+// update (sgld and params both NULL: gradients only).
+cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const float* T_final, const int32_t* n_last,
+                         const cgs_scene_grads* grads, const cgs_sgld* sgld, const cgs_scene_params* params, void* ws,
+                         size_t ws_bytes, void* stream) {
     static thread_local Host h;
     cgs_status s = plan_batch(batch, &h);
     if (s != CGS_OK) return s;
     if (!ws || !grads) return CGS_EINVAL;
+    h.d.sgld = 0;
+    if (sgld) {
+        if (!params) return CGS_EINVAL;
+        for (int k = 0; k < 4; ++k) {
+            const float e = (&sgld->eps_means)[k];
+            if (!(e >= 0.f) || !(e < 3.0e38f)) return CGS_EINVAL;
+            h.d.eps[k] = e;
+        }
+        h.d.sgld = 1;
+        h.d.seed = sgld->seed;
+        h.d.step = (int32_t)sgld->step;
+        const int nco = (h.d.row_width - 8) / 3;
+        for (int i = 0; i < batch->n_scenes; ++i) {
+            const cgs_scene_params& q = params[i];
+            SceneDesc& sd = h.d.scenes[i];
+            if (sd.n > 0 && !q.means) return CGS_EINVAL;
+            if (h.opacity_mode == 0 && sd.n > 0 && !q.opacity_logit) return CGS_EINVAL;
+            if (!q.sr || !q.sh) return CGS_EINVAL;
+            if (q.sr_col0 < 0 || q.sr_stride < q.sr_col0 + (h.opacity_mode ? 8 : 7)) return CGS_EINVAL;
+            if (q.sh_col0 < 0 || q.sh_stride < q.sh_col0 + 3 * nco) return CGS_EINVAL;
+            sd.u_means = q.means;
+            sd.u_opacity = q.opacity_logit;
+            sd.u_sr = q.sr;
+            sd.u_sr_stride = q.sr_stride;
+            sd.u_sr_col0 = q.sr_col0;
+            sd.u_sh = q.sh;
+            sd.u_sh_stride = q.sh_stride;
+            sd.u_sh_col0 = q.sh_col0;
+        }
+    }
     if (ws_bytes < h.p.total) return CGS_EWORKSPACE;
     if (h.d.n_pix > 0 && (!grad_image || !T_final || !n_last)) return CGS_EINVAL;
     bool single = h.fused;
@@ -425,6 +461,24 @@ cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, 
     }
     CGS_TRY(mark(h, 7, st));
     return CGS_OK;
+}
+
+}  // namespace
+
+cgs_status cgs_render_backward(const cgs_batch* batch, const float* grad_image, const float* T_final,
+                               const int32_t* n_last, const cgs_scene_grads* grads, void* ws, size_t ws_bytes,
+                               int64_t* d_info, void* stream) {
+    (void)d_info;
+    return backward_impl(batch, grad_image, T_final, n_last, grads, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+cgs_status cgs_render_backward_sgld(const cgs_batch* batch, const float* grad_image, const float* T_final,
+                                    const int32_t* n_last, const cgs_scene_grads* grads, const cgs_sgld* sgld,
+                                    const cgs_scene_params* params, void* ws, size_t ws_bytes, int64_t* d_info,
+                                    void* stream) {
+    (void)d_info;
+    if (!sgld || !params) return CGS_EINVAL;
+    return backward_impl(batch, grad_image, T_final, n_last, grads, sgld, params, ws, ws_bytes, stream);
 }
 
 size_t cgs_codebook_grad_reduce_workspace_bytes(int64_t n, int64_t k, int32_t d) {
@@ -558,6 +612,57 @@ cgs_status cgs_loss_l1(const float* image, const float* target, int64_t n, float
     int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
     if (nb < 1) nb = 1;
     return hip_status(launch_l1(image, target, n, grad, loss, static_cast<float*>(ws), nb, static_cast<hipStream_t>(stream)));
+}
+
+namespace {
+// Geometry of the loss batch; false on invalid sizes.
+bool loss_views(int32_t n_views, const int32_t* hw, cgs::LossViews* lv, int64_t* n_pix) {
+    if (n_views < 1 || n_views > CGS_MAX_VIEWS || !hw) return false;
+    memset(lv, 0, sizeof(*lv));
+    lv->n = n_views;
+    int64_t p = 0, t = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int32_t H = hw[2 * v], W = hw[2 * v + 1];
+        if (H <= 0 || W <= 0) return false;
+        lv->H[v] = H;
+        lv->W[v] = W;
+        lv->tiles_x[v] = (W + cgs::kTile - 1) / cgs::kTile;
+        lv->pix_off[v] = p;
+        lv->tile_off[v] = t;
+        p += (int64_t)H * W;
+        t += (int64_t)lv->tiles_x[v] * ((H + cgs::kTile - 1) / cgs::kTile);
+    }
+    lv->tile_off[n_views] = t;
+    *n_pix = p;
+    return t < ((int64_t)1 << 31);
+}
+}  // namespace
+
+size_t cgs_loss_recon_workspace_bytes(int32_t n_views, const int32_t* hw) {
+    cgs::LossViews lv;
+    int64_t P;
+    if (!loss_views(n_views, hw, &lv, &P)) return 0;
+    return align_up(36 * (size_t)P) + 16 * (size_t)lv.tile_off[n_views] + 256;
+}
+
+cgs_status cgs_loss_recon(const float* image, const float* target, int32_t n_views, const int32_t* hw,
+                          float lambda_ssim, float* grad, float* loss, void* ws, size_t ws_bytes, void* stream) {
+    cgs::LossViews lv;
+    int64_t P;
+    if (!loss_views(n_views, hw, &lv, &P)) return CGS_EINVAL;
+    if (!(lambda_ssim >= 0.f && lambda_ssim <= 1.f)) return CGS_EINVAL;
+    if (!image || !target || !grad || !loss || !ws) return CGS_EINVAL;
+    if (ws_bytes < cgs_loss_recon_workspace_bytes(n_views, hw)) return CGS_EWORKSPACE;
+    float* part = static_cast<float*>(ws);
+    double* sums = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up(36 * (size_t)P));
+    return hip_status(cgs::launch_loss_recon(lv, image, target, lambda_ssim, grad, loss, part, sums,
+                                             static_cast<hipStream_t>(stream)));
+}
+
+cgs_status cgs_sgld_normals(int64_t n, uint64_t index0, uint32_t tag, uint32_t step, uint64_t seed, float* z,
+                            uint32_t* words, void* stream) {
+    if (n < 0 || (n > 0 && !z)) return CGS_EINVAL;
+    return hip_status(cgs::launch_normals(n, index0, tag, step, seed, z, words, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

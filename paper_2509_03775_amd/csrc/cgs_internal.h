@@ -54,6 +54,12 @@ struct SceneDesc {
     float* g_sh;
     float* g_opacity;
     int32_t g_sr_stride, g_sr_col0, g_sh_stride, g_sh_col0;
+    // SGLD update targets (FP32 masters; see cgs_scene_params)
+    float* u_means;
+    float* u_opacity;
+    float* u_sr;
+    float* u_sh;
+    int32_t u_sr_stride, u_sr_col0, u_sh_stride, u_sh_col0;
 };
 
 struct BatchDesc {
@@ -66,9 +72,22 @@ struct BatchDesc {
     int64_t n_rec, n_gauss, n_tiles, n_pix, capacity;
     int64_t sr_rows_total, sh_rows_total;
     int64_t n_gauss_waves, n_rec_waves;   // scene-aligned / view-aligned wavefront counts
+    // SGLD update fused into the backward (sgld != 0): step sizes of means,
+    // opacity logit, SR columns, SH columns; Philox key and step
+    int32_t sgld, step;
+    float eps[4];
+    uint64_t seed;
     int32_t view_list[CGS_MAX_VIEWS];   // views grouped by scene
     ViewDesc views[CGS_MAX_VIEWS];
     SceneDesc scenes[CGS_MAX_SCENES];
+};
+
+// Image geometry of a batch of views for the loss kernels (by value).
+struct LossViews {
+    int32_t n;
+    int32_t H[CGS_MAX_VIEWS], W[CGS_MAX_VIEWS], tiles_x[CGS_MAX_VIEWS];
+    int64_t pix_off[CGS_MAX_VIEWS];
+    int64_t tile_off[CGS_MAX_VIEWS + 1];
 };
 
 // Device counters kept in the workspace.

@@ -3,6 +3,7 @@
 // mean and the codebook-row values, and the codebook reduction as a sort by
 // row index followed by fixed-order segmented sums (no contended atomics).
 #include "cgs_internal.h"
+#include "philox.h"
 #include "render_common.h"
 
 namespace cgs {
@@ -262,6 +263,57 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     for (int i = 0; i < 9; ++i) out[i] = d[i];
 }
 
+// ------------------------------------------------------------ SGLD update
+// theta <- theta - (eps/2) dL/dtheta + sqrt(eps) eta, eta ~ N(0, 1) from the
+// Philox streams (the parameter-update transition: grad log p = -grad L).
+// The FP32 master is updated in place and, when the renderer reads a
+// different copy (BF16 codebook, separate FP32 array), that copy is refreshed
+// from the new master (BF16 by round-to-nearest-even).
+
+// A Gaussian's own parameters: mean, and the opacity logit when it is per
+// Gaussian.
+__device__ inline void sgld_gaussian(const BatchDesc* desc, const SceneDesc& sd, int s, int64_t g, const float dmu[3],
+                                     float dlogit) {
+    float z[4];
+    normals4((uint64_t)g, gaussian_tag(s), (uint32_t)desc->step, desc->seed, z);
+    if (sd.u_means) {
+        const float e = desc->eps[0], h = 0.5f * e, r = sqrtf(e);
+        float* mirror = const_cast<float*>(sd.means);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float v = sd.u_means[3 * g + k] - h * dmu[k] + r * z[k];
+            sd.u_means[3 * g + k] = v;
+            if (mirror != sd.u_means) mirror[3 * g + k] = v;
+        }
+    }
+    if (sd.opacity_mode == 0 && sd.u_opacity) {
+        const float e = desc->eps[1];
+        const float v = sd.u_opacity[g] - 0.5f * e * dlogit + sqrtf(e) * z[3];
+        sd.u_opacity[g] = v;
+        float* mirror = const_cast<float*>(sd.opacity);
+        if (mirror != sd.u_opacity) mirror[g] = v;
+    }
+}
+
+// One codebook entry: row lr (scene-local) of scene s, row-layout column gc
+// (ls 0-2, q 3-6, logit 7, SH 8-), with its reduced gradient.
+__device__ inline void sgld_row(const BatchDesc* desc, int s, int64_t lr, int gc, float grad) {
+    const SceneDesc& sd = desc->scenes[s];
+    const bool srp = gc < 8;
+    float* m = srp ? sd.u_sr : sd.u_sh;
+    if (!m) return;
+    m += srp ? lr * sd.u_sr_stride + sd.u_sr_col0 + gc : lr * sd.u_sh_stride + sd.u_sh_col0 + (gc - 8);
+    const float e = gc < 7 ? desc->eps[2] : (gc == 7 ? desc->eps[1] : desc->eps[3]);
+    float z[4];
+    normals4(16u * (uint64_t)lr + (uint64_t)(gc >> 2), codebook_tag(s), (uint32_t)desc->step, desc->seed, z);
+    const float v = *m - 0.5f * e * grad + sqrtf(e) * z[gc & 3];
+    *m = v;
+    const int64_t off = srp ? lr * sd.sr_stride + sd.sr_col0 + gc : lr * sd.sh_stride + sd.sh_col0 + (gc - 8);
+    void* base = const_cast<void*>(srp ? sd.sr : sd.sh);
+    if (desc->dtype == CGS_BF16) static_cast<uint16_t*>(base)[off] = f32_to_bf16_rne(v);
+    else if (static_cast<float*>(base) + off != m) static_cast<float*>(base)[off] = v;
+}
+
 // ------------------------------------------------------------ chain rule
 // One thread per Gaussian: recompute the projection of every view of its
 // scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
@@ -272,7 +324,8 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
-    const SceneDesc& sd = desc->scenes[find_scene_by_wave(desc, wv)];
+    const int s = find_scene_by_wave(desc, wv);
+    const SceneDesc& sd = desc->scenes[s];
     const int64_t g = (wv - sd.wave_off) * kWave + (threadIdx.x & 63);
     if (g >= sd.n) return;
     const int64_t gg = sd.g_off + g;
@@ -284,6 +337,10 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         for (int i = 0; i < RW; ++i) out[i] = 0.f;
         if (sd.g_means) { sd.g_means[3 * g] = 0.f; sd.g_means[3 * g + 1] = 0.f; sd.g_means[3 * g + 2] = 0.f; }
         if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = 0.f;
+        if (desc->sgld) {
+            const float zero3[3] = {0.f, 0.f, 0.f};
+            sgld_gaussian(desc, sd, s, g, zero3, 0.f);
+        }
         return;
     }
     GaussShape sh;
@@ -477,6 +534,7 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         sd.g_means[3 * g + 2] = dmu[2];
     }
     if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
+    if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmu, dlogit);
 }
 
 // ------------------------------------------------- codebook row reduction
@@ -497,7 +555,7 @@ struct RowOut {
     int32_t col0;
 };
 
-__device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, int64_t* local) {
+__device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, int64_t* local, int* scene) {
     int lo = 0, hi = desc->n_scenes - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -505,6 +563,7 @@ __device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, i
         if (off <= row) lo = mid; else hi = mid - 1;
     }
     const SceneDesc& sd = desc->scenes[lo];
+    *scene = lo;
     if (part == 0) {
         *local = row - sd.sr_row_off;
         return RowOut{sd.g_sr, sd.g_sr_stride, sd.g_sr_col0};
@@ -542,7 +601,8 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const BatchDesc* __restrict
         if ((int64_t)r >= n_rows) break;                    // index outside the codebook: dropped
         const int64_t e = row_range[2 * (int64_t)r + 1];
         int64_t lr;
-        const RowOut o = row_out(desc, part, r, &lr);
+        int sc;
+        const RowOut o = row_out(desc, part, r, &lr, &sc);
         for (int cb = 0; cb < D; cb += 64) {
             const int col = cb + lane;
             const bool on = col < D;
@@ -559,14 +619,17 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const BatchDesc* __restrict
                 acc += a3;
             }
             for (; q < e; ++q) acc += on ? gtheta[(int64_t)sval[q] * ld + c0 + col] : 0.f;
-            if (on) o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
+            if (on) {
+                o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
+                if (desc->sgld) sgld_row(desc, sc, lr, c0 + col, acc);
+            }
         }
         p = e;
     }
 }
 
 // Rows no Gaussian maps to get a zero gradient.
-__global__ __launch_bounds__(256) void k_reduce_empty(const BatchDesc* __restrict__ desc, int part, int D,
+__global__ __launch_bounds__(256) void k_reduce_empty(const BatchDesc* __restrict__ desc, int part, int c0, int D,
                                                       int oshift, int64_t n_rows,
                                                       const uint32_t* __restrict__ row_range) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -575,8 +638,10 @@ __global__ __launch_bounds__(256) void k_reduce_empty(const BatchDesc* __restric
     const int col = (int)(e - row * D);
     if (row_range[2 * row] != row_range[2 * row + 1]) return;
     int64_t lr;
-    const RowOut o = row_out(desc, part, row, &lr);
+    int sc;
+    const RowOut o = row_out(desc, part, row, &lr, &sc);
     o.ptr[lr * o.stride + o.col0 + oshift + col] = 0.f;
+    if (desc->sgld) sgld_row(desc, sc, lr, c0 + col, 0.f);
 }
 
 // Sorted keys from a caller-provided permutation: key[i] = idx[perm[i]].
@@ -683,7 +748,7 @@ hipError_t launch_reduce(const BatchDesc* d_desc, int part, const float* gtheta,
                            ld, c0, D, oshift, skey, sval, n, n_rows, row_range);
     if (n_rows * D > 0)
         hipLaunchKernelGGL(k_reduce_empty, dim3((unsigned)((n_rows * D + 255) / 256)), dim3(256), 0, st, d_desc, part,
-                           D, oshift, n_rows, row_range);
+                           c0, D, oshift, n_rows, row_range);
     return hipGetLastError();
 }
 

@@ -219,6 +219,18 @@ class Renderer:
                             _stream_ptr(stream))
         return self.grad_means, self.grad_cb
 
+    def backward_sgld(self, grad_image: torch.Tensor, sgld: "cgs.Sgld", params: Sequence["cgs.SceneParams"],
+                      stream=None):
+        """backward() plus one fused SGLD step of every parameter (params:
+        one cgs.SceneParams per scene, e.g. from sgld_params())."""
+        assert grad_image.dtype == torch.float32 and grad_image.is_contiguous()
+        assert grad_image.numel() == 3 * self.n_pixels and len(params) == len(self.scenes)
+        arr = (cgs.SceneParams * len(params))(*params)
+        cgs.render_backward_sgld(self.batch, grad_image.data_ptr(), self.T_final.data_ptr(), self.n_last.data_ptr(),
+                                 self._grads, sgld, arr, self.ws.data_ptr(), self.ws_bytes, self.d_info.data_ptr(),
+                                 _stream_ptr(stream))
+        return self.grad_means, self.grad_cb
+
     def instances(self) -> int:
         """Instances the last forward needed (synchronises)."""
         return int(self.d_info[1].item())
@@ -275,6 +287,38 @@ def render(renderer: Renderer) -> torch.Tensor:
     for s in renderer.scenes:
         tensors += [s.means, s.cb]
     return CgsRenderFunction.apply(renderer, *tensors)
+
+
+def sgld_params(scene, master_sr: Optional[torch.Tensor] = None,
+                master_sh: Optional[torch.Tensor] = None) -> "cgs.SceneParams":
+    """The FP32 parameters an SGLD step updates for a scene: its own means
+    (and per-Gaussian opacity) in place; its codebook(s) in place when FP32,
+    else the given FP32 masters (fused layout: master_sr = the [K, R] master,
+    master_sh unused)."""
+    p = cgs.SceneParams()
+    p.means = scene.means.data_ptr()
+    if isinstance(scene, DeviceScene2):
+        sr = scene.sr if scene.sr.dtype == torch.float32 else master_sr
+        sh = scene.sh if scene.sh.dtype == torch.float32 else master_sh
+        assert sr is not None and sh is not None and sr.dtype == torch.float32 and sh.dtype == torch.float32
+        p.opacity_logit = scene.opacity_logit.data_ptr()
+        p.sr, p.sr_stride, p.sr_col0 = sr.data_ptr(), int(sr.shape[1]), 0
+        p.sh, p.sh_stride, p.sh_col0 = sh.data_ptr(), int(sh.shape[1]), 0
+    else:
+        cb = scene.cb if scene.cb.dtype == torch.float32 else master_sr
+        assert cb is not None and cb.dtype == torch.float32 and cb.shape == scene.cb.shape
+        p.opacity_logit = None
+        p.sr, p.sr_stride, p.sr_col0 = cb.data_ptr(), int(cb.shape[1]), 0
+        p.sh, p.sh_stride, p.sh_col0 = cb.data_ptr(), int(cb.shape[1]), 8
+    return p
+
+
+def loss_recon(image: torch.Tensor, target: torch.Tensor, hw: Sequence[Sequence[int]], lambda_ssim: float,
+               grad: torch.Tensor, loss: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    """Eq. 4's (1 - lambda) L1 + lambda (1 - SSIM) and its gradient (writes
+    grad and loss); hw = [(height, width)] per view."""
+    cgs.loss_recon(image.data_ptr(), target.data_ptr(), hw, float(lambda_ssim), grad.data_ptr(), loss.data_ptr(),
+                   ws.data_ptr(), ws.numel(), _stream_ptr(stream))
 
 
 def loss_l1(image: torch.Tensor, target: torch.Tensor, grad: torch.Tensor, loss: torch.Tensor,

@@ -112,3 +112,54 @@ def test_reduce_and_bin_validation():
     assert L.cgs_bin_tiles(0x1, 0x2, None, 10, 4, 4, 1, None, 0x3, 0x4, 100, None, 0x5, 1, None) == cgs.CGS_EWORKSPACE
     assert L.cgs_loss_l1(0x1, 0x2, -1, 0x3, 0x4, 0x5, 1 << 20, None) == cgs.CGS_EINVAL
     assert L.cgs_status_str(cgs.CGS_ECAPACITY) == b"instance capacity exceeded"
+
+
+def test_backward_sgld_validation():
+    b = _batch()
+    L = cgs.load()
+    need = L.cgs_workspace_bytes(ctypes.byref(b))
+    g = cgs.SceneGrads()
+    g.means, g.sr, g.sr_stride, g.sr_col0 = 0x100, 0x200, 11, 0
+    g.sh, g.sh_stride, g.sh_col0 = 0x200, 11, 8
+    p = cgs.SceneParams(0x500, None, 0x600, 11, 0, 0x600, 11, 8)
+    s = cgs.Sgld(1e-3, 1e-3, 1e-3, 1e-3, 7, 1, 0)
+    call = lambda sg, pp, ws=need: L.cgs_render_backward_sgld(ctypes.byref(b), 0x1, 0x2, 0x3, ctypes.byref(g), sg, pp,
+                                                              0x4, ws, None, None)
+    assert call(None, ctypes.byref(p)) == cgs.CGS_EINVAL
+    assert call(ctypes.byref(s), None) == cgs.CGS_EINVAL
+    neg = cgs.Sgld.from_buffer_copy(s)
+    neg.eps_sh = -1.0
+    assert call(ctypes.byref(neg), ctypes.byref(p)) == cgs.CGS_EINVAL
+    nan = cgs.Sgld.from_buffer_copy(s)
+    nan.eps_sr = float("nan")
+    assert call(ctypes.byref(nan), ctypes.byref(p)) == cgs.CGS_EINVAL
+    narrow = cgs.SceneParams.from_buffer_copy(p)
+    narrow.sh_stride = 3
+    assert call(ctypes.byref(s), ctypes.byref(narrow)) == cgs.CGS_EINVAL
+    nomeans = cgs.SceneParams.from_buffer_copy(p)
+    nomeans.means = None
+    assert call(ctypes.byref(s), ctypes.byref(nomeans)) == cgs.CGS_EINVAL
+    assert call(ctypes.byref(s), ctypes.byref(p), need - 1) == cgs.CGS_EWORKSPACE
+
+
+def test_loss_recon_validation():
+    L = cgs.load()
+    hw = (ctypes.c_int32 * 4)(37, 53, 16, 16)
+    need = L.cgs_loss_recon_workspace_bytes(2, hw)
+    assert need >= 36 * (37 * 53 + 256)
+    assert L.cgs_loss_recon_workspace_bytes(0, hw) == 0
+    bad = (ctypes.c_int32 * 2)(0, 5)
+    assert L.cgs_loss_recon_workspace_bytes(1, bad) == 0
+    args = lambda lam, ws=need, n=2, h=hw: L.cgs_loss_recon(0x1, 0x2, n, h, lam, 0x3, 0x4, 0x5, ws, None)
+    assert args(-0.1) == cgs.CGS_EINVAL
+    assert args(1.5) == cgs.CGS_EINVAL
+    assert args(0.2, n=0) == cgs.CGS_EINVAL
+    assert args(0.2, n=1, h=bad) == cgs.CGS_EINVAL
+    assert args(0.2, ws=need - 1) == cgs.CGS_EWORKSPACE
+
+
+def test_sgld_normals_validation():
+    L = cgs.load()
+    assert L.cgs_sgld_normals(-1, 0, 0, 0, 0, 0x1, None, None) == cgs.CGS_EINVAL
+    assert L.cgs_sgld_normals(4, 0, 0, 0, 0, None, None, None) == cgs.CGS_EINVAL
+    assert L.cgs_sgld_normals(0, 0, 0, 0, 0, None, None, None) == cgs.CGS_OK
