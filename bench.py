@@ -41,6 +41,7 @@ HBM_PEAK = 8.0e12                       # bytes/s
 # count) and 30 in the backward (T recovery 2, weight 1, colour grads 3,
 # alpha grad 7, background update 3, opacity grad 2, power grads 12).
 OPS_ALPHA, OPS_FWD_BLEND, OPS_BWD_BLEND = 11, 8, 30
+LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 
 # HBM bytes per launch of the blend kernels on the headline workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
@@ -106,9 +107,11 @@ class Form:
     """One way to run a step: `batched` renders every view in one call; `plain`
     issues one call per view."""
 
-    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08, waves_per_block=1, tile_order=0):
+    def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08, waves_per_block=1, tile_order=0,
+                 train: bool = False):
         self.wl = wl
         self.batched = batched
+        self.train = train
         ds = [render.DeviceScene.from_host(s, bf16=wl.bf16) for s in wl.scenes]
         self.scenes = ds
         if batched:
@@ -135,8 +138,28 @@ class Form:
         n = max(t.numel() for t in self.targets)
         self.loss_ws = torch.empty(cgs.loss_l1_workspace_bytes(n), dtype=torch.uint8, device="cuda")
         self.n_pixels = wl.n_pixels
+        if train:
+            # Eq. 4 with the SSIM term and the SGLD update fused into the
+            # backward; BF16 codebooks train an FP32 master (small steps keep
+            # the scene, and so the instance count, essentially unchanged)
+            self.masters = [None if s.cb.dtype == torch.float32 else s.cb.float() for s in ds]
+            self.hw = [[(wl.cameras[v].height, wl.cameras[v].width) for v in gidx] for gidx in groups]
+            self.recon_ws = [torch.empty(cgs.loss_recon_workspace_bytes(h), dtype=torch.uint8, device="cuda")
+                             for h in self.hw]
+            self.params = []
+            for gidx in groups:
+                used = sorted(set(int(wl.view_scene[v]) for v in gidx))
+                self.params.append([render.sgld_params(ds[s], master_sr=self.masters[s]) for s in used])
+            self.sgld = cgs.Sgld(1e-9, 1e-8, 1e-8, 1e-8, 2026, 0, 0)
 
     def step(self):
+        if self.train:
+            self.sgld.step += 1
+            for i, (r, t, g, l) in enumerate(zip(self.renderers, self.targets, self.grads, self.losses)):
+                img = r.forward()
+                render.loss_recon(img, t, self.hw[i], LAMBDA_SSIM, g, l, self.recon_ws[i])
+                r.backward_sgld(g, self.sgld, self.params[i])
+            return
         for r, t, g, l in zip(self.renderers, self.targets, self.grads, self.losses):
             img = r.forward()
             render.loss_l1(img, t, g, l, self.loss_ws)
@@ -161,7 +184,7 @@ class Form:
 
 
 def stage_times(ev: HipEvents, steps):
-    names = [("preprocess", 0, 1), ("binning", 1, 2), ("blend_fwd", 2, 3), ("blend_bwd", 4, 5),
+    names = [("preprocess", 0, 1), ("binning", 1, 2), ("blend_fwd", 2, 3), ("loss", 3, 4), ("blend_bwd", 4, 5),
              ("chain", 5, 6), ("codebook_reduce", 6, 7)]
     out = {}
     for name, a, b in names:
@@ -335,7 +358,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=HEADLINE)
-    ap.add_argument("--extra-forms", default="fp32_plain,1m,uncompressed,uneven16,graph",
+    ap.add_argument("--extra-forms", default="train,fp32_plain,1m,uncompressed,uneven16,graph",
                     help="comma list of: fp32_plain, 1m, uncompressed, uneven16, graph; or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -401,6 +424,19 @@ def main():
             torch.cuda.synchronize()
             extra_info["bf16_vs_fp32_codebook"] = compare_forms(head, f)
         del f, wl32
+        torch.cuda.empty_cache()
+    if "train" in extras:
+        log(f"[bench] timing {args.workload} training step: SSIM loss + fused SGLD update")
+        f = Form(wl, batched=True, waves_per_block=sched[0], tile_order=sched[1], train=True)
+        ev2 = HipEvents(nsteps * cgs.STAGE_EVENTS)
+        ms_t = f.time(nsteps, 2, ev2)
+        st2 = stage_times(ev2, nsteps)
+        forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_train_ssim_sgld:{args.workload}"] = wl.n_pixels / (ms_t * 1e-3) / 1e6
+        extra_info["train_step"] = {
+            "ms_per_step": ms_t, "lambda_ssim": LAMBDA_SSIM, "stages_ms": st2,
+            "loss_ssim_minus_l1_ms": st2["loss"] - stages["loss"],
+            "sgld_epilogues_ms": (st2["chain"] + st2["codebook_reduce"]) - (stages["chain"] + stages["codebook_reduce"])}
+        del f, ev2
         torch.cuda.empty_cache()
     if "uncompressed" in extras:
         log(f"[bench] timing {args.workload} uncompressed (K = N)")

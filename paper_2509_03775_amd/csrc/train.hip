@@ -8,9 +8,10 @@
 // with zero padding, C1 = 0.01^2, C2 = 0.03^2:
 //   S = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sxx + syy + C2)),
 //   mx = w*x, sxx = w*(x x) - mx^2, sxy = w*(x y) - mx my.
-// With A1, A2, B1, B2 the four factors, S depends on the image x through
-//   dS/dmx  = S (2my/A1 - 2my/A2 - 2mx/B1 + 2mx/B2),
-//   dS/dmxx = -S / B2,   dS/dmxy = 2 S / A2   (mxx = w*(x x), mxy = w*(x y)),
+// With A1, A2, B1, B2 the four factors (B1, B2 > 0; A2 = 2 sxy + C2 may
+// vanish, so nothing divides by it), S depends on the image x through
+//   dS/dmx  = 2 [my (A2 - A1) - mx S (B2 - B1)] / (B1 B2),
+//   dS/dmxx = -S / B2,   dS/dmxy = 2 A1 / (B1 B2)   (mxx = w*(x x), mxy = w*(x y)),
 // and the window is symmetric, so
 //   d(sum_q S(q))/dx(p) = w*(dS/dmx)(p) + 2 x(p) w*(dS/dmxx)(p) + y(p) w*(dS/dmxy)(p)
 // with the partial maps taken as zero outside the image.
@@ -116,10 +117,11 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
             const float A2 = 2.f * (m[4] - mx * my) + kC2;
             const float B1 = mx * mx + my * my + kC1;
             const float B2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
-            const float S = (A1 * A2) / (B1 * B2);
-            out[3 * ch + 0] = S * (2.f * my / A1 - 2.f * my / A2 - 2.f * mx / B1 + 2.f * mx / B2);
+            const float inv = 1.f / (B1 * B2);
+            const float S = A1 * A2 * inv;
+            out[3 * ch + 0] = 2.f * inv * (my * (A2 - A1) - mx * S * (B2 - B1));
             out[3 * ch + 1] = -S / B2;
-            out[3 * ch + 2] = 2.f * S / A2;
+            out[3 * ch + 2] = 2.f * A1 * inv;
             ss += (double)S;
             l1 += (double)fabsf(s_x[ch][ty + kHalo][tx + kHalo] - s_y[ch][ty + kHalo][tx + kHalo]);
         }

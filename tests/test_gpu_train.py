@@ -45,14 +45,31 @@ def test_sgld_normals():
     assert err <= NORMAL_TOL
 
 
+def _anticorrelated(h, w):
+    """Image and target that are mirror images about 0.5 with a checkerboard
+    of amplitude sqrt(C2 / 2): the local covariance is about -C2 / 2, so the
+    SSIM factor 2 sxy + C2 passes through zero."""
+    a = np.sqrt(otrain.SSIM_C2 / 2.0)
+    cb = np.indices((h, w)).sum(0) % 2 * 2.0 - 1.0
+    x = np.repeat((0.5 + a * cb)[:, :, None], 3, 2)
+    y = np.repeat((0.5 - a * cb)[:, :, None], 3, 2)
+    x[:, :, 1] = 0.3 + 0.9 * a * cb     # other channels near, not at, the zero
+    return x.astype(np.float32), y.astype(np.float32)
+
+
+@pytest.mark.parametrize("case", ["random", "anticorrelated"])
 @pytest.mark.parametrize("lam", [0.0, 0.2, 1.0])
-def test_loss_recon(lam):
+def test_loss_recon(lam, case):
     rng = np.random.default_rng(31)
     hw = [(37, 53), (16, 16), (1, 1), (70, 33)]
-    say(f"[loss] lambda={lam} views={hw}")
-    ims = [rng.uniform(0, 1, (h, w, 3)).astype(np.float32) for h, w in hw]
-    tgs = [np.clip(im + 0.15 * rng.standard_normal(im.shape), 0, 1).astype(np.float32) for im in ims]
-    tgs[0][3, 4] = ims[0][3, 4]          # exact ties: sign(0) = 0 on both sides
+    say(f"[loss] lambda={lam} {case} views={hw}")
+    if case == "random":
+        ims = [rng.uniform(0, 1, (h, w, 3)).astype(np.float32) for h, w in hw]
+        tgs = [np.clip(im + 0.15 * rng.standard_normal(im.shape), 0, 1).astype(np.float32) for im in ims]
+        tgs[0][3, 4] = ims[0][3, 4]          # exact ties: sign(0) = 0 on both sides
+    else:
+        pairs = [_anticorrelated(h, w) for h, w in hw]
+        ims, tgs = [p[0] for p in pairs], [p[1] for p in pairs]
     loss_o, grads_o = otrain.loss_recon(ims, tgs, lam)
     img = torch.from_numpy(np.concatenate([im.reshape(-1, 3) for im in ims])).cuda()
     tgt = torch.from_numpy(np.concatenate([t.reshape(-1, 3) for t in tgs])).cuda()
