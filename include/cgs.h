@@ -240,6 +240,52 @@ cgs_status cgs_sgld_normals(int64_t n, uint64_t index0, uint32_t tag, uint32_t s
  * hw: host int32 [n_views][2] (height, width); loss: device float[1]; grad is
  * written.  0 <= lambda <= 1.  Workspace: cgs_loss_recon_workspace_bytes. */
 size_t cgs_loss_recon_workspace_bytes(int32_t n_views, const int32_t* hw);
+
+/* Metropolis-Hastings moves on a codebook (the split and merge transitions of
+ * the proposal mixture, Sec. 4.4 and App. A.1).  One call makes n_proposals
+ * independent proposals from counter-based Philox streams (counter 16 b + j,
+ * tag 0x20000 split / 0x20001 merge, `step`, key `seed`).
+ * Split: Gaussian g = floor(w0 n / 2^32), offset u ~ N(0, eps_split^2 I) over
+ * the row, accepted with the paper's probability min(1, e^-lambda / q_sm(u)),
+ * q_sm(u) = exp(-|u|^2/2 (1/eps_split^2 - 1/eps_merge^2)); a Gaussian splits
+ * at most once per call (lowest proposal); accepted splits in proposal order
+ * append rows c + u (row c keeps its value) while rows < K_max and move g.
+ * Merge: a uniform pair of distinct live rows (c, c'), thinned by
+ * exp(-|c - c'|^2 / (2 eps_merge^2)) so that selected pairs follow q_merge,
+ * accepted with min(1, e^lambda q_sm(c - c')); a row joins at most one merge
+ * per call (later proposals naming it are withdrawn); the Gaussians of c'
+ * move to c, and live rows are compacted to 0 .. K'-1 (freed rows below K'
+ * take the surviving rows above, ascending).
+ * Deterministic (integer atomics only).  lambda is the prior cost of a row of
+ * this codebook (lambda_SR or lambda_SH). */
+typedef struct {
+    float lambda, eps_split, eps_merge;
+    int32_t n_proposals;
+    uint64_t seed;
+    uint32_t step;
+    uint32_t pad_;
+} cgs_mh;
+
+/* The codebook the moves act on (device pointers): FP32 rows [K_max, ld]
+ * holding D <= 60 values each from column 0; d_rows: device int64, the live
+ * row count K (read and updated on the device); idx [n] int32 row of each
+ * Gaussian; mirror: optional BF16 copy [K_max, mirror_ld] the renderer reads
+ * (rows written by a move are refreshed by round-to-nearest-even) or NULL. */
+typedef struct {
+    float* rows; int64_t ld; int64_t D; int64_t K_max;
+    int64_t* d_rows;
+    int32_t* idx; int64_t n;
+    uint16_t* mirror; int64_t mirror_ld;
+} cgs_mh_codebook;
+
+size_t cgs_mh_workspace_bytes(const cgs_mh_codebook* cb, int32_t n_proposals);
+cgs_status cgs_mh_split(const cgs_mh_codebook* cb, const cgs_mh* p, void* ws, size_t ws_bytes, void* stream);
+cgs_status cgs_mh_merge(const cgs_mh_codebook* cb, const cgs_mh* p, void* ws, size_t ws_bytes, void* stream);
+
+/* Host only: the transition a training step takes under the proposal mixture
+ * (0 parameter update, 1 split, 2 merge with probabilities 0.98 / 0.01 /
+ * 0.01), from uniform24 of word 0 of Philox counter (0, 0, 0x20002, step). */
+int32_t cgs_mh_transition(uint64_t seed, uint32_t step);
 cgs_status cgs_loss_recon(const float* image, const float* target, int32_t n_views, const int32_t* hw,
                           float lambda_ssim, float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
 

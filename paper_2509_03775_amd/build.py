@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip", "train.hip"]
+SOURCES = ["api.hip", "sort.hip", "render_fwd.hip", "render_bwd.hip", "train.hip", "mh.hip"]
 LIB = os.path.join(HERE, "libcgs.so")
 ARCH = os.environ.get("CGS_OFFLOAD_ARCH", "gfx950")
 

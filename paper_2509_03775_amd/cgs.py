@@ -19,7 +19,8 @@ EXPORTS = ("cgs_workspace_bytes", "cgs_render_forward", "cgs_render_backward",
            "cgs_codebook_grad_reduce_workspace_bytes", "cgs_codebook_grad_reduce",
            "cgs_bin_tiles_workspace_bytes", "cgs_bin_tiles", "cgs_loss_l1_workspace_bytes",
            "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version",
-           "cgs_render_backward_sgld", "cgs_sgld_normals", "cgs_loss_recon_workspace_bytes", "cgs_loss_recon")
+           "cgs_render_backward_sgld", "cgs_sgld_normals", "cgs_loss_recon_workspace_bytes", "cgs_loss_recon",
+           "cgs_mh_workspace_bytes", "cgs_mh_split", "cgs_mh_merge", "cgs_mh_transition")
 
 
 class Camera(ctypes.Structure):
@@ -76,6 +77,17 @@ class SceneParams(ctypes.Structure):
                 ("sh", c_void_p), ("sh_stride", c_int32), ("sh_col0", c_int32)]
 
 
+class Mh(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_float), ("eps_split", ctypes.c_float), ("eps_merge", ctypes.c_float),
+                ("n_proposals", c_int32), ("seed", ctypes.c_uint64), ("step", ctypes.c_uint32),
+                ("pad_", ctypes.c_uint32)]
+
+
+class MhCodebook(ctypes.Structure):
+    _fields_ = [("rows", c_void_p), ("ld", c_int64), ("D", c_int64), ("K_max", c_int64), ("d_rows", c_void_p),
+                ("idx", c_void_p), ("n", c_int64), ("mirror", c_void_p), ("mirror_ld", c_int64)]
+
+
 _LIB = None
 
 
@@ -120,6 +132,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cgs_loss_recon.argtypes = [c_void_p, c_void_p, c_int32, POINTER(c_int32), ctypes.c_float, c_void_p, c_void_p,
                                  c_void_p, c_size_t, c_void_p]
     L.cgs_loss_recon.restype = c_int32
+    L.cgs_mh_workspace_bytes.argtypes = [POINTER(MhCodebook), c_int32]
+    L.cgs_mh_workspace_bytes.restype = c_size_t
+    for fn in (L.cgs_mh_split, L.cgs_mh_merge):
+        fn.argtypes = [POINTER(MhCodebook), POINTER(Mh), c_void_p, c_size_t, c_void_p]
+        fn.restype = c_int32
+    L.cgs_mh_transition.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    L.cgs_mh_transition.restype = c_int32
     L.cgs_workspace_layout.argtypes = [pb, POINTER(WsLayout)]
     L.cgs_workspace_layout.restype = c_int32
     L.cgs_status_str.argtypes = [c_int32]
@@ -214,6 +233,22 @@ def loss_recon_workspace_bytes(hw) -> int:
 def loss_recon(image, target, hw, lambda_ssim, grad, loss, ws, ws_bytes, stream) -> None:
     check("cgs_loss_recon", load().cgs_loss_recon(image, target, len(hw), _hw_array(hw), lambda_ssim, grad, loss,
                                                   ws, ws_bytes, stream))
+
+
+def mh_workspace_bytes(cb: MhCodebook, n_proposals: int) -> int:
+    return load().cgs_mh_workspace_bytes(ctypes.byref(cb), n_proposals)
+
+
+def mh_split(cb: MhCodebook, p: Mh, ws, ws_bytes, stream) -> None:
+    check("cgs_mh_split", load().cgs_mh_split(ctypes.byref(cb), ctypes.byref(p), ws, ws_bytes, stream))
+
+
+def mh_merge(cb: MhCodebook, p: Mh, ws, ws_bytes, stream) -> None:
+    check("cgs_mh_merge", load().cgs_mh_merge(ctypes.byref(cb), ctypes.byref(p), ws, ws_bytes, stream))
+
+
+def mh_transition(seed: int, step: int) -> int:
+    return load().cgs_mh_transition(seed, step)
 
 
 def workspace_layout(batch: Batch) -> WsLayout:

@@ -39,6 +39,10 @@ hipError_t launch_l1(const float*, const float*, int64_t, float*, float*, float*
 hipError_t launch_loss_recon(const LossViews&, const float*, const float*, float, float*, float*, float*, double*,
                              hipStream_t);
 hipError_t launch_normals(int64_t, uint64_t, uint32_t, uint32_t, uint64_t, float*, uint32_t*, hipStream_t);
+size_t mh_workspace(int64_t, int64_t, int64_t, int64_t, MhWs*, char*);
+hipError_t mh_split(const MhArgs&, const MhWs&, hipStream_t);
+hipError_t mh_merge(const MhArgs&, const MhWs&, hipStream_t);
+int mh_transition_host(uint64_t, uint32_t);
 
 namespace {
 
@@ -658,6 +662,61 @@ cgs_status cgs_loss_recon(const float* image, const float* target, int32_t n_vie
     return hip_status(cgs::launch_loss_recon(lv, image, target, lambda_ssim, grad, loss, part, sums,
                                              static_cast<hipStream_t>(stream)));
 }
+
+namespace {
+// Host checks of a codebook under MH moves; fills the kernel arguments.
+bool mh_args(const cgs_mh_codebook* cb, const cgs_mh* p, cgs::MhArgs* a) {
+    if (!cb || !p || !cb->rows || !cb->d_rows) return false;
+    if (cb->D < 1 || cb->D > 60 || cb->ld < cb->D || cb->K_max < 1 || cb->K_max >= ((int64_t)1 << 31)) return false;
+    if (cb->n < 0 || cb->n >= ((int64_t)1 << 31) || (cb->n > 0 && !cb->idx)) return false;
+    if (cb->mirror && cb->mirror_ld < cb->D) return false;
+    if (p->n_proposals < 1 || !(p->lambda >= 0.f && p->lambda < 1e30f)) return false;
+    if (!(p->eps_split > 0.f && p->eps_split < 1e30f) || !(p->eps_merge > 0.f && p->eps_merge < 1e30f)) return false;
+    a->rows = cb->rows;
+    a->ld = cb->ld;
+    a->D = cb->D;
+    a->K_max = cb->K_max;
+    a->n = cb->n;
+    a->d_rows = cb->d_rows;
+    a->idx = cb->idx;
+    a->mirror = cb->mirror;
+    a->mirror_ld = cb->mirror_ld;
+    a->lambda = p->lambda;
+    a->inv_s2 = (float)(1.0 / ((double)p->eps_split * p->eps_split));
+    a->inv_m2 = (float)(1.0 / ((double)p->eps_merge * p->eps_merge));
+    a->eps_split = p->eps_split;
+    a->B = p->n_proposals;
+    a->seed = p->seed;
+    a->step = p->step;
+    return true;
+}
+}  // namespace
+
+size_t cgs_mh_workspace_bytes(const cgs_mh_codebook* cb, int32_t n_proposals) {
+    if (!cb || n_proposals < 1 || cb->D < 1 || cb->K_max < 1 || cb->n < 0) return 0;
+    return cgs::mh_workspace(n_proposals, cb->D, cb->K_max, cb->n, nullptr, nullptr);
+}
+
+static cgs_status mh_run(const cgs_mh_codebook* cb, const cgs_mh* p, void* ws, size_t ws_bytes, void* stream,
+                         bool split) {
+    cgs::MhArgs a;
+    if (!mh_args(cb, p, &a) || !ws) return CGS_EINVAL;
+    cgs::MhWs w;
+    const size_t need = cgs::mh_workspace(a.B, a.D, a.K_max, a.n, &w, static_cast<char*>(ws));
+    if (ws_bytes < need) return CGS_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return hip_status(split ? cgs::mh_split(a, w, st) : cgs::mh_merge(a, w, st));
+}
+
+cgs_status cgs_mh_split(const cgs_mh_codebook* cb, const cgs_mh* p, void* ws, size_t ws_bytes, void* stream) {
+    return mh_run(cb, p, ws, ws_bytes, stream, true);
+}
+
+cgs_status cgs_mh_merge(const cgs_mh_codebook* cb, const cgs_mh* p, void* ws, size_t ws_bytes, void* stream) {
+    return mh_run(cb, p, ws, ws_bytes, stream, false);
+}
+
+int32_t cgs_mh_transition(uint64_t seed, uint32_t step) { return cgs::mh_transition_host(seed, step); }
 
 cgs_status cgs_sgld_normals(int64_t n, uint64_t index0, uint32_t tag, uint32_t step, uint64_t seed, float* z,
                             uint32_t* words, void* stream) {

@@ -90,6 +90,26 @@ struct LossViews {
     int64_t tile_off[CGS_MAX_VIEWS + 1];
 };
 
+// Arguments and workspace of the Metropolis-Hastings codebook moves.
+struct MhArgs {
+    float* rows;
+    int64_t ld, D, K_max, n;
+    int64_t* d_rows;
+    int32_t* idx;
+    uint16_t* mirror;
+    int64_t mirror_ld;
+    float lambda, inv_s2, inv_m2;   // lambda, 1/eps_split^2, 1/eps_merge^2
+    float eps_split;
+    int64_t B;
+    uint64_t seed;
+    uint32_t step;
+};
+struct MhWs {
+    uint32_t *mark, *acc, *s0, *s1, *valid, *rank, *partner, *flag, *scan, *hole_of, *fin;
+    float* u;
+    unsigned long long *tot, *bsum;
+};
+
 // Device counters kept in the workspace.
 struct DevCounters {
     unsigned long long n_inst;     // instances needed

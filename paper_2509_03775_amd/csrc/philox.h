@@ -15,18 +15,27 @@
 
 namespace cgs {
 
-__device__ inline uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1) {
+__host__ __device__ inline uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r > 0) {
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, x.x), lo0 = 0xD2511F53u * x.x;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x.z), lo1 = 0xCD9E8D57u * x.z;
-        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x.x, p1 = (uint64_t)0xCD9E8D57u * x.z;
+        x = make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
     }
     return x;
+}
+
+// ((w >> 8) + 1/2) 2^-24: a uniform in (0, 1), exact in FP32.
+__host__ __device__ inline float uniform24(uint32_t w) {
+    return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-08f;
+}
+
+// floor(w n / 2^32): an integer uniform over [0, n) from a word, exact.
+__host__ __device__ inline uint32_t choice32(uint32_t w, uint32_t n) {
+    return (uint32_t)(((uint64_t)w * n) >> 32);
 }
 
 __device__ inline void box_muller_pair(uint32_t wa, uint32_t wb, float& z0, float& z1) {

@@ -313,6 +313,38 @@ def sgld_params(scene, master_sr: Optional[torch.Tensor] = None,
     return p
 
 
+class CodebookMoves:
+    """A codebook under the Metropolis-Hastings split / merge moves: FP32 rows
+    [K_max, ld] (D values from column 0), the live row count on the device,
+    the Gaussians' row indices, an optional BF16 copy the renderer reads."""
+
+    def __init__(self, rows: torch.Tensor, n_live: int, idx: torch.Tensor, D: Optional[int] = None,
+                 mirror: Optional[torch.Tensor] = None, n_proposals: int = 4096):
+        assert rows.dtype == torch.float32 and rows.is_contiguous() and idx.dtype == torch.int32
+        self.rows, self.idx, self.mirror = rows, idx, mirror
+        self.d_rows = torch.tensor([n_live], dtype=torch.int64, device=rows.device)
+        self.cb = cgs.MhCodebook(rows.data_ptr(), int(rows.shape[1]), int(D or rows.shape[1]), int(rows.shape[0]),
+                                 self.d_rows.data_ptr(), idx.data_ptr(), int(idx.numel()),
+                                 None if mirror is None else mirror.data_ptr(),
+                                 0 if mirror is None else int(mirror.shape[1]))
+        self.n_proposals = n_proposals
+        nb = cgs.mh_workspace_bytes(self.cb, n_proposals)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=rows.device)
+
+    def params(self, lam: float, eps_split: float, eps_merge: float, seed: int, step: int) -> "cgs.Mh":
+        return cgs.Mh(lam, eps_split, eps_merge, self.n_proposals, seed, step, 0)
+
+    def split(self, p: "cgs.Mh", stream=None) -> None:
+        cgs.mh_split(self.cb, p, self.ws.data_ptr(), self.ws.numel(), _stream_ptr(stream))
+
+    def merge(self, p: "cgs.Mh", stream=None) -> None:
+        cgs.mh_merge(self.cb, p, self.ws.data_ptr(), self.ws.numel(), _stream_ptr(stream))
+
+    def live_rows(self) -> int:
+        """Live row count (synchronises)."""
+        return int(self.d_rows.item())
+
+
 def loss_recon(image: torch.Tensor, target: torch.Tensor, hw: Sequence[Sequence[int]], lambda_ssim: float,
                grad: torch.Tensor, loss: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
     """Eq. 4's (1 - lambda) L1 + lambda (1 - SSIM) and its gradient (writes

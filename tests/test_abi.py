@@ -163,3 +163,32 @@ def test_sgld_normals_validation():
     assert L.cgs_sgld_normals(-1, 0, 0, 0, 0, 0x1, None, None) == cgs.CGS_EINVAL
     assert L.cgs_sgld_normals(4, 0, 0, 0, 0, None, None, None) == cgs.CGS_EINVAL
     assert L.cgs_sgld_normals(0, 0, 0, 0, 0, None, None, None) == cgs.CGS_OK
+
+
+def test_mh_transition_matches_oracle():
+    """The host-side transition choice (Philox on the host) against the oracle."""
+    from oracle import mh
+    names = {0: "update", 1: "split", 2: "merge"}
+    for seed in (0, 777, 2 ** 40 + 3):
+        assert all(names[cgs.mh_transition(seed, s)] == mh.transition(seed, s) for s in range(3000))
+
+
+def test_mh_validation():
+    L = cgs.load()
+    cb = cgs.MhCodebook(0x1000, 8, 7, 100, 0x2000, 0x3000, 500, None, 0)
+    p = cgs.Mh(2.3, 0.1, 0.05, 64, 1, 2, 0)
+    need = L.cgs_mh_workspace_bytes(ctypes.byref(cb), 64)
+    assert need > 0
+    for fn in (L.cgs_mh_split, L.cgs_mh_merge):
+        assert fn(ctypes.byref(cb), ctypes.byref(p), 0x4, need - 1, None) == cgs.CGS_EWORKSPACE
+        for field, value in (("D", 61), ("D", 0), ("ld", 6), ("K_max", 0), ("n", -1)):
+            bad = cgs.MhCodebook.from_buffer_copy(cb)
+            setattr(bad, field, value)
+            assert fn(ctypes.byref(bad), ctypes.byref(p), 0x4, need, None) == cgs.CGS_EINVAL, field
+        for field, value in (("eps_split", 0.0), ("eps_merge", -1.0), ("lambda_", -0.5), ("n_proposals", 0)):
+            bad = cgs.Mh.from_buffer_copy(p)
+            setattr(bad, field, value)
+            assert fn(ctypes.byref(cb), ctypes.byref(bad), 0x4, need, None) == cgs.CGS_EINVAL, field
+        nomirror_ld = cgs.MhCodebook.from_buffer_copy(cb)
+        nomirror_ld.mirror = 0x5000
+        assert fn(ctypes.byref(nomirror_ld), ctypes.byref(p), 0x4, need, None) == cgs.CGS_EINVAL
