@@ -253,7 +253,7 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
     # target_s, so the fixed cost is spread as it would be over a larger sample
     n = 2
     dt, npix, ntiles = run(n)
-    while dt < 0.5 * target_s and n < 4096:
+    while dt < 0.8 * target_s and n < 4096:
         n = int(min(4096, max(2 * n, n * 0.9 * target_s / max(dt, 1e-3))))
         dt, npix, ntiles = run(n)
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
@@ -328,6 +328,33 @@ def uncompressed_workload(wl: sc.Workload) -> sc.Workload:
     return sc.Workload(wl.name + ":uncompressed", scenes, wl.cameras, wl.view_scene, wl.targets, wl.bf16)
 
 
+def time_moves(wl: sc.Workload, n_proposals: int = 4096, reps: int = 10) -> dict:
+    """Split and merge moves on the workload's first codebook (FP32 master
+    with room for 2K rows, BF16 copy refreshed): mean ms per call over `reps`
+    calls of each, the state carried from call to call."""
+    s = wl.scenes[0]
+    K, R = s.cb.shape
+    rows = torch.zeros((2 * K, R), dtype=torch.float32, device="cuda")
+    rows[:K] = torch.from_numpy(np.ascontiguousarray(s.cb)).cuda()
+    mirror = torch.zeros((2 * K, R), dtype=torch.int16, device="cuda")
+    idx = torch.from_numpy(np.ascontiguousarray(s.idx)).cuda()
+    mv = render.CodebookMoves(rows, K, idx, mirror=mirror, n_proposals=n_proposals)
+    out = {"gaussians": s.n, "rows": int(K), "row_width": int(R), "proposals": n_proposals}
+    for kind in ("split", "merge"):
+        fn = mv.split if kind == "split" else mv.merge
+        fn(mv.params(2.3, 0.1, 0.05, 1, 0))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(reps):
+            fn(mv.params(2.3, 0.1, 0.05, 1, 1 + k))
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{kind}_ms"] = e0.elapsed_time(e1) / reps
+    out["live_rows_after"] = mv.live_rows()
+    return out
+
+
 def time_graph(form: "Form", steps: int) -> float:
     """One step captured in a HIP graph, replayed `steps` times."""
     form.step()
@@ -358,7 +385,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default=HEADLINE)
-    ap.add_argument("--extra-forms", default="train,fp32_plain,1m,uncompressed,uneven16,graph",
+    ap.add_argument("--extra-forms", default="train,mh,fp32_plain,1m,uncompressed,uneven16,graph",
                     help="comma list of: fp32_plain, 1m, uncompressed, uneven16, graph; or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -438,6 +465,9 @@ def main():
             "sgld_epilogues_ms": (st2["chain"] + st2["codebook_reduce"]) - (stages["chain"] + stages["codebook_reduce"])}
         del f, ev2
         torch.cuda.empty_cache()
+    if "mh" in extras:
+        log("[bench] timing the split and merge moves")
+        extra_info["mh_moves"] = time_moves(wl)
     if "uncompressed" in extras:
         log(f"[bench] timing {args.workload} uncompressed (K = N)")
         wu = uncompressed_workload(wl)
