@@ -98,6 +98,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _LIB
     if not os.path.exists(path):
         raise RuntimeError(f"libcgs not built: {path} is missing (run paper_2509_03775_amd/build.py)")
+    # torch ships its own HIP runtime: load it first so that libcgs binds to
+    # the same runtime (and device context) as the tensors it is given
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     pb = POINTER(Batch)
     L.cgs_workspace_bytes.argtypes = [pb]

@@ -24,10 +24,10 @@ hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, c
 hipError_t launch_plain_keys(const uint32_t*, const uint32_t*, const uint32_t*, const DevCounters*, int64_t,
                              uint64_t*, uint32_t*, hipStream_t);
 hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            float*, float*, int32_t*, int32_t*, hipStream_t);
+                            uint8_t*, float*, float*, int32_t*, int32_t*, hipStream_t);
 hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            const uint32_t*, const uint32_t*, const float*, const float*, const int32_t*, float*,
-                            uint2*, hipStream_t);
+                            const uint8_t*, const uint32_t*, const uint32_t*, const float*, const float*,
+                            const int32_t*, float*, uint2*, hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, int64_t, const float*, const uint32_t*, const uint32_t*,
                         const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, float*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
@@ -223,6 +223,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     for (int i = 0; i < 2; ++i) { p.inst_key[i] = take(4 * (size_t)cap); p.inst_val[i] = take(4 * (size_t)cap); }
     p.tile_range = take(8 * (size_t)T);
     p.tile_cut = take(8 * (size_t)T);
+    p.qbits = take((size_t)cap);
     for (int i = 0; i < 2; ++i) { p.tperm_key[i] = take(4 * (size_t)T); p.tperm_val[i] = take(4 * (size_t)T); }
     const int64_t nmax = std::max(std::max(R, cap), G);
     p.radix_blocks_max = (nmax + kSortTile - 1) / kSortTile;
@@ -356,7 +357,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     }
     CGS_TRY(mark(h, 2, st));
     CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
-                             at<float4>(ws, p.rec), image, T_final, n_last, h.n_blend, st));
+                             at<float4>(ws, p.rec), at<uint8_t>(ws, p.qbits), image, T_final, n_last, h.n_blend, st));
     CGS_TRY(mark(h, 3, st));
     return CGS_OK;
 }
@@ -438,7 +439,8 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     CGS_TRY(mark(h, 4, st));
     float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
-                             at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key), at<uint32_t>(ws, p.slot_off),
+                             at<float4>(ws, p.rec), at<const uint8_t>(ws, p.qbits), at<uint32_t>(ws, p.depth_key),
+                             at<uint32_t>(ws, p.slot_off),
                              grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);

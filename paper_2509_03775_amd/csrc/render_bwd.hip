@@ -10,8 +10,9 @@ namespace cgs {
 
 // ------------------------------------------------------------ backward blend
 // One wavefront per tile, same pixel mapping and quadrant skipping as the
-// forward.  Each pixel walks its list from n_last-1 down to 0, re-derives
-// alpha with the forward's code, recovers T before the Gaussian as
+// forward (with the quadrant masks the forward stored per list position).
+// Each pixel walks its list from n_last-1 down to 0, re-derives alpha with
+// the forward's code, recovers T before the Gaussian as
 // T_after / (1 - alpha), and accumulates dL/d(u, v, -A/2, -B, -C/2, opacity,
 // r, g, b).  The lane's four pixels are summed in registers, each 16-lane row
 // by DPP shifts, and the four row partials of every record are added once per
@@ -28,6 +29,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
                                                          const float4* __restrict__ rec,
+                                                         const uint8_t* __restrict__ qbits,
                                                          const uint32_t* __restrict__ depth_key,
                                                          const uint32_t* __restrict__ slot_off,
                                                          const float* __restrict__ grad_image,
@@ -47,8 +49,6 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     const int64_t lt = tile - vd.tile_off;
     const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
     const int x0 = tx * kTile, y0 = ty * kTile;
-    const float bx0 = (float)x0, by0 = (float)y0;
-    const float bxm = (float)min(x0 + kTile - 1, vd.W - 1), bym = (float)min(y0 + kTile - 1, vd.H - 1);
 
     float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpx[4], fpy[4];
     uint32_t last[4];
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             const uint32_t rlo = __float_as_uint(x.y), rhi = __float_as_uint(x.z);
             const int rx0 = (int)(rlo & 0xffffu), ry0 = (int)(rlo >> 16), rx1 = (int)(rhi & 0xffffu);
             slot = (int64_t)slot_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
-            qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
+            qm = qbits[start + li];     // the forward's quadrant mask of this record
         }
         const uint64_t km = __ballot(qm != 0u);
         const uint32_t mine = popc_below(km);
@@ -696,19 +696,20 @@ __global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
-                            const uint32_t* inst_rec, const float4* rec, const uint32_t* dk, const uint32_t* eo,
+                            const uint32_t* inst_rec, const float4* rec, const uint8_t* qbits, const uint32_t* dk,
+                            const uint32_t* eo,
                             const float* grad_image, const float* T_final, const int32_t* n_last, float* ginst,
                             uint2* cut, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (wpb == 1) {
         hipLaunchKernelGGL(k_blend_bwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rec,
-                           dk, eo, grad_image, T_final, n_last, ginst, cut);
+                           qbits, dk, eo, grad_image, T_final, n_last, ginst, cut);
     } else if (wpb == 2) {
         hipLaunchKernelGGL(k_blend_bwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
-                           inst_rec, rec, dk, eo, grad_image, T_final, n_last, ginst, cut);
+                           inst_rec, rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut);
     } else {
         hipLaunchKernelGGL(k_blend_bwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
-                           inst_rec, rec, dk, eo, grad_image, T_final, n_last, ginst, cut);
+                           inst_rec, rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut);
     }
     return hipGetLastError();
 }

@@ -191,11 +191,15 @@ __global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__
 // dropped, the rest are packed in order into LDS (ballot prefix) and read
 // back as wave-uniform broadcasts; a quadrant the record cannot reach is
 // skipped by the whole wave.  List positions are kept, so n_last is unchanged.
+// The quadrant mask of each list position is also stored for the backward
+// (qbits, one byte per position, written up to where every pixel of the tile
+// has terminated).
 template <int WPB, bool STATS>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
                                                          const float4* __restrict__ rec,
+                                                         uint8_t* __restrict__ qbits,
                                                          float* __restrict__ image, float* __restrict__ T_final,
                                                          int32_t* __restrict__ n_last, int32_t* __restrict__ n_blend) {
     __shared__ float4 s_g[WPB][64];
@@ -239,12 +243,12 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
             qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
         }
         const uint64_t km = __ballot(qm != 0u);
+        const uint32_t mine = popc_below(km);
         if (qm != 0u) {
-            const uint32_t slot = popc_below(km);
-            s_g[w][slot] = g;
-            s_c[w][slot] = c;
-            s_b[w][slot] = bl;
-            s_p[w][slot] = ((idx - start + 1u) << 4) | qm;
+            s_g[w][mine] = g;
+            s_c[w][mine] = c;
+            s_b[w][mine] = bl;
+            s_p[w][mine] = ((idx - start + 1u) << 4) | qm;
         }
         wave_sync();
         const int cnt = (int)__popcll(km);
@@ -276,6 +280,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
                 if constexpr (STATS) ++nb[k];
             }
         }
+        if (idx < end) qbits[idx] = (uint8_t)qm;
         wave_sync();
     }
 #pragma unroll
@@ -357,11 +362,11 @@ hipError_t launch_plain_keys(const uint32_t* stile, const uint32_t* sgid, const 
 }
 
 hipError_t launch_blend_fwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
-                            const uint32_t* inst_rec, const float4* rec,
+                            const uint32_t* inst_rec, const float4* rec, uint8_t* qbits,
                             float* image, float* T_final, int32_t* n_last, int32_t* n_blend, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
 #define CGS_BF(W, S) hipLaunchKernelGGL((k_blend_fwd<W, S>), dim3((unsigned)((n_tiles + W - 1) / W)), dim3(W * 64), \
-                                        0, st, d_desc, ranges, inst_rec, rec, image, T_final, n_last, n_blend)
+                                        0, st, d_desc, ranges, inst_rec, rec, qbits, image, T_final, n_last, n_blend)
     if (n_blend) {
         if (wpb == 1) CGS_BF(1, true); else if (wpb == 2) CGS_BF(2, true); else CGS_BF(4, true);
     } else {
