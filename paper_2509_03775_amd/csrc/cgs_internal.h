@@ -184,6 +184,13 @@ __device__ inline float row16_sum(float v) {
     return v;
 }
 
+// Bitwise OR over the 64 lanes (every lane must be active); valid in all lanes.
+__device__ inline uint32_t wave_or_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v |= (uint32_t)__shfl_xor((int)v, d, 64);
+    return v;
+}
+
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
     for (int d = 32; d >= 1; d >>= 1) {
         uint32_t o = (uint32_t)__shfl_xor((int)v, d, 64);

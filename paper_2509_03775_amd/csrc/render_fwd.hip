@@ -193,7 +193,8 @@ __global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__
 // skipped by the whole wave.  List positions are kept, so n_last is unchanged.
 // The quadrant mask of each list position is also stored for the backward
 // (qbits, one byte per position, written up to where every pixel of the tile
-// has terminated).
+// has terminated), or 0 when no pixel of the tile blended the record: the
+// backward then skips it without re-deriving alpha.
 template <int WPB, bool STATS>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
         }
         wave_sync();
         const int cnt = (int)__popcll(km);
+        uint32_t hit_lo = 0u, hit_hi = 0u;     // staged records this lane blended (bit j)
         for (int j = 0; j < cnt; ++j) {
             if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
             const float4 gg = s_g[w][j];
@@ -279,8 +281,14 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
                 last[k] = pos;
                 if constexpr (STATS) ++nb[k];
             }
+            // a pixel blended this record iff its last position is now this one
+            const uint32_t hit = ((last[0] == pos) | (last[1] == pos) | (last[2] == pos) | (last[3] == pos)) ? 1u : 0u;
+            if (j < 32) hit_lo |= hit << j; else hit_hi |= hit << (j - 32);
         }
-        if (idx < end) qbits[idx] = (uint8_t)qm;
+        hit_lo = wave_or_u32(hit_lo);
+        hit_hi = wave_or_u32(hit_hi);
+        const uint32_t blended = mine < 32 ? (hit_lo >> mine) & 1u : (hit_hi >> (mine - 32)) & 1u;
+        if (idx < end) qbits[idx] = (qm != 0u && blended) ? (uint8_t)qm : (uint8_t)0;
         wave_sync();
     }
 #pragma unroll
