@@ -29,7 +29,8 @@ hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, con
                             const uint8_t*, const uint32_t*, const uint32_t*, const float*, const float*,
                             const int32_t*, float*, uint2*, hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, int64_t, const float*, const uint32_t*, const uint32_t*,
-                        const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, float*, hipStream_t);
+                        const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*, float*,
+                        hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
@@ -233,6 +234,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.slot_off = take(4 * (size_t)R);
     p.ginst = take(4 * 9 * (size_t)cap);
     p.rec_grad = take(4 * 9 * (size_t)R);
+    p.rec_flag = take(8 * (size_t)d.n_rec_waves + 8);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
     p.row_start = take(8 * (size_t)(h->rows_total + 1));
@@ -446,7 +448,8 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     float* gth = at<float>(ws, p.gtheta);
     CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.slot_off),
                          at<uint32_t>(ws, p.ntiles), at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key),
-                         at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), gth, st));
+                         at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), at<uint32_t>(ws, p.rec_flag),
+                         gth, st));
     CGS_TRY(mark(h, 6, st));
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
     uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};

@@ -126,7 +126,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
     size_t radix_counts, scan_bsum;
-    size_t slot_off, ginst, rec_grad, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t slot_off, ginst, rec_grad, rec_flag, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t radix_blocks_max, scan_blocks_max;
 };

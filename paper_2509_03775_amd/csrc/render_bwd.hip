@@ -208,7 +208,9 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // record's tile slots, in row-major tile order (slots of consecutive records
 // are adjacent: coalesced reads), over the tiles whose backward walk reached
 // the record -- (depth key, record) ordered before the tile's cut.  Written
-// as 9 floats per record; zeros when no tile reached it.
+// as 9 floats per record, only for records with a nonzero sum; a bit per
+// record (two words per wavefront, records of one view per wavefront) says
+// which, so records no walk reached cost neither a write nor a read.
 __device__ const float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
 __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                                                   const uint2* __restrict__ tile_rect,
                                                   const uint32_t* __restrict__ depth_key,
                                                   const uint2* __restrict__ tile_cut,
-                                                  const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad) {
+                                                  const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad,
+                                                  uint32_t* __restrict__ rec_flag) {
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_rec_waves) return;
     const ViewDesc& vd = desc->views[find_view_by_wave(desc, wv)];
@@ -258,9 +261,19 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                 for (int i = 0; i < 9; ++i) d[i] += src[j][i];
         }
     }
-    float* out = rec_grad + 9 * r;
+    bool nz = false;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i] = d[i];
+    for (int k = 0; k < 9; ++k) nz |= d[k] != 0.f;
+    const uint64_t m = __ballot(nz);
+    if ((threadIdx.x & 63) == 0) {
+        rec_flag[2 * wv] = (uint32_t)m;
+        rec_flag[2 * wv + 1] = (uint32_t)(m >> 32);
+    }
+    if (nz) {
+        float* out = rec_grad + 9 * r;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[k] = d[k];
+    }
 }
 
 // ------------------------------------------------------------ SGLD update
@@ -320,6 +333,7 @@ __device__ inline void sgld_row(const BatchDesc* desc, int s, int64_t lr, int gc
 // the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
 template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ rec_grad,
+                                               const uint32_t* __restrict__ rec_flag,
                                                float* __restrict__ gtheta) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
@@ -356,10 +370,15 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
     // dL/d(record) of the next view is loaded while this view's math runs
     float dn[9];
     auto load_rec = [&](int vi, float* out9) {
-        const int64_t r = desc->views[desc->view_list[sd.vfirst + vi]].rec_off + g;
-        const float* src = rec_grad + 9 * r;
+        const ViewDesc& v = desc->views[desc->view_list[sd.vfirst + vi]];
+        const int64_t fw = 2 * (v.rec_wave_off + (g >> 6)) + ((g >> 5) & 1);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out9[i] = src[i];
+        for (int i = 0; i < 9; ++i) out9[i] = 0.f;
+        if ((rec_flag[fw] >> (g & 31)) & 1u) {      // no load for records with a zero sum
+            const float* src = rec_grad + 9 * (v.rec_off + g);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) out9[i] = src[i];
+        }
     };
     if (sd.vcount > 0) load_rec(0, dn);
 
@@ -716,13 +735,14 @@ hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, c
 
 hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, int64_t n_rec_waves,
                         const float* ginst, const uint32_t* eo, const uint32_t* nt, const uint2* tr, const uint32_t* dk,
-                        const uint2* cut, const DevCounters* cnt, float* rec_grad, float* gtheta, hipStream_t st) {
+                        const uint2* cut, const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, float* gtheta,
+                        hipStream_t st) {
     if (n_rec_waves > 0)
         hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
-                           nt, tr, dk, cut, cnt, rec_grad);
+                           nt, tr, dk, cut, cnt, rec_grad, rec_flag);
     if (n_gauss_waves <= 0) return hipGetLastError();
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, gtheta)
+#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_CH(CGS_F32, 0); break; case 1: CGS_CH(CGS_F32, 1); break;
                        case 2: CGS_CH(CGS_F32, 2); break; default: CGS_CH(CGS_F32, 3); break; }
