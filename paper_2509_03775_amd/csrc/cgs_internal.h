@@ -184,6 +184,28 @@ __device__ inline float row16_sum(float v) {
     return v;
 }
 
+// Sum over the 64 lanes into lane 63 (every lane must be active): row sums
+// by DPP shifts, then lane 15 of each row into the next row, then lane 31
+// into rows 2-3, giving ((r3 + r2) + (r1 + r0)) in lane 63 (other lanes hold
+// partial sums; the broadcasts use all row masks so each step is one fused
+// DPP add).
+__device__ inline float wave_sum_to_63(float v) {
+    int x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xf, 0xf, true));   // row_bcast:15
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xf, 0xf, true));   // row_bcast:31
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+
 // Bitwise OR over the 64 lanes (every lane must be active); valid in all lanes.
 __device__ inline uint32_t wave_or_u32(uint32_t v) {
 #pragma unroll

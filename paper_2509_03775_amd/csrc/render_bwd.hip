@@ -14,9 +14,9 @@ namespace cgs {
 // Each pixel walks its list from n_last-1 down to 0, re-derives alpha with
 // the forward's code, recovers T before the Gaussian as
 // T_after / (1 - alpha), and accumulates dL/d(u, v, -A/2, -B, -C/2, opacity,
-// r, g, b).  The lane's four pixels are summed in registers, each 16-lane row
-// by DPP shifts, and the four row partials of every record are added once per
-// batch by the lane that loaded the record.  The tile's total for a record
+// r, g, b).  The lane's four pixels are summed in registers, then over the
+// wave by DPP row shifts and row broadcasts into lane 63, which parks the
+// record's nine sums in LDS for the lane that loaded the record.  The tile's total for a record
 // goes to that (tile, record) instance's own slot -- the record's slot offset
 // (tile counts scanned in record order) + the tile's row-major index in the
 // record's rectangle -- with plain
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
     __shared__ uint32_t s_p[WPB][64];
-    __shared__ float s_o[WPB][64][4][9];
+    __shared__ float s_o[WPB][64][9];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
     if (tile >= desc->n_tiles) return;
@@ -87,8 +87,6 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         }
         tile_cut[tile] = cut;
     }
-    const int row = lane >> 4;
-    const bool row_end = (lane & 15) == 15;
     for (int64_t bend = maxlast; bend > 0; bend -= 64) {
         const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
         const int64_t li = bbeg + lane;
@@ -165,16 +163,16 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 a_u += dpx;
                 a_v += dpy;
             }
-            float* so = &s_o[w][j][row][0];
+            float* so = &s_o[w][j][0];
             if (any) {
-                const float s0 = row16_sum(a_u), s1 = row16_sum(a_v), s2 = row16_sum(a_a);
-                const float s3 = row16_sum(a_b), s4 = row16_sum(a_c), s5 = row16_sum(a_o);
-                const float s6 = row16_sum(a_r), s7 = row16_sum(a_g), s8 = row16_sum(a_bl);
-                if (row_end) {
+                const float s0 = wave_sum_to_63(a_u), s1 = wave_sum_to_63(a_v), s2 = wave_sum_to_63(a_a);
+                const float s3 = wave_sum_to_63(a_b), s4 = wave_sum_to_63(a_c), s5 = wave_sum_to_63(a_o);
+                const float s6 = wave_sum_to_63(a_r), s7 = wave_sum_to_63(a_g), s8 = wave_sum_to_63(a_bl);
+                if (lane == 63) {
                     so[0] = s0; so[1] = s1; so[2] = s2; so[3] = s3; so[4] = s4;
                     so[5] = s5; so[6] = s6; so[7] = s7; so[8] = s8;
                 }
-            } else if (row_end) {
+            } else if (lane == 63) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) so[k] = 0.f;
             }
@@ -185,8 +183,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             if (qm != 0u) {
                 float t9[9];
 #pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    t9[k] = ((s_o[w][mine][0][k] + s_o[w][mine][1][k]) + s_o[w][mine][2][k]) + s_o[w][mine][3][k];
+                for (int k = 0; k < 9; ++k) t9[k] = s_o[w][mine][k];
                 // natural-log conic entries of this lane's record
                 const float na2 = 2.f * kLn2 * g.z, nb = kLn2 * g.w, nc2 = 2.f * kLn2 * c.x;
                 const float sx = t9[0], sy = t9[1];
