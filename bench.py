@@ -51,8 +51,8 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", "render_common.h", "cgs_internal.h"),
                   "k_blend_fwd": ("render_fwd.hip", "render_common.h", "cgs_internal.h")}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "a8b46ae67f5f75d4", "read": 3241930418, "write": 729442112},
-    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "05d29d67d967991e", "read": 1542154568, "write": 217980640},
+    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "5bcca90c1c48c0a8", "read": 3310743144, "write": 867149216},
+    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "907e62775376a00b", "read": 1547464965, "write": 234997992},
 }
 
 

@@ -167,23 +167,6 @@ __device__ inline float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Sum over each 16-lane row (every lane must be active); lane 15 of each row
-// (lanes 15, 31, 47, 63) receives its row's total.
-__device__ inline float row16_sum(float v) {
-    int x = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));  // row_shr:1
-    x = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));  // row_shr:2
-    x = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
-    x = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));  // row_shr:8
-    // keep the last add next to its shift (one DPP add) instead of letting it
-    // sink into the caller's lane-15 branch as a separate move and add
-    __asm__ volatile("" : "+v"(v));
-    return v;
-}
-
 // Sum over the 64 lanes into lane 63 (every lane must be active): row sums
 // by DPP shifts, then lane 15 of each row into the next row, then lane 31
 // into rows 2-3, giving ((r3 + r2) + (r1 + r0)) in lane 63 (other lanes hold
