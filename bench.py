@@ -51,8 +51,8 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", "render_common.h", "cgs_internal.h"),
                   "k_blend_fwd": ("render_fwd.hip", "render_common.h", "cgs_internal.h")}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "5bcca90c1c48c0a8", "read": 3310743144, "write": 867149216},
-    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "907e62775376a00b", "read": 1547464965, "write": 234997992},
+    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "2922ff3cbc53377d", "read": 3310623514, "write": 867182816},
+    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "b61c13f0588924ee", "read": 1547753823, "write": 235022168},
 }
 
 
@@ -277,8 +277,12 @@ def blend_roofline(stage, ms, e_eval, e_blend, workload, schedule):
 def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     """Algorithmic HBM bytes of one step, per stage: what the method must
     read and write once (codebook rows counted once per unique row; radix
-    passes at 20 B per item: key+value in and out plus the key histogram
-    read).  The blends read only the walked instances W (positions before
+    passes at 16 B per item: key+value in and out, plus one 4 B key read per
+    sort for the digit counts of all its passes).  Binning: the depth sort
+    (its last pass writes no keys but gathers each record's 8 B rectangle
+    and writes it with its 4 B count), the offsets scan (8 B per record),
+    the emission (20 B in per record, 8 B out per instance), the slot-offset
+    scan (8 B per record) and the tile sort.  The blends read only the walked instances W (positions before
     the tile's termination): a 4 B record id plus the record's 36 B of blend
     data each; the backward adds the record's tile rectangle and slot offset
     (12 B) and writes a 36 B gradient slot; the chain rule reads those slots
@@ -295,12 +299,12 @@ def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     row_passes = (max(1, (K - 1).bit_length()) + 7) // 8
     out = {
         "preprocess": N * 16 + K * RW * b + Rrec * 52,
-        "binning": 4 * 20 * Rrec + Rrec * 20 + Rrec * 12 + Rrec * 16 + M * 8 + tile_passes * 20 * M + Rrec * 8,
+        "binning": (4 * 16 + 20 + 8 + 20 + 8) * Rrec + (8 + 4 + tile_passes * 16) * M,
         "blend_fwd": walked * 40 + P * 20,
         "loss": P * 36,
         "blend_bwd": walked * (40 + 12 + 36) + P * 24 + tiles * 8,
         "chain": N * 16 + K * RW * b + Rrec * 20 + walked * 36 + tiles * 8 + N * (12 + 4 * RW),
-        "codebook_reduce": N * 8 + row_passes * 20 * N + N * 4 * RW + K * 4 * RW,
+        "codebook_reduce": N * 8 + row_passes * 16 * N + 4 * N + N * 4 * RW + K * 4 * RW,
     }
     out["total"] = sum(out.values())
     return out

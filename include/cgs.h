@@ -350,6 +350,16 @@ const char* cgs_status_str(int32_t status);
 /* Library version: major*10000 + minor*100 + patch. */
 int32_t cgs_version(void);
 
+/* Diagnostic of the radix sorts inside the binning, the codebook reduction
+ * and cgs_bin_tiles: the number of look-back waits that reached their bound on
+ * the current device since the library was loaded.  A sorting workgroup
+ * waits only on workgroups that started before it and publish their counts
+ * without waiting, so this stays 0; a nonzero value means that the sorted
+ * output of some call since then is wrong (its writes stay in bounds).
+ * Synchronous (a device read on the null stream); 0xffffffff if that read
+ * fails. */
+uint32_t cgs_sort_stalls(void);
+
 #ifdef __cplusplus
 }
 #endif

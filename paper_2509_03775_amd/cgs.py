@@ -18,7 +18,7 @@ MAX_VIEWS = MAX_SCENES = 64
 EXPORTS = ("cgs_workspace_bytes", "cgs_render_forward", "cgs_render_backward",
            "cgs_codebook_grad_reduce_workspace_bytes", "cgs_codebook_grad_reduce",
            "cgs_bin_tiles_workspace_bytes", "cgs_bin_tiles", "cgs_loss_l1_workspace_bytes",
-           "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version",
+           "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version", "cgs_sort_stalls",
            "cgs_render_backward_sgld", "cgs_sgld_normals", "cgs_loss_recon_workspace_bytes", "cgs_loss_recon",
            "cgs_mh_workspace_bytes", "cgs_mh_split", "cgs_mh_merge", "cgs_mh_transition")
 
@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cgs_status_str.restype = ctypes.c_char_p
     L.cgs_version.argtypes = []
     L.cgs_version.restype = c_int32
+    L.cgs_sort_stalls.argtypes = []
+    L.cgs_sort_stalls.restype = ctypes.c_uint32
     _LIB = L
     return L
 

@@ -15,7 +15,6 @@ namespace cgs {
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*,
                              hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
-hipError_t launch_gather_depth(int64_t, const uint32_t*, const uint2*, uint2*, uint32_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
                        const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
@@ -226,10 +225,9 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.tile_cut = take(8 * (size_t)T);
     p.qbits = take((size_t)cap);
     for (int i = 0; i < 2; ++i) { p.tperm_key[i] = take(4 * (size_t)T); p.tperm_val[i] = take(4 * (size_t)T); }
-    const int64_t nmax = std::max(std::max(R, cap), G);
-    p.radix_blocks_max = (nmax + kSortTile - 1) / kSortTile;
-    p.radix_counts = take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(p.radix_blocks_max, 1));
-    p.scan_blocks_max = (int64_t)scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * p.radix_blocks_max));
+    const int64_t nmax = std::max(std::max(R, cap), std::max(G, T));   // every sort and scan below
+    p.radix_ws = take(radix_ws_bytes(nmax));
+    p.scan_blocks_max = (int64_t)scan_bsum_count(nmax);
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
     p.slot_off = take(4 * (size_t)R);
     p.ginst = take(4 * 9 * (size_t)cap);
@@ -273,6 +271,8 @@ using namespace cgs;
 extern "C" {
 
 int32_t cgs_version(void) { return 10000; }
+
+uint32_t cgs_sort_stalls(void) { return sort_stalls(); }
 
 const char* cgs_status_str(int32_t s) {
     switch (s) {
@@ -320,7 +320,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     const BatchDesc* dd = at<const BatchDesc>(ws, p.desc);
     DevCounters* cnt = at<DevCounters>(ws, p.counters);
     unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
-    uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
+    void* sws = at<char>(ws, p.radix_ws);
     CGS_TRY(mark(h, 0, st));
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
@@ -331,12 +331,11 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
     uint32_t* dv[2] = {at<uint32_t>(ws, p.dsort_val[0]), at<uint32_t>(ws, p.dsort_val[1])};
     hipError_t e;
-    int db = radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, counts, bsum,
-                              st, &e);
+    // the last pass also gathers each record's tile rectangle and count in depth order
+    const SortGather rg{at<const uint2>(ws, p.tile_rect), at<uint2>(ws, p.rect_d), at<uint32_t>(ws, p.cnt_d), 1};
+    int db = radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, sws, st, &e, &rg);
     CGS_TRY(e);
     // instance offsets in depth order, capacity check, emission
-    CGS_TRY(launch_gather_depth(h.d.n_rec, dv[db], at<uint2>(ws, p.tile_rect), at<uint2>(ws, p.rect_d),
-                                at<uint32_t>(ws, p.cnt_d), st));
     CGS_TRY(scan_u32(at<uint32_t>(ws, p.cnt_d), nullptr, h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));
     CGS_TRY(launch_capacity(cnt, h.d.capacity, d_info, st));
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
@@ -345,7 +344,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
                         at<uint32_t>(ws, p.cnt_d), cnt, ik[1], iv[1], st));
     // backward gradient slots of each record, in record order
     CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), nullptr, h.d.n_rec, at<uint32_t>(ws, p.slot_off), nullptr, bsum, st));
-    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, counts, bsum, st, &e);
+    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
     CGS_TRY(e);
     if (ib != h.inst_buf) return CGS_EHIP;
     CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
@@ -353,7 +352,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
         uint32_t* tk[2] = {at<uint32_t>(ws, p.tperm_key[0]), at<uint32_t>(ws, p.tperm_key[1])};
         uint32_t* tv[2] = {at<uint32_t>(ws, p.tperm_val[0]), at<uint32_t>(ws, p.tperm_val[1])};
         CGS_TRY(tile_len_keys(at<uint32_t>(ws, p.tile_range), h.d.n_tiles, tk[1], st));
-        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, 16, counts, bsum, st, &e);
+        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, 16, sws, st, &e);
         CGS_TRY(e);
         if (tb != h.tperm_buf) return CGS_EHIP;
     }
@@ -433,8 +432,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const WsPlan& p = h.p;
     const BatchDesc* dd = at<const BatchDesc>(ws, p.desc);
-    unsigned long long* bsum = at<unsigned long long>(ws, p.scan_bsum);
-    uint32_t* counts = at<uint32_t>(ws, p.radix_counts);
+    void* sws = at<char>(ws, p.radix_ws);
     DevCounters* cnt = at<DevCounters>(ws, p.counters);
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
@@ -463,7 +461,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
         else { c0 = 8; D = h.d.row_width - 8; }
         CGS_TRY(launch_row_keys(dd, part_i, h.d.n_gauss, pk[1], st));
         hipError_t e;
-        int pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), counts, bsum, st, &e);
+        int pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), sws, st, &e);
         CGS_TRY(e);
         CGS_TRY(tile_ranges(pk[pb], nullptr, h.d.n_gauss, rows, rr, st));
         CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
@@ -497,9 +495,7 @@ size_t cgs_codebook_grad_reduce_workspace_bytes(int64_t n, int64_t k, int32_t d)
     take(sizeof(BatchDesc));
     for (int i = 0; i < 4; ++i) take(4 * (size_t)n);
     take(8 * (size_t)(k + 1));
-    const int64_t nb = (n + kSortTile - 1) / kSortTile;
-    take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1));
-    take(8 * scan_bsum_count(std::max<int64_t>(n, kRadixBins * nb)));
+    take(radix_ws_bytes(n));
     return o;
 }
 
@@ -531,9 +527,7 @@ cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* i
     uint32_t* pv[2];
     for (int i = 0; i < 2; ++i) { pk[i] = at<uint32_t>(ws, take(4 * (size_t)n)); pv[i] = at<uint32_t>(ws, take(4 * (size_t)n)); }
     uint32_t* rr = at<uint32_t>(ws, take(8 * (size_t)(k + 1)));
-    const int64_t nb = (n + kSortTile - 1) / kSortTile;
-    uint32_t* counts = at<uint32_t>(ws, take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1)));
-    unsigned long long* bsum = at<unsigned long long>(ws, take(8 * scan_bsum_count(std::max<int64_t>(n, kRadixBins * nb))));
+    void* sws = at<char>(ws, take(radix_ws_bytes(n)));
     char* dbase = static_cast<char*>(ws) + o_desc;
     CGS_TRY(upload_bytes(dbase, &hd, offsetof(BatchDesc, views), st));
     CGS_TRY(upload_bytes(dbase + offsetof(BatchDesc, scenes), &sd, sizeof(sd), st));
@@ -544,7 +538,7 @@ cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* i
     } else {
         CGS_TRY(launch_copy_keys(idx, n, pk[1], st));
         hipError_t e;
-        pb = radix_sort_pairs(pk[1], nullptr, pk, pv, n, nullptr, bits_for(k), counts, bsum, st, &e);
+        pb = radix_sort_pairs(pk[1], nullptr, pk, pv, n, nullptr, bits_for(k), sws, st, &e);
         CGS_TRY(e);
     }
     CGS_TRY(tile_ranges(pk[pb], nullptr, n, k, rr, st));
@@ -560,9 +554,8 @@ size_t cgs_bin_tiles_workspace_bytes(int64_t n, int32_t tiles_x, int32_t tiles_y
     for (int i = 0; i < 6; ++i) take(4 * (size_t)n);        // ntiles, offs, dsort key/val x2
     for (int i = 0; i < 4; ++i) take(4 * (size_t)capacity); // instance key/val x2
     const int64_t nmax = std::max(n, capacity);
-    const int64_t nb = (nmax + kSortTile - 1) / kSortTile;
-    take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1));
-    take(8 * scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * nb)));
+    take(radix_ws_bytes(nmax));
+    take(8 * scan_bsum_count(nmax));
     return o;
 }
 
@@ -592,17 +585,16 @@ cgs_status cgs_bin_tiles(const uint32_t* depth_key, const uint16_t* trect, const
         iv[i] = at<uint32_t>(ws, take(4 * (size_t)capacity));
     }
     const int64_t nmax = std::max(n, capacity);
-    const int64_t nb = (nmax + kSortTile - 1) / kSortTile;
-    uint32_t* counts = at<uint32_t>(ws, take(4 * (size_t)kRadixBins * (size_t)std::max<int64_t>(nb, 1)));
-    unsigned long long* bsum = at<unsigned long long>(ws, take(8 * scan_bsum_count(std::max<int64_t>(nmax, kRadixBins * nb))));
+    void* sws = at<char>(ws, take(radix_ws_bytes(nmax)));
+    unsigned long long* bsum = at<unsigned long long>(ws, take(8 * scan_bsum_count(nmax)));
     CGS_TRY(launch_plain_counts(trect, n, nt, st));
     hipError_t e;
-    int db = radix_sort_pairs(depth_key, nullptr, dk, dv, n, nullptr, 32, counts, bsum, st, &e);
+    int db = radix_sort_pairs(depth_key, nullptr, dk, dv, n, nullptr, 32, sws, st, &e);
     CGS_TRY(e);
     CGS_TRY(scan_u32(nt, dv[db], n, offs, &cnt->n_inst, bsum, st));
     CGS_TRY(launch_capacity(cnt, capacity, d_info, st));
     CGS_TRY(launch_emit_plain(trect, view_of, dv[db], offs, n, tiles_x, tiles_y, cnt, ik[1], iv[1], st));
-    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, capacity, &cnt->n_inst_ok, bits_for(ntile), counts, bsum, st, &e);
+    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, capacity, &cnt->n_inst_ok, bits_for(ntile), sws, st, &e);
     CGS_TRY(e);
     CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, capacity, ntile, tile_range, st));
     CGS_TRY(launch_plain_keys(ik[ib], iv[ib], depth_key, cnt, capacity, sorted_key, sorted_gid, st));

@@ -125,10 +125,10 @@ struct WsPlan {
     size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
-    size_t radix_counts, scan_bsum;
+    size_t radix_ws, scan_bsum;
     size_t slot_off, ginst, rec_grad, rec_flag, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
-    int64_t radix_blocks_max, scan_blocks_max;
+    int64_t scan_blocks_max;
 };
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -285,14 +285,28 @@ hipError_t fill_u32(void* dst, uint32_t value, size_t count, hipStream_t st);
 hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out,
                     unsigned long long* total, unsigned long long* bsum, hipStream_t st);
 
-// Stable LSD radix sort of (key, value) u32 pairs on bits [0, nbits).  The
-// first pass reads kin/vin (vin NULL: value = position), later passes ping-pong
-// between kbuf/vbuf[0] and [1] (kin may alias kbuf[1]).  n_dev (optional) holds
-// the live item count, clamped to n_max.  Returns the index (0/1) of the
-// buffer pair that holds the result.
+// Stable LSD radix sort of (key, value) u32 pairs on bits [0, nbits), at
+// most 32 bits.  The first pass reads kin/vin (vin NULL: value = position),
+// later passes ping-pong between kbuf/vbuf[0] and [1] (kin may alias
+// kbuf[1]).  n_dev (optional) holds the live item count, clamped to n_max.
+// ws: radix_ws_bytes(n_max) bytes of scratch.  Returns the index (0/1) of
+// the buffer pair that holds the result.
+// last (optional) extends the final pass: rect_out[i] = rect_in[value i] and
+// cnt_out[i] = that tile rectangle's area (packed u16 x0,y0 | x1,y1, half
+// open); with drop_keys the sorted keys are not written.
+struct SortGather {
+    const uint2* rect_in;
+    uint2* rect_out;
+    uint32_t* cnt_out;
+    int drop_keys;
+};
+size_t radix_ws_bytes(int64_t n_max);
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
-                     const unsigned long long* n_dev, int nbits, uint32_t* counts, unsigned long long* bsum,
-                     hipStream_t st, hipError_t* err);
+                     const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
+                     const SortGather* last = nullptr);
+// Look-back waits of the radix passes that hit their bound on the current
+// device since the library was loaded (synchronous read; 0 expected).
+uint32_t sort_stalls();
 
 hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key, hipStream_t st);
 

@@ -70,20 +70,6 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
 }
 
 // ------------------------------------------------------------------ emission
-// Depth-ordered copies of each record's tile rectangle and tile count (one
-// random 8-byte gather per record -- the count is the rectangle's area -- so
-// the scan and the emission read contiguously).
-__global__ __launch_bounds__(256) void k_gather_depth(int64_t n_rec, const uint32_t* __restrict__ sorted_rec,
-                                                      const uint2* __restrict__ tile_rect, uint2* __restrict__ rect_d,
-                                                      uint32_t* __restrict__ cnt_d) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_rec) return;
-    const uint2 tr = tile_rect[sorted_rec[j]];
-    rect_d[j] = tr;
-    const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu, y1 = tr.y >> 16;
-    cnt_d[j] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
-}
-
 // Wave-cooperative emission: a wavefront owns 64 consecutive records of the
 // depth order; their instances occupy one contiguous range of the instance
 // array, which the 64 lanes write in order (each lane finds the record of an
@@ -325,14 +311,6 @@ hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_
 
 hipError_t launch_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info, hipStream_t st) {
     hipLaunchKernelGGL(k_capacity, dim3(1), dim3(1), 0, st, cnt, capacity, d_info);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather_depth(int64_t n_rec, const uint32_t* sorted_rec, const uint2* tr, uint2* rect_d,
-                               uint32_t* cnt_d, hipStream_t st) {
-    if (n_rec <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_depth, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0, st, n_rec, sorted_rec, tr,
-                       rect_d, cnt_d);
     return hipGetLastError();
 }
 

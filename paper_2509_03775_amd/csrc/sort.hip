@@ -2,13 +2,11 @@
 // exclusive scan and a stable LSD radix sort of (u32 key, u32 value) pairs.
 // All of it is bit-exact integer work.
 //
-// Radix sort layout: a workgroup of 256 threads owns 4096 consecutive items;
-// wave w owns items [w*1024, w*1024+1024) and walks them 64 at a time, so the
-// item order inside a workgroup is (wave, step, lane) and ranks computed in
-// that order keep the sort stable.  Lanes holding equal digits find each
-// other with one ballot per digit bit; the lowest of them updates the wave's
-// running count in LDS.  Counts are laid out digit-major ([digit][block]) so a
-// single exclusive scan yields every (digit, block) output offset.
+// Radix sort layout: a workgroup of 512 threads owns a tile of 8192
+// consecutive items and ranks them in item order, so the sort is stable;
+// per-tile digit states are published tile-major ([tile][digit], 64-bit
+// words: a 2-bit state, how far back the sum reaches, the sum) for the
+// look-back.
 #include "cgs_internal.h"
 
 namespace cgs {
@@ -156,162 +154,310 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_
 }
 
 // ------------------------------------------------------------- radix sort
+// Single-pass form of the LSD radix sort (decoupled look-back, Merrill &
+// Garland 2016; one sweep per digit, Adinets & Merrill 2022).  k_os_hist
+// counts the digits of every pass from the input keys at once (a digit
+// histogram does not depend on the order of the keys).  Each pass is then one
+// kernel: a workgroup takes a ticket (its tile of kOsTile items, in the order
+// workgroups start), ranks its items, publishes its per-digit counts and
+// walks back over the states of tiles with earlier tickets.  A state holds a
+// sum of counts and how far back it reaches: "tiles (k, t]" while tile t is
+// still walking (it is rewritten at each step, so a tile behind it can jump
+// over the stretch t has already summed), "tiles [0, t]" once t is done.  A
+// ticket is taken only by a running workgroup and a workgroup publishes its
+// state before it waits, so every wait ends; the wait is still bounded (a
+// stall is counted and the pass finishes with its writes kept in bounds).
+constexpr int kOsThreads = 512;             // 8 waves
+constexpr int kOsWaves = kOsThreads / 64;
+constexpr int kOsItems = 16;                // keys per lane
+constexpr int kOsTile = kOsItems * kOsThreads;   // 8192 keys per workgroup
+constexpr int kOsHistBlocks = 512;
+constexpr int kHistCopies = 8;
+constexpr uint64_t kStAgg = 1ull << 62;     // bits 32..61: k + 1; low 32: count of tiles (k, t]
+constexpr uint64_t kStInc = 2ull << 62;     // low 32: count of tiles [0, t]
+constexpr uint32_t kSpinLimit = 1u << 21;
+
+__device__ uint32_t g_sort_stalls;          // bounded waits that gave up since load
+
 __device__ inline int64_t live_count(int64_t n_max, const unsigned long long* n_dev) {
     if (!n_dev) return n_max;
     unsigned long long v = *n_dev;
     return (int64_t)v < n_max ? (int64_t)v : n_max;
 }
 
-// Mask of active lanes whose digit (< 2^kRadixBits) equals this lane's:
-// one ballot per digit bit (bits above a narrower pass's width are zero and
-// match trivially).
-__device__ inline uint64_t match_digit(uint32_t d) {
-    uint64_t peers = __ballot(1);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-        const uint32_t bit = (d >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    return peers;
+__device__ inline void status_put(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint32_t* keys, int64_t n_max,
-                                                           const unsigned long long* n_dev, int shift, int nbits,
-                                                           uint32_t* counts, int64_t nblocks) {
-    __shared__ uint32_t hist[kRadixBins];
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t n = live_count(n_max, n_dev);
+__device__ inline uint64_t status_get(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint32_t pass_mask(int nbits, int p) {
+    const int w = nbits - p * kRadixBits < kRadixBits ? nbits - p * kRadixBits : kRadixBits;
+    return (1u << w) - 1u;
+}
+
+// Exclusive scan over the workgroup of one value per thread (kOsThreads).
+__device__ inline uint32_t os_scan(uint32_t v, uint32_t* s_wave) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortTile / 4);
-    const uint32_t mask = (1u << nbits) - 1u;
-    if ((int64_t)blockIdx.x * kSortTile < n) {
-        uint32_t k_[kSortItems];     // all loads issued before the first LDS update
+    const uint32_t inc = wave_incl_scan(v, lane);
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < kOsWaves; ++i)
+        if (i < w) before += s_wave[i];
+    __syncthreads();
+    return before + inc - v;
+}
+
+struct SortWs {
+    uint64_t* status[2];    // [tiles][256] per pass, the two alternating
+    uint32_t* ghist;        // [4][256] digit counts of every pass
+    uint32_t* tickets;      // [4] per pass
+};
+
+SortWs sort_ws(void* ws, int64_t n_max) {
+    const int64_t nb = std::max<int64_t>(1, (n_max + kOsTile - 1) / kOsTile);
+    char* p = static_cast<char*>(ws);
+    SortWs s;
+    const size_t st_bytes = align_up(8 * (size_t)kRadixBins * (size_t)nb);
+    s.status[0] = reinterpret_cast<uint64_t*>(p);
+    s.status[1] = reinterpret_cast<uint64_t*>(p + st_bytes);
+    s.ghist = reinterpret_cast<uint32_t*>(p + 2 * st_bytes);
+    s.tickets = s.ghist + 4 * kRadixBins;
+    return s;
+}
+
+size_t radix_ws_bytes(int64_t n_max) {
+    const int64_t nb = std::max<int64_t>(1, (n_max + kOsTile - 1) / kOsTile);
+    return 2 * align_up(8 * (size_t)kRadixBins * (size_t)nb) + align_up(4 * (4 * (size_t)kRadixBins + 4));
+}
+
+// Digit histograms of every pass over the live keys (global atomics of each
+// workgroup's nonzero LDS bins) and a zeroed state row per live tile for the
+// first pass.  Each bin has kHistCopies LDS copies, lane l adding to copy l % kHistCopies,
+// so lanes of a wave that share a digit (the high digits of depth keys take
+// few values) collide at most 64 / kHistCopies ways.
+__global__ __launch_bounds__(kOsThreads) void k_os_hist(const uint32_t* keys, int64_t n_max,
+                                                        const unsigned long long* n_dev, int nbits, uint32_t* ghist,
+                                                        uint64_t* status0) {
+    __shared__ uint32_t h[4 * kRadixBins * kHistCopies];
+    for (int i = threadIdx.x; i < 4 * kRadixBins * kHistCopies; i += kOsThreads) h[i] = 0;
+    __syncthreads();
+    const uint32_t copy = threadIdx.x % kHistCopies;
+    const int64_t n = live_count(n_max, n_dev);
+    const int64_t nb = (n + kOsTile - 1) / kOsTile;
+    const int passes = (nbits + kRadixBits - 1) / kRadixBits;
+    for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
+        if (threadIdx.x < kRadixBins) status0[t * kRadixBins + threadIdx.x] = 0ull;
+        uint32_t k_[kOsItems];
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
-            const int64_t j = base + i * 64 + lane;
+        for (int i = 0; i < kOsItems; ++i) {
+            const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
             k_[i] = j < n ? keys[j] : 0u;
         }
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
-            const int64_t j = base + i * 64 + lane;
-            if (j < n) {
-                const uint32_t d = (k_[i] >> shift) & mask;
-                const uint64_t peers = match_digit(d);
-                if (popc_below(peers) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
-            }
+        for (int i = 0; i < kOsItems; ++i) {
+            const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
+            if (j < n)
+                for (int p = 0; p < passes; ++p) {
+                    const uint32_t d = (k_[i] >> (p * kRadixBits)) & pass_mask(nbits, p);
+                    atomicAdd(&h[(p * kRadixBins + d) * kHistCopies + copy], 1u);
+                }
         }
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+    for (int p = 0; p < passes && threadIdx.x < kRadixBins; ++p) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < kHistCopies; ++q) c += h[(p * kRadixBins + threadIdx.x) * kHistCopies + q];
+        if (c) atomicAdd(&ghist[p * kRadixBins + threadIdx.x], c);
+    }
 }
 
-// Scatter pass.  Ranks are computed per wave in item order as in the
-// histogram pass; the workgroup then places its items in LDS in block-local
-// digit order and writes them out linearly, so each digit's run of items goes
-// to consecutive global addresses (coalesced) instead of 64 scattered writes
-// per instruction.
-__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint32_t* keys_in, const uint32_t* vals_in,
-                                                              uint32_t* keys_out, uint32_t* vals_out,
-                                                              int64_t n_max, const unsigned long long* n_dev,
-                                                              int shift, int nbits, const uint32_t* offsets,
-                                                              int64_t nblocks) {
-    __shared__ uint32_t cnt[4][kRadixBins];
-    __shared__ uint32_t s_key[kSortTile];
-    __shared__ uint32_t s_val[kSortTile];
+// One pass.  Wave w of the workgroup owns keys [w * 1024, w * 1024 + 1024)
+// of the tile and walks them 64 at a time; ranks are computed in that item
+// order (wave, step, lane), which keeps the sort stable: for each step the
+// lanes OR their bit into an LDS mask per (wave, digit), read it back (the
+// lanes sharing their digit), and the lowest of them advances the wave's
+// count of the digit and clears the mask.  The keys then go to LDS in
+// block-local digit order and out linearly, so each digit's run goes to
+// consecutive global addresses; the values follow through the same LDS
+// buffer.  Threads 0..255 own one digit each for the counts and the
+// look-back.
+template <bool GATHER>
+__global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in, const uint32_t* vals_in,
+                                                        uint32_t* keys_out, uint32_t* vals_out, int64_t n_max,
+                                                        const unsigned long long* n_dev, int shift, uint32_t mask,
+                                                        const uint32_t* ghist, uint64_t* status,
+                                                        uint64_t* status_next, uint32_t* ticket, SortGather g) {
+    __shared__ uint32_t cnt[kOsWaves][kRadixBins];
+    __shared__ unsigned long long s_peer[kOsWaves][kRadixBins];
+    __shared__ uint32_t s_buf[kOsTile];
     __shared__ uint32_t s_goff[kRadixBins];
-    __shared__ uint32_t s_wave[kSortBlock / 64];
+    __shared__ uint32_t s_wave[kOsWaves];
+    __shared__ uint32_t s_ticket;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = 0; i < 4; ++i) cnt[i][threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
+    for (int i = threadIdx.x; i < kOsWaves * kRadixBins; i += kOsThreads) {
+        (&cnt[0][0])[i] = 0;
+        (&s_peer[0][0])[i] = 0ull;
+    }
     __syncthreads();
+    const int64_t b = s_ticket;
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t blk0 = (int64_t)blockIdx.x * kSortTile;
-    if (blk0 >= n) return;     // whole workgroup: nothing here
-    const int64_t base = blk0 + (int64_t)w * (kSortTile / 4);
-    const uint32_t mask = (1u << nbits) - 1u;
-    uint32_t k_[kSortItems], v_[kSortItems];
-    uint32_t rank[kSortItems];
-    // all loads issued before the first LDS update
+    const int64_t blk0 = b * kOsTile;
+    if (blk0 >= n) return;
+    const bool dig = threadIdx.x < kRadixBins;
+    const uint32_t d = dig ? threadIdx.x : 0u;
+    if (status_next && dig) status_next[b * kRadixBins + d] = 0ull;
+    const int64_t base = blk0 + (int64_t)w * (kOsItems * 64);
+    uint32_t k_[kOsItems], v_[kOsItems];
+    uint32_t lp[kOsItems];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < kOsItems; ++i) {
         const int64_t j = base + i * 64 + lane;
         k_[i] = j < n ? keys_in[j] : 0u;
-        v_[i] = j < n ? (vals_in ? vals_in[j] : (uint32_t)j) : 0u;
     }
+    const unsigned long long bit = 1ull << lane;
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        int64_t j = base + i * 64 + lane;
-        rank[i] = 0xffffffffu;
-        if (j < n) {
-            const uint32_t key = k_[i];
-            uint32_t d = (key >> shift) & mask;
-            uint64_t peers = match_digit(d);
-            uint32_t below = popc_below(peers);
-            uint32_t run = cnt[w][d];
-            rank[i] = run + below;
+    for (int i = 0; i < kOsItems; ++i) {
+        const bool live = base + i * 64 + lane < n;
+        const uint32_t dd = (k_[i] >> shift) & mask;
+        lp[i] = 0xffffffffu;
+        if (live) atomicOr(&s_peer[w][dd], bit);
+        wave_sync();
+        if (live) {
+            const uint64_t peers = s_peer[w][dd];
+            const uint32_t below = popc_below(peers);
+            const uint32_t run = cnt[w][dd];
+            lp[i] = run + below;
             wave_sync();
-            if (below == 0) cnt[w][d] = run + (uint32_t)__popcll(peers);
+            if (below == 0) {
+                cnt[w][dd] = run + (uint32_t)__popcll(peers);
+                s_peer[w][dd] = 0ull;
+            }
         }
         wave_sync();
     }
     __syncthreads();
-    // per digit: block-local start (prefix over digits), each wave's local
-    // base, and the shift from local to global positions
-    {
-        const uint32_t d = threadIdx.x;
-        uint32_t tot = 0, wb[4];
-        for (int i = 0; i < 4; ++i) { wb[i] = tot; tot += cnt[i][d]; }
-        uint32_t all;
-        const uint32_t dstart = block_excl_scan(tot, s_wave, &all);
-        for (int i = 0; i < 4; ++i) cnt[i][d] = dstart + wb[i];
-        s_goff[d] = offsets[(int64_t)d * nblocks + blockIdx.x] - dstart;
+    uint32_t tot = 0, wb[kOsWaves];
+#pragma unroll
+    for (int i = 0; i < kOsWaves; ++i) { wb[i] = tot; tot += dig ? cnt[i][d] : 0u; }
+    uint64_t* mine = status + b * kRadixBins + d;
+    if (dig) status_put(mine, (b == 0 ? kStInc : (kStAgg | ((uint64_t)b << 32))) | (uint64_t)tot);
+#pragma unroll
+    for (int i = 0; i < kOsItems; ++i) {
+        const int64_t j = base + i * 64 + lane;
+        v_[i] = j < n ? (vals_in ? vals_in[j] : (uint32_t)j) : 0u;
     }
+    const uint32_t gstart = os_scan(dig ? ghist[d] : 0u, s_wave);
+    const uint32_t dstart = os_scan(tot, s_wave);
+    if (dig)
+        for (int i = 0; i < kOsWaves; ++i) cnt[i][d] = dstart + wb[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        if (rank[i] != 0xffffffffu) {
-            const uint32_t d = (k_[i] >> shift) & mask;
-            const uint32_t lp = cnt[w][d] + rank[i];
-            s_key[lp] = k_[i];
-            s_val[lp] = v_[i];
+    for (int i = 0; i < kOsItems; ++i)
+        if (lp[i] != 0xffffffffu) {
+            lp[i] += cnt[w][(k_[i] >> shift) & mask];
+            s_buf[lp[i]] = k_[i];
+        }
+    uint32_t excl = 0;
+    if (dig && b > 0) {
+        int64_t k = b - 1;
+        uint32_t spins = 0;
+        for (;;) {
+            const uint64_t s = status_get(status + k * kRadixBins + d);
+            const uint64_t f = s >> 62;
+            if (f == 0) {
+                if (++spins >= kSpinLimit) { atomicAdd(&g_sort_stalls, 1u); break; }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += (uint32_t)s;
+            if (f == 2) break;
+            k = (int64_t)((s >> 32) & 0x3fffffffull) - 1;
+            status_put(mine, kStAgg | ((uint64_t)(k + 1) << 32) | (uint64_t)(excl + tot));
+        }
+        status_put(mine, kStInc | (uint64_t)(excl + tot));
+    }
+    if (dig) s_goff[d] = gstart + excl - dstart;
+    __syncthreads();
+    const int m = (int)(n - blk0 < kOsTile ? n - blk0 : kOsTile);
+    uint32_t pos[kOsItems];
+#pragma unroll
+    for (int i = 0; i < kOsItems; ++i) {
+        const int q = i * kOsThreads + (int)threadIdx.x;
+        pos[i] = 0xffffffffu;
+        if (q < m) {
+            const uint32_t key = s_buf[q];
+            pos[i] = s_goff[(key >> shift) & mask] + (uint32_t)q;
+            if (keys_out && (int64_t)pos[i] < n) keys_out[pos[i]] = key;
         }
     }
     __syncthreads();
-    const int m = (int)(n - blk0 < kSortTile ? n - blk0 : kSortTile);
-    for (int i = threadIdx.x; i < m; i += kSortBlock) {
-        const uint32_t key = s_key[i];
-        const uint32_t pos = s_goff[(key >> shift) & mask] + (uint32_t)i;
-        keys_out[pos] = key;
-        vals_out[pos] = s_val[i];
+#pragma unroll
+    for (int i = 0; i < kOsItems; ++i)
+        if (lp[i] != 0xffffffffu) s_buf[lp[i]] = v_[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kOsItems; ++i) {
+        const int q = i * kOsThreads + (int)threadIdx.x;
+        if (q < m && (int64_t)pos[i] < n) {
+            const uint32_t v = s_buf[q];
+            vals_out[pos[i]] = v;
+            if (GATHER) {
+                const uint2 tr = g.rect_in[v];
+                const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu, y1 = tr.y >> 16;
+                g.rect_out[pos[i]] = tr;
+                g.cnt_out[pos[i]] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
+            }
+        }
     }
 }
 
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
-                     const unsigned long long* n_dev, int nbits, uint32_t* counts, unsigned long long* bsum,
-                     hipStream_t st, hipError_t* err) {
+                     const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
+                     const SortGather* last) {
     *err = hipSuccess;
     const int passes = (nbits + kRadixBits - 1) / kRadixBits;
     const int final_buf = passes > 0 ? (passes - 1) & 1 : 0;
-    const int64_t nblocks = (n_max + kSortTile - 1) / kSortTile;
+    const int64_t nblocks = (n_max + kOsTile - 1) / kOsTile;
     if (nblocks == 0 || nbits <= 0) return final_buf;
+    if (passes > 4) { *err = hipErrorInvalidValue; return final_buf; }
+    const SortWs s = sort_ws(ws, n_max);
+    *err = fill_u32(s.ghist, 0u, 4 * kRadixBins + 4, st);
+    if (*err != hipSuccess) return final_buf;
+    const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
+    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev, nbits, s.ghist,
+                       s.status[0]);
     const uint32_t* ksrc = kin;
     const uint32_t* vsrc = vin;
-    int out = 0;
-    for (int shift = 0; shift < nbits; shift += kRadixBits) {
-        const int pb = nbits - shift < kRadixBits ? nbits - shift : kRadixBits;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblocks), dim3(kSortBlock), 0, st, ksrc, n_max, n_dev, shift,
-                           pb, counts, nblocks);
-        hipError_t e = scan_u32(counts, nullptr, nblocks * kRadixBins, counts, nullptr, bsum, st);
-        if (e != hipSuccess) { *err = e; return final_buf; }
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblocks), dim3(kSortBlock), 0, st, ksrc, vsrc, kbuf[out],
-                           vbuf[out], n_max, n_dev, shift, pb, counts, nblocks);
+    for (int p = 0; p < passes; ++p) {
+        const int out = p & 1;
+        const bool fin = p + 1 == passes;
+        SortGather g{};
+        if (fin && last) g = *last;
+        auto kern = g.rect_in ? k_os_pass<true> : k_os_pass<false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kOsThreads), 0, st, ksrc, vsrc,
+                           fin && last && last->drop_keys ? nullptr : kbuf[out],
+                           vbuf[out], n_max, n_dev, p * kRadixBits,
+                           (uint32_t)((1ull << std::min(kRadixBits, nbits - p * kRadixBits)) - 1ull),
+                           s.ghist + p * kRadixBins, s.status[p & 1], p + 1 < passes ? s.status[(p + 1) & 1] : nullptr,
+                           s.tickets + p, g);
         ksrc = kbuf[out];
         vsrc = vbuf[out];
-        out ^= 1;
     }
     *err = hipGetLastError();
     return final_buf;
+}
+
+uint32_t sort_stalls() {
+    uint32_t v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_sort_stalls), sizeof(v), 0, hipMemcpyDeviceToHost) != hipSuccess)
+        return 0xffffffffu;
+    return v;
 }
 
 // ----------------------------------------------------------- tile ranges

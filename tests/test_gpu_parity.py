@@ -197,13 +197,14 @@ def _gpu_bin(key, trect, view, tx, ty, V, cap):
                   sk.data_ptr(), sg.data_ptr(), rg.data_ptr(), cap, info.data_ptr(), ws.data_ptr(), nb,
                   torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
+    assert cgs.load().cgs_sort_stalls() == 0
     return (sk.cpu().numpy().view(np.uint64), sg.cpu().numpy().view(np.uint32),
             rg.cpu().numpy().view(np.uint32).reshape(-1, 2), info.cpu().numpy())
 
 
 @pytest.mark.parametrize("seed,n,tx,ty,V,ties", [(1, 5000, 13, 9, 3, True), (2, 20000, 40, 30, 1, False),
                                                  (3, 1, 4, 4, 1, True), (4, 0, 4, 4, 2, True),
-                                                 (5, 70000, 123, 69, 4, True)])
+                                                 (5, 70000, 123, 69, 4, True), (6, 300000, 123, 69, 4, False)])
 def test_bin_tiles_bit_exact(seed, n, tx, ty, V, ties):
     say(f"[bin_tiles] seed={seed} n={n} tiles={tx}x{ty}x{V}")
     key, trect, view = _bin_inputs(seed, n, tx, ty, V, ties)
