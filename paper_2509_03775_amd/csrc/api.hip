@@ -12,7 +12,7 @@
 namespace cgs {
 
 // launchers defined in the other translation units
-hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*,
+hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*, uint32_t*,
                              hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
@@ -156,6 +156,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     if (goff >= ((int64_t)1 << 32) || sroff >= ((int64_t)1 << 32) || shoff >= ((int64_t)1 << 32)) return CGS_EINVAL;
     h->rows_total = std::max(sroff, shoff);
     int64_t roff = 0, toff = 0, poff = 0, rwaves = 0;
+    d.pack_rect = 1;
     for (int v = 0; v < b->n_views; ++v) {
         const cgs_camera& c = b->cameras[v];
         const int s = b->view_scene[v];
@@ -167,6 +168,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         vd.H = c.height;
         vd.tiles_x = (c.width + kTile - 1) / kTile;
         vd.tiles_y = (c.height + kTile - 1) / kTile;
+        if (vd.tiles_x > 255 || vd.tiles_y > 255) d.pack_rect = 0;
         vd.scene = s;
         vd.tile_off = toff;
         vd.pix_off = poff;
@@ -216,6 +218,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.depth_key = take(4 * (size_t)R);
     p.tile_rect = take(8 * (size_t)R);
     p.ntiles = take(4 * (size_t)R);
+    p.prect = take(4 * (size_t)R);
+    for (int i = 0; i < 2; ++i) p.pay[i] = take(4 * (size_t)R);
     for (int i = 0; i < 2; ++i) { p.dsort_key[i] = take(4 * (size_t)R); p.dsort_val[i] = take(4 * (size_t)R); }
     p.offs = take(4 * (size_t)R);
     p.rect_d = take(8 * (size_t)R);
@@ -325,14 +329,22 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
-                              at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), st));
+                              at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect), st));
     CGS_TRY(mark(h, 1, st));
     // depth order of every record (stable: ties keep record order)
     uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
     uint32_t* dv[2] = {at<uint32_t>(ws, p.dsort_val[0]), at<uint32_t>(ws, p.dsort_val[1])};
     hipError_t e;
-    // the last pass also gathers each record's tile rectangle and count in depth order
-    const SortGather rg{at<const uint2>(ws, p.tile_rect), at<uint2>(ws, p.rect_d), at<uint32_t>(ws, p.cnt_d), 1};
+    // the depth-ordered tile rectangle and count of each record: carried
+    // through the sort packed in one word when every view has fewer than 256
+    // tiles per side, else gathered by the last pass
+    SortGather rg{at<const uint2>(ws, p.tile_rect), at<uint2>(ws, p.rect_d), at<uint32_t>(ws, p.cnt_d), 1, nullptr,
+                  {nullptr, nullptr}};
+    if (h.d.pack_rect) {
+        rg.pay_in = at<const uint32_t>(ws, p.prect);
+        rg.pay_buf[0] = at<uint32_t>(ws, p.pay[0]);
+        rg.pay_buf[1] = at<uint32_t>(ws, p.pay[1]);
+    }
     int db = radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, sws, st, &e, &rg);
     CGS_TRY(e);
     // instance offsets in depth order, capacity check, emission

@@ -67,7 +67,7 @@ struct BatchDesc {
     int32_t row_width;      // 8 + 3 (d+1)^2: per-Gaussian gradient row
     int32_t tile_order;
     int32_t vec_rows;       // every codebook row is 16-byte aligned: vector loads allowed
-    int32_t pad_;
+    int32_t pack_rect;      // every view is below 256 tiles per side: rectangles fit one word
     const uint32_t* tile_perm;   // tile order 2: tiles by descending list length
     int64_t n_rec, n_gauss, n_tiles, n_pix, capacity;
     int64_t sr_rows_total, sh_rows_total;
@@ -120,7 +120,7 @@ struct DevCounters {
 // ---------------------------------------------------------- workspace plan
 struct WsPlan {
     size_t desc, counters;
-    size_t rec, depth_key, tile_rect, ntiles;
+    size_t rec, depth_key, tile_rect, ntiles, prect, pay[2];
     size_t dsort_key[2], dsort_val[2];
     size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
@@ -291,14 +291,20 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_
 // kbuf[1]).  n_dev (optional) holds the live item count, clamped to n_max.
 // ws: radix_ws_bytes(n_max) bytes of scratch.  Returns the index (0/1) of
 // the buffer pair that holds the result.
-// last (optional) extends the final pass: rect_out[i] = rect_in[value i] and
-// cnt_out[i] = that tile rectangle's area (packed u16 x0,y0 | x1,y1, half
-// open); with drop_keys the sorted keys are not written.
+// last (optional) makes the final pass write each item's tile rectangle
+// (rect_out, packed u16 x0,y0 | x1,y1, half open) and tile count (cnt_out),
+// either gathered through the value (rect_in[value]) or, when pay_in is set,
+// from a packed payload word (x0 | y0 << 8 | x1 << 16 | y1 << 24, tiles below
+// 256 per side) that every pass carries with the item (pay_in read by the
+// first pass, pay_buf[2] in between).  With drop_keys the final pass writes
+// no keys.
 struct SortGather {
     const uint2* rect_in;
     uint2* rect_out;
     uint32_t* cnt_out;
     int drop_keys;
+    const uint32_t* pay_in;
+    uint32_t* pay_buf[2];
 };
 size_t radix_ws_bytes(int64_t n_max);
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,

@@ -11,7 +11,8 @@ namespace cgs {
 template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict__ desc,
                                                     float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
-                                                    uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles) {
+                                                    uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles,
+                                                    uint32_t* __restrict__ prect) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
@@ -35,6 +36,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
             depth_key[r] = kCulledKey;
             tile_rect[r] = make_uint2(0u, 0u);
             ntiles[r] = 0u;
+            if (desc->pack_rect) prect[r] = 0u;
             rec[kRecF4 * r + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[kRecF4 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[kRecF4 * r + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -50,6 +52,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         const uint32_t rhi = (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16);
         tile_rect[r] = make_uint2(rlo, rhi);
         ntiles[r] = (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0));
+        if (desc->pack_rect)
+            prect[r] = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 8) | ((uint32_t)vp.tx1 << 16) | ((uint32_t)vp.ty1 << 24);
         rec[kRecF4 * r + 0] = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
         rec[kRecF4 * r + 1] = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
         rec[kRecF4 * r + 2] = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), 0.f);
@@ -294,10 +298,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, float4* rec,
-                             uint32_t* dk, uint2* tr, uint32_t* nt, hipStream_t st) {
+                             uint32_t* dk, uint2* tr, uint32_t* nt, uint32_t* prect, hipStream_t st) {
     if (n_gauss_waves <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt)
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
                        case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }

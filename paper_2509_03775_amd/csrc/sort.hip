@@ -283,15 +283,24 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const uint32_t* keys, in
 // lanes sharing their digit), and the lowest of them advances the wave's
 // count of the digit and clears the mask.  The keys then go to LDS in
 // block-local digit order and out linearly, so each digit's run goes to
-// consecutive global addresses; the values follow through the same LDS
-// buffer.  Threads 0..255 own one digit each for the counts and the
-// look-back.
-template <bool GATHER>
+// consecutive global addresses; the values (and a payload word, if any)
+// follow through the same LDS buffer.  Threads 0..255 own one digit each for
+// the counts and the look-back.
+//
+// MODE 0: plain.  1 (last pass): also gathers each value's tile rectangle
+// from g.rect_in.  2: carries g.pay (pay_in -> pay_out).  3 (last pass):
+// unpacks the payload (x0 | y0 << 8 | x1 << 16 | y1 << 24) into the
+// rectangle and its tile count.
+constexpr int kPassPlain = 0, kPassGather = 1, kPassCarry = 2, kPassUnpack = 3;
+
+template <int MODE>
 __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in, const uint32_t* vals_in,
                                                         uint32_t* keys_out, uint32_t* vals_out, int64_t n_max,
                                                         const unsigned long long* n_dev, int shift, uint32_t mask,
                                                         const uint32_t* ghist, uint64_t* status,
-                                                        uint64_t* status_next, uint32_t* ticket, SortGather g) {
+                                                        uint64_t* status_next, uint32_t* ticket, SortGather g,
+                                                        const uint32_t* pay_in, uint32_t* pay_out) {
+    constexpr bool PAY = MODE == kPassCarry || MODE == kPassUnpack;
     __shared__ uint32_t cnt[kOsWaves][kRadixBins];
     __shared__ unsigned long long s_peer[kOsWaves][kRadixBins];
     __shared__ uint32_t s_buf[kOsTile];
@@ -313,7 +322,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
     const uint32_t d = dig ? threadIdx.x : 0u;
     if (status_next && dig) status_next[b * kRadixBins + d] = 0ull;
     const int64_t base = blk0 + (int64_t)w * (kOsItems * 64);
-    uint32_t k_[kOsItems], v_[kOsItems];
+    uint32_t k_[kOsItems], v_[kOsItems], p_[PAY ? kOsItems : 1];
     uint32_t lp[kOsItems];
 #pragma unroll
     for (int i = 0; i < kOsItems; ++i) {
@@ -351,6 +360,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
     for (int i = 0; i < kOsItems; ++i) {
         const int64_t j = base + i * 64 + lane;
         v_[i] = j < n ? (vals_in ? vals_in[j] : (uint32_t)j) : 0u;
+        if constexpr (PAY) p_[i] = j < n ? pay_in[j] : 0u;
     }
     const uint32_t gstart = os_scan(dig ? ghist[d] : 0u, s_wave);
     const uint32_t dstart = os_scan(tot, s_wave);
@@ -407,11 +417,32 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
         if (q < m && (int64_t)pos[i] < n) {
             const uint32_t v = s_buf[q];
             vals_out[pos[i]] = v;
-            if (GATHER) {
+            if constexpr (MODE == kPassGather) {
                 const uint2 tr = g.rect_in[v];
                 const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu, y1 = tr.y >> 16;
                 g.rect_out[pos[i]] = tr;
                 g.cnt_out[pos[i]] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
+            }
+        }
+    }
+    if constexpr (PAY) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kOsItems; ++i)
+            if (lp[i] != 0xffffffffu) s_buf[lp[i]] = p_[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kOsItems; ++i) {
+            const int q = i * kOsThreads + (int)threadIdx.x;
+            if (q < m && (int64_t)pos[i] < n) {
+                const uint32_t pw = s_buf[q];
+                if constexpr (MODE == kPassCarry) {
+                    pay_out[pos[i]] = pw;
+                } else {
+                    const uint32_t x0 = pw & 0xffu, y0 = (pw >> 8) & 0xffu, x1 = (pw >> 16) & 0xffu, y1 = pw >> 24;
+                    g.rect_out[pos[i]] = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+                    g.cnt_out[pos[i]] = (x1 > x0 && y1 > y0) ? (x1 - x0) * (y1 - y0) : 0u;
+                }
             }
         }
     }
@@ -438,14 +469,24 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
         const int out = p & 1;
         const bool fin = p + 1 == passes;
         SortGather g{};
-        if (fin && last) g = *last;
-        auto kern = g.rect_in ? k_os_pass<true> : k_os_pass<false>;
+        const uint32_t* pin = nullptr;
+        uint32_t* pout = nullptr;
+        auto kern = k_os_pass<kPassPlain>;
+        if (last && last->pay_in) {       // payload carried through every pass
+            g = *last;
+            pin = p == 0 ? last->pay_in : last->pay_buf[(p - 1) & 1];
+            pout = last->pay_buf[p & 1];
+            kern = fin ? k_os_pass<kPassUnpack> : k_os_pass<kPassCarry>;
+        } else if (fin && last && last->rect_in) {
+            g = *last;
+            kern = k_os_pass<kPassGather>;
+        }
         hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kOsThreads), 0, st, ksrc, vsrc,
                            fin && last && last->drop_keys ? nullptr : kbuf[out],
                            vbuf[out], n_max, n_dev, p * kRadixBits,
                            (uint32_t)((1ull << std::min(kRadixBits, nbits - p * kRadixBits)) - 1ull),
                            s.ghist + p * kRadixBins, s.status[p & 1], p + 1 < passes ? s.status[(p + 1) & 1] : nullptr,
-                           s.tickets + p, g);
+                           s.tickets + p, g, pin, pout);
         ksrc = kbuf[out];
         vsrc = vbuf[out];
     }

@@ -30,7 +30,7 @@ def small_workload(kind: str) -> sc.Workload:
     if kind == "uniform4k_128px":
         return sc.make_workload("uniform4k_128px")
     rng = np.random.default_rng({"clusters20k_d3": 71, "clusters20k_d3_bf16": 72, "views3": 73,
-                                 "scenes3": 74, "ragged_d1": 75}[kind])
+                                 "scenes3": 74, "ragged_d1": 75, "wide258": 76}[kind])
     if kind in ("clusters20k_d3", "clusters20k_d3_bf16"):
         bf = kind.endswith("bf16")
         s = sc.make_scene(rng, 20000, 512, 3, sc.screen_matched_mu(200), clusters=True, bf16=bf)
@@ -54,6 +54,13 @@ def small_workload(kind: str) -> sc.Workload:
         cams = [sc.pinhole(77, 45, (0.1, 0.1, -2.5))]
         return sc.Workload(kind, [s], cams, np.array([0], np.int32),
                            [rng.uniform(0, 1, (45, 77, 3)).astype(np.float32)], False)
+    if kind == "wide258":
+        # 258 tiles across: the depth sort gathers tile rectangles instead of
+        # carrying them packed in one word (fewer than 256 tiles per side)
+        s = sc.make_scene(rng, 20000, 256, 1, sc.screen_matched_mu(600), clusters=False)
+        cams = [sc.pinhole(4120, 72, (0.0, 0.0, -3.0))]
+        return sc.Workload(kind, [s], cams, np.array([0], np.int32),
+                           [rng.uniform(0, 1, (72, 4120, 3)).astype(np.float32)], False)
     raise KeyError(kind)
 
 
@@ -64,7 +71,7 @@ def gpu_renderer(wl: sc.Workload, **kw) -> render.Renderer:
     return r
 
 
-SMALL = ["uniform4k_128px", "clusters20k_d3", "clusters20k_d3_bf16", "views3", "scenes3", "ragged_d1"]
+SMALL = ["uniform4k_128px", "clusters20k_d3", "clusters20k_d3_bf16", "views3", "scenes3", "ragged_d1", "wide258"]
 
 
 @pytest.mark.parametrize("kind", SMALL)
