@@ -189,6 +189,19 @@ __device__ inline float wave_sum_to_63(float v) {
     return v;
 }
 
+// Sum of each aligned group of 8 lanes, in the group's last lane (lanes
+// 8m + 7); the other lanes hold partial sums.  Every lane must be active.
+__device__ inline float group8_sum_to_last(float v) {
+    int x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = __float_as_int(v);
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+
 // Bitwise OR over the 64 lanes (every lane must be active); valid in all lanes.
 __device__ inline uint32_t wave_or_u32(uint32_t v) {
 #pragma unroll

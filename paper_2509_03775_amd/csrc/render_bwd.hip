@@ -40,7 +40,8 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
     __shared__ uint32_t s_p[WPB][64];
-    __shared__ float s_o[WPB][64][9];
+    __shared__ uint32_t s_s[WPB][64];                          // gradient slot of each staged record
+    __shared__ __align__(16) float s_red[WPB][2][9][64];        // per-lane sums of a pair of records, by value
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
     if (tile >= desc->n_tiles) return;
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             s_c[w][mine] = c;
             s_b[w][mine] = bl;
             s_p[w][mine] = ((uint32_t)li << 4) | qm;
+            s_s[w][mine] = (uint32_t)slot;
         }
         wave_sync();
         const int cnt = (int)__popcll(km);
@@ -122,7 +124,6 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             const float4 cc = s_c[w][j];
             const float bb = s_b[w][j];
             float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
-            bool any = false;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
@@ -133,7 +134,6 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
                 const bool use = (pos < last[k]) && (alpha >= kMinAlpha);
                 if (__ballot(use) == 0ull) continue;       // no pixel of the quadrant blended it
-                any = true;
                 // Branch-free for the lanes of the quadrant: pairs the forward
                 // did not blend get alpha 0 and zero gradients, which leaves T
                 // and the background sum unchanged.
@@ -163,38 +163,53 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                 a_u += dpx;
                 a_v += dpy;
             }
-            float* so = &s_o[w][j][0];
-            if (any) {
-                const float s0 = wave_sum_to_63(a_u), s1 = wave_sum_to_63(a_v), s2 = wave_sum_to_63(a_a);
-                const float s3 = wave_sum_to_63(a_b), s4 = wave_sum_to_63(a_c), s5 = wave_sum_to_63(a_o);
-                const float s6 = wave_sum_to_63(a_r), s7 = wave_sum_to_63(a_g), s8 = wave_sum_to_63(a_bl);
-                if (lane == 63) {
-                    so[0] = s0; so[1] = s1; so[2] = s2; so[3] = s3; so[4] = s4;
-                    so[5] = s5; so[6] = s6; so[7] = s7; so[8] = s8;
-                }
-            } else if (lane == 63) {
+            // This lane's nine sums for record j, the position sums already
+            // turned into dL/du, dL/dv by the record's natural-log conic (a
+            // linear map, so it is applied before the sum over lanes).
+            {
+                const float na2 = 2.f * kLn2 * gg.z, nb = kLn2 * gg.w, nc2 = 2.f * kLn2 * cc.x;
+                float* red = &s_red[w][j & 1][0][lane];
+                red[0 * 64] = -fmaf(na2, a_u, nb * a_v);
+                red[1 * 64] = -fmaf(nc2, a_v, nb * a_u);
+                red[2 * 64] = a_a;
+                red[3 * 64] = a_b;
+                red[4 * 64] = a_c;
+                red[5 * 64] = a_o;
+                red[6 * 64] = a_r;
+                red[7 * 64] = a_g;
+                red[8 * 64] = a_bl;
+            }
+            if ((j & 1) == 0) {
+                // Sum the pair (records j, j + 1 if staged) over the lanes: the
+                // 2 x 9 value vectors are split into 8-lane segments; lane l of
+                // round t takes segment l & 7 of vector (64 t + l) >> 3, adds its
+                // eight values, the segments of a vector are combined by DPP row
+                // shifts into its last lane, which writes the record's slot.
+                wave_sync();
+                const int nrec = cnt - j < 2 ? cnt - j : 2;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) so[k] = 0.f;
+                for (int t = 0; t < 3; ++t) {
+                    const int p = 64 * t + lane;
+                    const int rec = p >= 72 ? 1 : 0;
+                    const int val = (p - 72 * rec) >> 3;
+                    const bool ok = p < 144 && rec < nrec;
+                    float x = 0.f;
+                    if (ok) {
+                        const float4 lo = *reinterpret_cast<const float4*>(&s_red[w][rec][val][8 * (lane & 7)]);
+                        const float4 hi = *reinterpret_cast<const float4*>(&s_red[w][rec][val][8 * (lane & 7) + 4]);
+                        x = ((lo.x + lo.y) + (lo.z + lo.w)) + ((hi.x + hi.y) + (hi.z + hi.w));
+                    }
+                    x = group8_sum_to_last(x);
+                    if (ok && (lane & 7) == 7) ginst[9 * (int64_t)s_s[w][j + rec] + val] = x;
+                }
+                wave_sync();
             }
         }
         wave_sync();
-        if (slot >= 0) {
+        if (slot >= 0 && qm == 0u) {       // a record no pixel of the tile blended
             float* dst = ginst + 9 * slot;
-            if (qm != 0u) {
-                float t9[9];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) t9[k] = s_o[w][mine][k];
-                // natural-log conic entries of this lane's record
-                const float na2 = 2.f * kLn2 * g.z, nb = kLn2 * g.w, nc2 = 2.f * kLn2 * c.x;
-                const float sx = t9[0], sy = t9[1];
-                t9[0] = -fmaf(na2, sx, nb * sy);
-                t9[1] = -fmaf(nc2, sy, nb * sx);
-#pragma unroll
-                for (int k = 0; k < 9; ++k) dst[k] = t9[k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) dst[k] = 0.f;
-            }
+            for (int k = 0; k < 9; ++k) dst[k] = 0.f;
         }
         wave_sync();
     }

@@ -346,7 +346,7 @@ __device__ inline float blend_alpha(float dx, float dy, const float4& g, const f
     const float t = __builtin_fmaf(g.z, dx, g.w * dy);
     float pw = __builtin_fmaf(t, dx, (c.x * dy) * dy);
     pclamp = pw > 0.0f;
-    pw = pclamp ? 0.0f : pw;
+    pw = fminf(pw, 0.0f);
     G = __builtin_amdgcn_exp2f(pw);
     const float og = c.y * G;
     return og < kMaxAlpha ? og : kMaxAlpha;

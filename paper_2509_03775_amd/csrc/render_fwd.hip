@@ -208,20 +208,21 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
     const float bx0 = (float)x0, by0 = (float)y0;
     const float bxm = (float)min(x0 + kTile - 1, vd.W - 1), bym = (float)min(y0 + kTile - 1, vd.H - 1);
 
+    // T > 0 while the pixel is live; a finished (or outside) pixel keeps -T,
+    // so a dead lane takes the termination branch and changes nothing
     float T[4], C0[4], C1[4], C2[4], fpx[4], fpy[4];
     uint32_t last[4], nb[4];
-    bool live[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
-        T[k] = 1.f; C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
+        T[k] = (px < vd.W && py < vd.H) ? 1.f : -1.f;
+        C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
         fpx[k] = (float)px;
         fpy[k] = (float)py;
-        live[k] = px < vd.W && py < vd.H;
     }
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     for (uint32_t b = start; b < end; b += 64) {
-        if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
+        if (__ballot((T[0] > 0.f) | (T[1] > 0.f) | (T[2] > 0.f) | (T[3] > 0.f)) == 0ull) break;
         const uint32_t idx = b + lane;
         uint32_t qm = 0u;
         float4 g, c;
@@ -243,18 +244,24 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
         }
         wave_sync();
         const int cnt = (int)__popcll(km);
-        uint32_t hit_lo = 0u, hit_hi = 0u;     // staged records this lane blended (bit j)
+        uint64_t hit = 0ull;     // staged records this lane blended (bit j)
         for (int j = 0; j < cnt; ++j) {
-            if (__ballot(live[0] | live[1] | live[2] | live[3]) == 0ull) break;
+            // quadrants with a live pixel (wave-uniform)
+            uint32_t qlive = 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (__ballot(T[k] > 0.f) != 0ull) qlive |= 1u << k;
+            if (qlive == 0u) break;
             const float4 gg = s_g[w][j];
             const float4 cc = s_c[w][j];
             const float bb = s_b[w][j];
             const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
             const uint32_t pos = pq >> 4;
+            const uint32_t act = pq & qlive;
+            const uint64_t jbit = 1ull << j;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
-                if (!live[k]) continue;
+                if (!((act >> k) & 1u)) continue;          // wave-uniform quadrant skip
                 const float dx = fpx[k] - gg.x;
                 const float dy = fpy[k] - gg.y;
                 float G;
@@ -262,21 +269,21 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
                 const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
                 if (alpha < kMinAlpha) continue;
                 const float Tn = T[k] * (1.f - alpha);
-                if (Tn < kMinT) { live[k] = false; continue; }
+                if (Tn < kMinT) {      // finished here (or already): keep -T
+                    T[k] = -fabsf(T[k]);
+                    continue;
+                }
                 const float wgt = alpha * T[k];
                 C0[k] = fmaf(wgt, cc.z, C0[k]);
                 C1[k] = fmaf(wgt, cc.w, C1[k]);
                 C2[k] = fmaf(wgt, bb, C2[k]);
                 T[k] = Tn;
                 last[k] = pos;
+                hit |= jbit;           // this lane blended staged record j
                 if constexpr (STATS) ++nb[k];
             }
-            // a pixel blended this record iff its last position is now this one
-            const uint32_t hit = ((last[0] == pos) | (last[1] == pos) | (last[2] == pos) | (last[3] == pos)) ? 1u : 0u;
-            if (j < 32) hit_lo |= hit << j; else hit_hi |= hit << (j - 32);
         }
-        hit_lo = wave_or_u32(hit_lo);
-        hit_hi = wave_or_u32(hit_hi);
+        const uint32_t hit_lo = wave_or_u32((uint32_t)hit), hit_hi = wave_or_u32((uint32_t)(hit >> 32));
         const uint32_t blended = mine < 32 ? (hit_lo >> mine) & 1u : (hit_hi >> (mine - 32)) & 1u;
         if (idx < end) qbits[idx] = (qm != 0u && blended) ? (uint8_t)qm : (uint8_t)0;
         wave_sync();
@@ -286,10 +293,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
         const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
         if (px < vd.W && py < vd.H) {
             const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
-            image[3 * p + 0] = C0[k] + T[k] * vd.bg[0];
-            image[3 * p + 1] = C1[k] + T[k] * vd.bg[1];
-            image[3 * p + 2] = C2[k] + T[k] * vd.bg[2];
-            T_final[p] = T[k];
+            const float Tk = fabsf(T[k]);
+            image[3 * p + 0] = C0[k] + Tk * vd.bg[0];
+            image[3 * p + 1] = C1[k] + Tk * vd.bg[1];
+            image[3 * p + 2] = C2[k] + Tk * vd.bg[2];
+            T_final[p] = Tk;
             n_last[p] = (int32_t)last[k];
             if constexpr (STATS) n_blend[p] = (int32_t)nb[k];
         }
