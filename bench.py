@@ -51,8 +51,8 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", "render_common.h", "cgs_internal.h"),
                   "k_blend_fwd": ("render_fwd.hip", "render_common.h", "cgs_internal.h")}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "047d6eb6bf9ac4ca", "read": 3310811811, "write": 867177824},
-    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "3a666dfceca13487", "read": 1547710177, "write": 235046072},
+    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "d03ebf8e2f297981", "read": 3286372801, "write": 729503104},
+    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "0b012b4f0f00bd84", "read": 1549012277, "write": 235011856},
 }
 
 
