@@ -17,7 +17,14 @@
  *    live in host memory and are read during the call only.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
  *    the call returns without synchronising.  No host<->device copies are
- *    made, so calls may be captured into a HIP graph.
+ *    made, so calls may be captured into a HIP graph.  cgs_render_forward
+ *    and cgs_render_backward fork independent parts of their work (a scan, a
+ *    sort by codebook row) to a second stream the library creates per device
+ *    on first use (default priority, kept until the process ends) and join
+ *    them back by events before returning: the caller's stream orders all of
+ *    it, and a capture of that stream takes both.  The first call on a
+ *    device should not be inside a capture (the second stream is not created
+ *    then and the work stays on the caller's stream).
  *  - The return value covers host-side validation only (null pointers,
  *    negative sizes, unsupported options, workspace too small, launch
  *    failure).  Conditions found on the device are written to the caller's

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "cgs_internal.h"
 
@@ -233,6 +234,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.radix_ws = take(radix_ws_bytes(nmax));
     p.scan_blocks_max = (int64_t)scan_bsum_count(nmax);
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
+    p.scan_bsum2 = take(8 * (size_t)p.scan_blocks_max);
     p.slot_off = take(4 * (size_t)R);
     p.ginst = take(4 * 9 * (size_t)cap);
     p.rec_grad = take(4 * 9 * (size_t)R);
@@ -265,6 +267,53 @@ hipError_t upload_desc(const Host& h, void* ws, hipStream_t st) {
 
 hipError_t mark(const Host& h, int i, hipStream_t st) {
     return h.events ? hipEventRecord(h.events[i], st) : hipSuccess;
+}
+
+// A second stream per device for work that does not depend on the kernels
+// just before it on the caller's stream.  Created on first use (default
+// priority, non-blocking) with two events and kept until the process ends;
+// work is forked to it and joined back by events, so the caller's stream
+// still orders everything and a graph capture follows the dependencies.  It
+// is not created while the caller's stream is being captured (the work then
+// stays on the caller's stream), and calls that use it are serialised per
+// device from fork to join.
+struct Side {
+    std::mutex mu;
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool failed = false;
+};
+
+Side* side_stream(hipStream_t caller) {
+    static Side sides[64];
+    static std::mutex create_mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    Side& sd = sides[dev];
+    std::lock_guard<std::mutex> lk(create_mu);
+    if (sd.s || sd.failed) return sd.s ? &sd : nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(caller, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) {
+        sd.failed = true;
+        sd.s = nullptr;
+        return nullptr;
+    }
+    return &sd;
+}
+
+// Fork: the side stream waits for everything enqueued on `st` so far.
+hipError_t side_fork(Side* sd, hipStream_t st) {
+    hipError_t e = hipEventRecord(sd->fork, st);
+    return e == hipSuccess ? hipStreamWaitEvent(sd->s, sd->fork, 0) : e;
+}
+
+// Join: `st` waits for everything enqueued on the side stream so far.
+hipError_t side_join(Side* sd, hipStream_t st) {
+    hipError_t e = hipEventRecord(sd->join, sd->s);
+    return e == hipSuccess ? hipStreamWaitEvent(st, sd->join, 0) : e;
 }
 
 }  // namespace
@@ -331,6 +380,16 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect), st));
     CGS_TRY(mark(h, 1, st));
+    // backward gradient slots of each record, in record order: needed only by
+    // the backward, so scanned beside the depth sort on the side stream
+    Side* side = side_stream(st);
+    std::unique_lock<std::mutex> side_lk;
+    if (side) {
+        side_lk = std::unique_lock<std::mutex>(side->mu);
+        CGS_TRY(side_fork(side, st));
+    }
+    CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), nullptr, h.d.n_rec, at<uint32_t>(ws, p.slot_off), nullptr,
+                     at<unsigned long long>(ws, p.scan_bsum2), side ? side->s : st));
     // depth order of every record (stable: ties keep record order)
     uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
     uint32_t* dv[2] = {at<uint32_t>(ws, p.dsort_val[0]), at<uint32_t>(ws, p.dsort_val[1])};
@@ -354,8 +413,6 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
     CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.rect_d),
                         at<uint32_t>(ws, p.cnt_d), cnt, ik[1], iv[1], st));
-    // backward gradient slots of each record, in record order
-    CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), nullptr, h.d.n_rec, at<uint32_t>(ws, p.slot_off), nullptr, bsum, st));
     int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
     CGS_TRY(e);
     if (ib != h.inst_buf) return CGS_EHIP;
@@ -371,6 +428,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(mark(h, 2, st));
     CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
                              at<float4>(ws, p.rec), at<uint8_t>(ws, p.qbits), image, T_final, n_last, h.n_blend, st));
+    if (side) CGS_TRY(side_join(side, st));
     CGS_TRY(mark(h, 3, st));
     return CGS_OK;
 }
@@ -449,6 +507,27 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(mark(h, 4, st));
+    uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
+    uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
+    uint32_t* rr = at<uint32_t>(ws, p.row_start);
+    // Single-codebook layout: the sort of Gaussians by row depends only on
+    // the indices, so it runs on the side stream beside the backward blend
+    // and the chain rule.
+    auto sort_rows = [&](int part_i, int64_t rows, hipStream_t s2, int* pb) -> hipError_t {
+        hipError_t e = launch_row_keys(dd, part_i, h.d.n_gauss, pk[1], s2);
+        if (e != hipSuccess) return e;
+        *pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), sws, s2, &e);
+        if (e != hipSuccess) return e;
+        return tile_ranges(pk[*pb], nullptr, h.d.n_gauss, rows, rr, s2);
+    };
+    Side* side = single ? side_stream(st) : nullptr;
+    std::unique_lock<std::mutex> side_lk;
+    int pb0 = 0;
+    if (side) {
+        side_lk = std::unique_lock<std::mutex>(side->mu);
+        CGS_TRY(side_fork(side, st));
+        CGS_TRY(sort_rows(0, h.d.sr_rows_total, side->s, &pb0));
+    }
     float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
                              at<float4>(ws, p.rec), at<const uint8_t>(ws, p.qbits), at<uint32_t>(ws, p.depth_key),
@@ -461,9 +540,6 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
                          at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), at<uint32_t>(ws, p.rec_flag),
                          gth, st));
     CGS_TRY(mark(h, 6, st));
-    uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
-    uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
-    uint32_t* rr = at<uint32_t>(ws, p.row_start);
     const int nparts = single ? 1 : 2;
     for (int part_i = 0; part_i < nparts; ++part_i) {
         const int64_t rows = part_i == 0 ? h.d.sr_rows_total : h.d.sh_rows_total;
@@ -471,11 +547,9 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
         if (single) { c0 = 0; D = h.d.row_width; }
         else if (part_i == 0) { c0 = 0; D = h.opacity_mode ? 8 : 7; }
         else { c0 = 8; D = h.d.row_width - 8; }
-        CGS_TRY(launch_row_keys(dd, part_i, h.d.n_gauss, pk[1], st));
-        hipError_t e;
-        int pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), sws, st, &e);
-        CGS_TRY(e);
-        CGS_TRY(tile_ranges(pk[pb], nullptr, h.d.n_gauss, rows, rr, st));
+        int pb = pb0;
+        if (side) CGS_TRY(side_join(side, st));
+        else CGS_TRY(sort_rows(part_i, rows, st, &pb));
         CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
     }
     CGS_TRY(mark(h, 7, st));
