@@ -51,8 +51,8 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", "render_common.h", "cgs_internal.h"),
                   "k_blend_fwd": ("render_fwd.hip", "render_common.h", "cgs_internal.h")}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "d03ebf8e2f297981", "read": 3286372801, "write": 729503104},
-    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "0b012b4f0f00bd84", "read": 1549012277, "write": 235011856},
+    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "7bd589610e4e4573", "read": 3286201579, "write": 729497664},
+    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "92600b220563afd9", "read": 1549057013, "write": 235018928},
 }
 
 

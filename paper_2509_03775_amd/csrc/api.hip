@@ -47,6 +47,20 @@ int mh_transition_host(uint64_t, uint32_t);
 
 namespace {
 
+// Byte offsets of the forward/backward workspace arrays (host-side plan).
+struct WsPlan {
+    size_t desc, counters;
+    size_t rec, depth_key, tile_rect, ntiles, prect, pay[2];
+    size_t dsort_key[2], dsort_val[2];
+    size_t offs, rect_d, cnt_d;
+    size_t inst_key[2], inst_val[2];
+    size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
+    size_t radix_ws, scan_bsum, scan_bsum2;
+    size_t slot_off, ginst, rec_grad, rec_flag, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t total;
+    int64_t scan_blocks_max;
+};
+
 int bits_for(int64_t n) {   // bits needed for values in [0, n)
     int b = 1;
     while (b < 40 && ((int64_t)1 << b) < n) ++b;

@@ -117,20 +117,6 @@ struct DevCounters {
     unsigned long long pad[6];
 };
 
-// ---------------------------------------------------------- workspace plan
-struct WsPlan {
-    size_t desc, counters;
-    size_t rec, depth_key, tile_rect, ntiles, prect, pay[2];
-    size_t dsort_key[2], dsort_val[2];
-    size_t offs, rect_d, cnt_d;
-    size_t inst_key[2], inst_val[2];
-    size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
-    size_t radix_ws, scan_bsum, scan_bsum2;
-    size_t slot_off, ginst, rec_grad, rec_flag, gtheta, psort_key[2], psort_val[2], row_start;
-    size_t total;
-    int64_t scan_blocks_max;
-};
-
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // ------------------------------------------------------------ wave helpers
