@@ -91,23 +91,31 @@ __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc
     if (j0 >= desc->n_rec) return;
     const int64_t j = j0 + lane;
     const bool valid = j < desc->n_rec;
-    const uint32_t o0 = __builtin_amdgcn_readfirstlane(offs[j0]);
-    uint32_t rel = 0, c = 0, r = 0;
-    if (valid) {
-        r = sorted_rec[j];
-        rel = offs[j] - o0;
-        c = cnt_d[j];
-    }
+    // every load this wave needs is issued at once (lanes past the end read
+    // the wave's first record); lane 0's offset is the wave's base
+    const int64_t jc = valid ? j : j0;
+    const bool emit = cnt->n_inst_ok != 0ull;
+    const uint2 tr = rect_d[jc];
+    const uint32_t oj = offs[jc];
+    const uint32_t r = sorted_rec[jc];
+    const uint32_t c = valid ? cnt_d[jc] : 0u;
+    const uint32_t o0 = __builtin_amdgcn_readfirstlane(oj);
+    const uint32_t rel = valid ? oj - o0 : 0u;
     uint32_t endrel = valid ? rel + c : 0u;
     endrel = wave_max_u32(endrel);
-    if (cnt->n_inst_ok == 0ull) return;
+    if (!emit) return;
+    // the record's view: views hold consecutive record ranges, read with
+    // scalar loads (no per-lane search through memory)
+    uint32_t tx = (uint32_t)desc->views[0].tiles_x, toff = (uint32_t)desc->views[0].tile_off;
+    for (int v = 1; v < desc->n_views; ++v) {
+        const ViewDesc& vd = desc->views[v];
+        if ((int64_t)r >= vd.rec_off) { tx = (uint32_t)vd.tiles_x; toff = (uint32_t)vd.tile_off; }
+    }
     if (valid && c > 0) {
-        const uint2 tr = rect_d[j];
         const uint32_t x0 = tr.x & 0xffffu, y0 = tr.x >> 16, x1 = tr.y & 0xffffu;
-        const ViewDesc& vd = desc->views[find_view_by_rec(desc, r)];
         s_w[w][lane] = x1 - x0;
-        s_tx[w][lane] = (uint32_t)vd.tiles_x;
-        s_base[w][lane] = (uint32_t)vd.tile_off + y0 * (uint32_t)vd.tiles_x + x0;
+        s_tx[w][lane] = tx;
+        s_base[w][lane] = toff + y0 * tx + x0;
         s_r[w][lane] = r;
     }
     s_rel[w][lane] = valid ? rel : endrel;
