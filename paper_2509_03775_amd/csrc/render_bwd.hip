@@ -223,7 +223,9 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // as 9 floats per record, only for records with a nonzero sum; a bit per
 // record (two words per wavefront, records of one view per wavefront) says
 // which, so records no walk reached cost neither a write nor a read.
-__device__ const float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+// Zeros read in place of a slot not reached (global, never written: a
+// selection between it and a slot stays in the global address space).
+__device__ float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
 __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
                                                   const uint32_t* __restrict__ slot_off,
@@ -240,12 +242,14 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     if (i >= desc->scenes[vd.scene].n) return;
     const int64_t r = vd.rec_off + i;
     float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // the record's four words are loaded together, before the first use
+    const uint2 tr = tile_rect[r];
+    const uint32_t so = slot_off[r];
+    const uint32_t key = depth_key[r];
     const uint32_t nt = cnt->n_inst_ok != 0ull ? ntiles[r] : 0u;
     if (nt != 0u) {
-        const float* gi = ginst + 9 * (int64_t)slot_off[r];
-        const uint2 tr = tile_rect[r];
+        const float* gi = ginst + 9 * (int64_t)so;
         const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rw = (int)(tr.y & 0xffffu) - rx0;
-        const uint32_t key = depth_key[r];
         const uint2* cut = tile_cut + vd.tile_off + (int64_t)ry0 * vd.tiles_x + rx0;
         int ex = 0;
         int64_t erow = 0;
@@ -638,18 +642,27 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const BatchDesc* __restrict
             const int col = cb + lane;
             const bool on = col < D;
             float acc = 0.f;
-            int64_t q = p;
-            for (; q + 4 <= e; q += 4) {
-                const float a0 = on ? gtheta[(int64_t)sval[q] * ld + c0 + col] : 0.f;
-                const float a1 = on ? gtheta[(int64_t)sval[q + 1] * ld + c0 + col] : 0.f;
-                const float a2 = on ? gtheta[(int64_t)sval[q + 2] * ld + c0 + col] : 0.f;
-                const float a3 = on ? gtheta[(int64_t)sval[q + 3] * ld + c0 + col] : 0.f;
-                acc += a0;
-                acc += a1;
-                acc += a2;
-                acc += a3;
+            // 64 sorted Gaussian ids per coalesced load, broadcast by readlane;
+            // eight rows' loads in flight; the sum keeps position order
+            for (int64_t qb = p; qb < e; qb += 64) {
+                const int nq = (int)(e - qb < 64 ? e - qb : 64);
+                const uint32_t ids = lane < nq ? sval[qb + lane] : 0u;
+                int k = 0;
+                for (; k + 8 <= nq; k += 8) {
+                    float a[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)ids, k + t);
+                        a[t] = on ? gtheta[(int64_t)gid * ld + c0 + col] : 0.f;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) acc += a[t];
+                }
+                for (; k < nq; ++k) {
+                    const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)ids, k);
+                    acc += on ? gtheta[(int64_t)gid * ld + c0 + col] : 0.f;
+                }
             }
-            for (; q < e; ++q) acc += on ? gtheta[(int64_t)sval[q] * ld + c0 + col] : 0.f;
             if (on) {
                 o.ptr[lr * o.stride + o.col0 + oshift + col] = acc;
                 if (desc->sgld) sgld_row(desc, sc, lr, c0 + col, acc);
