@@ -48,18 +48,36 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 # scaled by what the same counter read for a 512 MiB torch.neg copy (FETCH
 # 2.0, WRITE 1.0).  A figure holds only for the kernel sources and schedule it
 # was taken on: the first 16 hex digits of the SHA-256 of those sources.
-KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", "render_common.h", "cgs_internal.h"),
-                  "k_blend_fwd": ("render_fwd.hip", "render_common.h", "cgs_internal.h")}
+# The measured kernel's own source (its definition, from "template" to the
+# closing brace, inside the named file) and the headers it includes.
+KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", ("render_common.h", "cgs_internal.h")),
+                  "k_blend_fwd": ("render_fwd.hip", ("render_common.h", "cgs_internal.h"))}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "7bd589610e4e4573", "read": 3286201579, "write": 729497664},
-    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "92600b220563afd9", "read": 1549057013, "write": 235018928},
+    ("k_blend_bwd", HEADLINE, (1, 2)): {"sources": "faad185bcfb1cdc3", "read": 3286624975, "write": 729415616},
+    ("k_blend_fwd", HEADLINE, (1, 2)): {"sources": "e12ae1536197b080", "read": 1549391583, "write": 234983504},
 }
+
+
+def kernel_text(src: str, kernel: str) -> str:
+    """The definition of `kernel` in a source file: from the template line
+    (or the __global__ line) before its name to the first closing brace at
+    column 0 after it."""
+    at = src.index(" " + kernel + "(")
+    start = src.rfind("\ntemplate", 0, at)
+    glob = src.rfind("\n__global__", 0, at)
+    start = max(start, glob) + 1
+    end = src.index("\n}\n", at) + 3
+    return src[start:end]
 
 
 def sources_digest(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_2509_03775_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2509_03775_amd", "csrc")
+    body_file, headers = KERNEL_SOURCES[kernel]
+    with open(os.path.join(csrc, body_file)) as fh:
+        h.update(kernel_text(fh.read(), kernel).encode())
+    for f in headers:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
