@@ -156,7 +156,10 @@ def test_batched_equals_per_view_calls():
 
 def test_graph_replay_matches_eager():
     """forward + L1 + backward captured once in a HIP graph; three replays
-    (with eager work in between) equal the eager step bit for bit."""
+    (with eager work in between) equal the eager step bit for bit.  The whole
+    workspace is overwritten with garbage before each replay, so every value
+    a replay reads (including what the library's second stream computes) must
+    come from the graph itself."""
     name = "uneven16_512px"
     say(f"[graph replay] {name}")
     wl, r = workload_and_renderer(name)
@@ -188,6 +191,9 @@ def test_graph_replay_matches_eager():
         r.image.zero_()
         for c in r.grad_cb:
             c.zero_()
+        for m in r.grad_means:
+            m.zero_()
+        r.ws.fill_(0x5A)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
