@@ -710,7 +710,21 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const
                                             float inv_n, float* __restrict__ grad, float* __restrict__ part) {
     __shared__ float s[256];
     float acc = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // 16-byte loads and stores over the aligned bulk, single values after it
+    const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
+                       reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
+    const int64_t n4 = vec ? n / 4 : 0;
+    for (int64_t q = t0; q < n4; q += stride) {
+        const float4 a = reinterpret_cast<const float4*>(img)[q], b = reinterpret_cast<const float4*>(tgt)[q];
+        const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+        acc += fabsf(d0); acc += fabsf(d1); acc += fabsf(d2); acc += fabsf(d3);
+        reinterpret_cast<float4*>(grad)[q] =
+            make_float4(d0 > 0.f ? inv_n : (d0 < 0.f ? -inv_n : 0.f), d1 > 0.f ? inv_n : (d1 < 0.f ? -inv_n : 0.f),
+                        d2 > 0.f ? inv_n : (d2 < 0.f ? -inv_n : 0.f), d3 > 0.f ? inv_n : (d3 < 0.f ? -inv_n : 0.f));
+    }
+    for (int64_t i = 4 * n4 + t0; i < n; i += stride) {
         const float d = img[i] - tgt[i];
         acc += fabsf(d);
         grad[i] = d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f);
