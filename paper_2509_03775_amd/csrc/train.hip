@@ -18,7 +18,9 @@
 //
 // Two tiled passes per 16x16 pixel tile (256 threads, one pixel each): the
 // statistics pass stages the tile plus a 5-pixel halo of image and target in
-// LDS, blurs rows then columns, and writes the three partials per channel
+// LDS, blurs rows then columns (each blur thread slides its 11-tap window
+// along one line in registers, the taps added in the same order for every
+// output), and writes the three partials per channel
 // and the tile's L1 and SSIM sums; the gradient pass blurs the partial maps
 // the same way and combines them with the image, the target and the L1 term.
 // A last single-workgroup pass adds the tile sums in a fixed order in FP64.
@@ -52,10 +54,11 @@ __device__ inline int loss_view_of(const LossViews& v, int64_t t) {
 __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* __restrict__ image,
                                                     const float* __restrict__ target, float* __restrict__ part,
                                                     double* __restrict__ sums) {
-    __shared__ float s_x[3][kSpan][kSpan];
-    __shared__ float s_y[3][kSpan][kSpan];
+    __shared__ float s_xy[2][3][kSpan][kSpan];     // image, target (tile + halo); then the column sums
     __shared__ float s_h[15][kSpan][kTile];
     __shared__ double s_red[2][256];
+    auto s_x = s_xy[0];
+    auto s_y = s_xy[1];
     const int64_t t = blockIdx.x;
     const int v = loss_view_of(lv, t);
     const int H = lv.H[v], W = lv.W[v];
@@ -75,29 +78,55 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
         }
     }
     __syncthreads();
-    // rows: five window sums per (row, output column, channel)
-    for (int i = threadIdx.x; i < kSpan * kTile * 3; i += 256) {
-        const int r = i / (kTile * 3), rem = i % (kTile * 3);
-        const int ch = rem / kTile, c = rem % kTile;
-        float hx = 0.f, hy = 0.f, hxx = 0.f, hyy = 0.f, hxy = 0.f;
+    // rows: five window sums per (row, output column, channel); a thread
+    // takes eight outputs of one row and slides the window in registers
+    if (threadIdx.x < kSpan * 3 * 2) {
+        const int r = threadIdx.x / 6, ch = (threadIdx.x / 2) % 3, c0 = 8 * (threadIdx.x & 1);
+        float a[18], b[18];
 #pragma unroll
-        for (int k = 0; k < 11; ++k) {
-            const float a = s_x[ch][r][c + k], b = s_y[ch][r][c + k], w = kWin[k];
-            hx = fmaf(w, a, hx);
-            hy = fmaf(w, b, hy);
-            hxx = fmaf(w, a * a, hxx);
-            hyy = fmaf(w, b * b, hyy);
-            hxy = fmaf(w, a * b, hxy);
+        for (int k = 0; k < 18; ++k) { a[k] = s_x[ch][r][c0 + k]; b[k] = s_y[ch][r][c0 + k]; }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            float hx = 0.f, hy = 0.f, hxx = 0.f, hyy = 0.f, hxy = 0.f;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) {
+                const float aa = a[o + k], bb = b[o + k], w = kWin[k];
+                hx = fmaf(w, aa, hx);
+                hy = fmaf(w, bb, hy);
+                hxx = fmaf(w, aa * aa, hxx);
+                hyy = fmaf(w, bb * bb, hyy);
+                hxy = fmaf(w, aa * bb, hxy);
+            }
+            s_h[5 * ch + 0][r][c0 + o] = hx;
+            s_h[5 * ch + 1][r][c0 + o] = hy;
+            s_h[5 * ch + 2][r][c0 + o] = hxx;
+            s_h[5 * ch + 3][r][c0 + o] = hyy;
+            s_h[5 * ch + 4][r][c0 + o] = hxy;
         }
-        s_h[5 * ch + 0][r][c] = hx;
-        s_h[5 * ch + 1][r][c] = hy;
-        s_h[5 * ch + 2][r][c] = hxx;
-        s_h[5 * ch + 3][r][c] = hyy;
-        s_h[5 * ch + 4][r][c] = hxy;
     }
     __syncthreads();
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
     const int gx = x0 + tx, gy = y0 + ty;
+    float cx[3], cy[3];     // this pixel's image and target values (the staging buffer is reused below)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) { cx[ch] = s_x[ch][ty + kHalo][tx + kHalo]; cy[ch] = s_y[ch][ty + kHalo][tx + kHalo]; }
+    __syncthreads();
+    // columns: a thread takes one (quantity, column) and slides down it
+    float* s_m = &s_xy[0][0][0][0];     // [15][kTile][kTile]
+    if (threadIdx.x < 15 * kTile) {
+        const int l = threadIdx.x / kTile, c = threadIdx.x % kTile;
+        float col[kSpan];
+#pragma unroll
+        for (int k = 0; k < kSpan; ++k) col[k] = s_h[l][k][c];
+#pragma unroll
+        for (int o = 0; o < kTile; ++o) {
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], col[o + k], a);
+            s_m[(l * kTile + o) * kTile + c] = a;
+        }
+    }
+    __syncthreads();
     double l1 = 0.0, ss = 0.0;
     if (gx < W && gy < H) {
         const int64_t p = lv.pix_off[v] + (int64_t)gy * W + gx;
@@ -106,12 +135,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
         for (int ch = 0; ch < 3; ++ch) {
             float m[5];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                float a = 0.f;
-#pragma unroll
-                for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], s_h[5 * ch + q][ty + k][tx], a);
-                m[q] = a;
-            }
+            for (int q = 0; q < 5; ++q) m[q] = s_m[((5 * ch + q) * kTile + ty) * kTile + tx];
             const float mx = m[0], my = m[1];
             const float A1 = 2.f * mx * my + kC1;
             const float A2 = 2.f * (m[4] - mx * my) + kC2;
@@ -123,7 +147,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
             out[3 * ch + 1] = -S / B2;
             out[3 * ch + 2] = 2.f * A1 * inv;
             ss += (double)S;
-            l1 += (double)fabsf(s_x[ch][ty + kHalo][tx + kHalo] - s_y[ch][ty + kHalo][tx + kHalo]);
+            l1 += (double)fabsf(cx[ch] - cy[ch]);
         }
     }
     s_red[0][threadIdx.x] = l1;
@@ -162,13 +186,34 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __
         for (int q = 0; q < 9; ++q) s_p[q][r][c] = in ? pp[9 * p + q] : 0.f;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kSpan * kTile * 9; i += 256) {
-        const int r = i / (kTile * 9), rem = i % (kTile * 9);
-        const int q = rem / kTile, c = rem % kTile;
-        float a = 0.f;
+    // rows, then columns, each thread sliding an 11-tap window along one line
+    if (threadIdx.x < kSpan * 9) {
+        const int r = threadIdx.x / 9, q = threadIdx.x % 9;
+        float row[kSpan];
 #pragma unroll
-        for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], s_p[q][r][c + k], a);
-        s_h[q][r][c] = a;
+        for (int k = 0; k < kSpan; ++k) row[k] = s_p[q][r][k];
+#pragma unroll
+        for (int o = 0; o < kTile; ++o) {
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], row[o + k], a);
+            s_h[q][r][o] = a;
+        }
+    }
+    __syncthreads();
+    float* s_m = &s_p[0][0][0];     // [9][kTile][kTile], the partials are no longer needed
+    if (threadIdx.x < 9 * kTile) {
+        const int q = threadIdx.x / kTile, c = threadIdx.x % kTile;
+        float col[kSpan];
+#pragma unroll
+        for (int k = 0; k < kSpan; ++k) col[k] = s_h[q][k][c];
+#pragma unroll
+        for (int o = 0; o < kTile; ++o) {
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], col[o + k], a);
+            s_m[(q * kTile + o) * kTile + c] = a;
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
@@ -179,12 +224,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __
     for (int ch = 0; ch < 3; ++ch) {
         float b[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            float a = 0.f;
-#pragma unroll
-            for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], s_h[3 * ch + q][ty + k][tx], a);
-            b[q] = a;
-        }
+        for (int q = 0; q < 3; ++q) b[q] = s_m[((3 * ch + q) * kTile + ty) * kTile + tx];
         const float x = image[3 * p + ch], y = target[3 * p + ch];
         const float d = x - y;
         const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
@@ -193,19 +233,30 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __
     }
 }
 
-// loss = (1 - lambda) L1sum / n + lambda (1 - Ssum / n), sums in FP64 in a fixed order
-__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ sums, int64_t nt, int64_t n,
-                                                    float lambda, float* __restrict__ loss) {
-    __shared__ double s[2][256];
+// loss = (1 - lambda) L1sum / n + lambda (1 - Ssum / n), sums in FP64 in a fixed
+// order; each thread loads eight tile pairs at a time, then adds them in index order
+__global__ __launch_bounds__(1024) void k_loss_final(const double* __restrict__ sums, int64_t nt, int64_t n,
+                                                     float lambda, float* __restrict__ loss) {
+    __shared__ double s[2][1024];
     double a = 0.0, b = 0.0;
-    for (int64_t i = threadIdx.x; i < nt; i += 256) {
-        a += sums[2 * i];
-        b += sums[2 * i + 1];
+    for (int64_t i0 = threadIdx.x; i0 < nt; i0 += 8 * 1024) {
+        double ua[8], ub[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = i0 + (int64_t)k * 1024;
+            ua[k] = i < nt ? sums[2 * i] : 0.0;
+            ub[k] = i < nt ? sums[2 * i + 1] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a += ua[k];
+            b += ub[k];
+        }
     }
     s[0][threadIdx.x] = a;
     s[1][threadIdx.x] = b;
     __syncthreads();
-    for (int d = 128; d > 0; d >>= 1) {
+    for (int d = 512; d > 0; d >>= 1) {
         if ((int)threadIdx.x < d) {
             s[0][threadIdx.x] += s[0][threadIdx.x + d];
             s[1][threadIdx.x] += s[1][threadIdx.x + d];
@@ -229,7 +280,7 @@ hipError_t launch_loss_recon(const LossViews& lv, const float* image, const floa
         hipLaunchKernelGGL(k_ssim_grad, dim3((unsigned)nt), dim3(256), 0, st, lv, image, target, part,
                            (1.f - lambda) * inv, lambda * inv, grad);
     }
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, sums, nt, n, lambda, loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1024), 0, st, sums, nt, n, lambda, loss);
     return hipGetLastError();
 }
 
