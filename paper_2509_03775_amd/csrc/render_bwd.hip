@@ -344,6 +344,54 @@ __device__ inline void sgld_row(const BatchDesc* desc, int s, int64_t lr, int gc
 }
 
 // ------------------------------------------------------------ chain rule
+// The Gaussian's SH coefficients as the chain rule holds them across its view
+// loop.  BF16 rows stay packed, two values per register, and are widened at
+// each use (exact); `pin` makes the packed words opaque so the widened values
+// are not kept live across the loop.  This halves the registers the rows hold
+// beside the 3 NCO gradient accumulators.
+template <int DT, int SHD>
+struct ShRegs {
+    static constexpr int N = 3 * (SHD + 1) * (SHD + 1);
+    float v[N];
+    __device__ void load(const SceneDesc&, int64_t, const GaussParams& gp, bool) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = gp.sh[i];
+    }
+    __device__ float operator[](int i) const { return v[i]; }
+    __device__ void pin() {}
+};
+
+template <int SHD>
+struct ShRegs<CGS_BF16, SHD> {
+    static constexpr int N = 3 * (SHD + 1) * (SHD + 1);
+    uint32_t w[(N + 1) / 2];
+    __device__ void load(const SceneDesc& sd, int64_t g, const GaussParams&, bool vec) {
+        const uint16_t* row = static_cast<const uint16_t*>(sd.sh) + sd.idx_sh[g] * sd.sh_stride + sd.sh_col0;
+        if constexpr (N % 8 == 0) {
+            if (vec) {      // host-checked: 16-byte aligned rows
+                const uint4* r4 = reinterpret_cast<const uint4*>(row);
+#pragma unroll
+                for (int k = 0; k < N / 8; ++k) {
+                    const uint4 u = r4[k];
+                    w[4 * k] = u.x; w[4 * k + 1] = u.y; w[4 * k + 2] = u.z; w[4 * k + 3] = u.w;
+                }
+                return;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < (N + 1) / 2; ++k)
+            w[k] = (uint32_t)row[2 * k] | (2 * k + 1 < N ? (uint32_t)row[2 * k + 1] << 16 : 0u);
+    }
+    __device__ float operator[](int i) const {
+        const uint32_t x = w[i >> 1];
+        return __uint_as_float((i & 1) ? (x & 0xffff0000u) : (x << 16));
+    }
+    __device__ void pin() {
+#pragma unroll
+        for (int k = 0; k < (N + 1) / 2; ++k) asm volatile("" : "+v"(w[k]));
+    }
+};
+
 // One thread per Gaussian: recompute the projection of every view of its
 // scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
 // the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
@@ -376,6 +424,8 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
     GaussShape sh;
     gaussian_shape(gp, sh);
     const float opac = 1.0f / (1.0f + __expf(-gp.logit));
+    ShRegs<DT, SHD> shc;
+    shc.load(sd, g, gp, desc->vec_rows != 0);
 
     float dmu[3] = {0.f, 0.f, 0.f};
     float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
@@ -470,6 +520,7 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         dmu[2] += Wm[2] * gx + Wm[6] * gy + Wm[10] * gz;
         // colour: c = max(0, sum Y k + 1/2), Y of the unit direction camera -> mean
         {
+            shc.pin();
             float ex = gp.mean[0] - vd.campos[0], ey = gp.mean[1] - vd.campos[1], ez = gp.mean[2] - vd.campos[2];
             const float il = rsqrtf(ex * ex + ey * ey + ez * ez);
             const float x = ex * il, y = ey * il, z = ez * il;
@@ -480,7 +531,7 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
             for (int ch = 0; ch < 3; ++ch) {
                 float acc = 0.5f;
 #pragma unroll
-                for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], gp.sh[3 * j + ch], acc);
+                for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], shc[3 * j + ch], acc);
                 dcol[ch] = acc > 0.f ? d[6 + ch] : 0.f;
             }
 #pragma unroll
@@ -488,10 +539,11 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) dk[3 * j + ch] = fmaf(Y[j], dcol[ch], dk[3 * j + ch]);
             if constexpr (SHD >= 1) {
+                shc.pin();
                 float e[16];
 #pragma unroll
                 for (int j = 0; j < NCO; ++j)
-                    e[j] = dcol[0] * gp.sh[3 * j] + dcol[1] * gp.sh[3 * j + 1] + dcol[2] * gp.sh[3 * j + 2];
+                    e[j] = dcol[0] * shc[3 * j] + dcol[1] * shc[3 * j + 1] + dcol[2] * shc[3 * j + 2];
                 float qx = -kY1 * e[3], qy = -kY1 * e[1], qz = kY1 * e[2];
                 if constexpr (SHD >= 2) {
                     qx += kY2a * y * e[4] - kY2a * z * e[7] - 2.f * kY2b * x * e[6] + 2.f * kY2c * x * e[8];
@@ -518,6 +570,12 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
             }
         }
     }
+    // the shape again (bitwise the same) rather than R, M held across the loop
+#pragma unroll
+    for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(gp.ls[i]));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(gp.q[i]));
+    gaussian_shape(gp, sh);
     // Sigma = M M^T -> dM = (G + G^T) M ; M = R diag(s)
     float dR[3][3], ds[3] = {0.f, 0.f, 0.f};
 #pragma unroll
