@@ -216,13 +216,19 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 }
 
 // ------------------------------------------------------- record gradients
-// One thread per (view, Gaussian) record: dL/d(record) = the sum of the
-// record's tile slots, in row-major tile order (slots of consecutive records
-// are adjacent: coalesced reads), over the tiles whose backward walk reached
-// the record -- (depth key, record) ordered before the tile's cut.  Written
-// as 9 floats per record, only for records with a nonzero sum; a bit per
-// record (two words per wavefront, records of one view per wavefront) says
-// which, so records no walk reached cost neither a write nor a read.
+// dL/d(record) for every (view, Gaussian) record = the sum of the record's
+// tile slots, in row-major tile order, over the tiles whose backward walk
+// reached the record -- (depth key, record) ordered before the tile's cut.
+// Written as 9 floats per record, only for records with a nonzero sum; a bit
+// per record (two words per wavefront, records of one view per wavefront)
+// says which, so records no walk reached cost neither a write nor a read.
+//
+// Wave-cooperative: a wavefront owns 64 consecutive records, whose slots are
+// one contiguous range.  The lanes walk that range 64 slots at a time, one
+// slot each (its record by a search over the wave's slot offsets in LDS),
+// so a record covering many tiles does not hold up the other 63; then each
+// lane adds its own record's slots of the chunk from LDS in slot order --
+// the same order, and so the same bits, as a sequential sum per record.
 // Zeros read in place of a slot not reached (global, never written: a
 // selection between it and a slot stays in the global address space).
 __device__ float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -235,53 +241,76 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                                                   const uint2* __restrict__ tile_cut,
                                                   const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad,
                                                   uint32_t* __restrict__ rec_flag) {
+    __shared__ uint32_t s_start[4][64], s_so[4][64], s_key[4][64], s_org[4][64], s_w[4][64];
+    __shared__ float s_v[4][9][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_rec_waves) return;
     const ViewDesc& vd = desc->views[find_view_by_wave(desc, wv)];
-    const int64_t i = (wv - vd.rec_wave_off) * kWave + (threadIdx.x & 63);
-    if (i >= desc->scenes[vd.scene].n) return;
-    const int64_t r = vd.rec_off + i;
-    float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    // the record's four words are loaded together, before the first use
+    const int64_t i0 = (wv - vd.rec_wave_off) * kWave;
+    const int64_t i = i0 + lane;
+    const bool valid = i < desc->scenes[vd.scene].n;
+    // the record's four words are loaded together (lanes past the end read
+    // the wave's first record and own no slots)
+    const int64_t r = vd.rec_off + (valid ? i : i0);
     const uint2 tr = tile_rect[r];
     const uint32_t so = slot_off[r];
     const uint32_t key = depth_key[r];
-    const uint32_t nt = cnt->n_inst_ok != 0ull ? ntiles[r] : 0u;
-    if (nt != 0u) {
-        const float* gi = ginst + 9 * (int64_t)so;
-        const int rx0 = (int)(tr.x & 0xffffu), ry0 = (int)(tr.x >> 16), rw = (int)(tr.y & 0xffffu) - rx0;
-        const uint2* cut = tile_cut + vd.tile_off + (int64_t)ry0 * vd.tiles_x + rx0;
-        int ex = 0;
-        int64_t erow = 0;
-        // four slots at a time: their cuts, then their values, are loaded
-        // together (a slot not reached reads zeros from kZeroSlot)
-        for (uint32_t e0 = 0; e0 < nt; e0 += 4) {
-            uint2 c[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                c[j] = make_uint2(0u, 0u);
-                if (e0 + j < nt) {
-                    c[j] = cut[erow + ex];
-                    if (++ex == rw) { ex = 0; erow += vd.tiles_x; }
+    const uint32_t ntr = ntiles[r];
+    const uint32_t nt = valid && cnt->n_inst_ok != 0ull ? ntr : 0u;
+    const uint32_t incl = wave_incl_scan(nt, lane);
+    const uint32_t start = incl - nt;
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (total != 0u) {
+        s_start[w][lane] = start;
+        s_so[w][lane] = so;
+        s_key[w][lane] = key;
+        s_org[w][lane] = tr.x;                                   // rx0 | ry0 << 16
+        s_w[w][lane] = (tr.y & 0xffffu) - (tr.x & 0xffffu);      // rectangle width in tiles
+        wave_sync();
+        const uint2* cutv = tile_cut + vd.tile_off;
+        const uint32_t rec0 = (uint32_t)(vd.rec_off + i0);
+        const uint32_t my_end = start + nt;
+        for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+            const uint32_t k = c0 + (uint32_t)lane;
+            float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (k < total) {
+                // the last record of the wave whose slots start at or before k
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[w][mid] <= k) lo = mid; else hi = mid - 1;
                 }
+                const uint32_t e = k - s_start[w][lo];
+                const uint32_t wq = s_w[w][lo];
+                uint32_t row = (uint32_t)((float)e * __builtin_amdgcn_rcpf((float)wq));
+                while (row * wq > e) --row;
+                while ((row + 1) * wq <= e) ++row;
+                const uint32_t org = s_org[w][lo];
+                const uint2 ct = cutv[(int64_t)((org >> 16) + row) * vd.tiles_x + (org & 0xffffu) + (e - row * wq)];
+                const uint32_t kk = s_key[w][lo];
+                const bool reached = kk < ct.x || (kk == ct.x && rec0 + (uint32_t)lo < ct.y);
+                const float* src = reached ? ginst + 9 * ((int64_t)s_so[w][lo] + e) : kZeroSlot;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) v[q] = src[q];
             }
-            const float* src[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const bool reached = e0 + j < nt && (key < c[j].x || (key == c[j].x && (uint32_t)r < c[j].y));
-                src[j] = reached ? gi + 9 * (e0 + j) : kZeroSlot;
-            }
+            for (int q = 0; q < 9; ++q) s_v[w][q][lane] = v[q];
+            wave_sync();
+            const uint32_t a = start > c0 ? start : c0;
+            const uint32_t b = my_end < c0 + 64u ? my_end : c0 + 64u;
+            for (uint32_t j = a; j < b; ++j)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) d[i] += src[j][i];
+                for (int q = 0; q < 9; ++q) d[q] += s_v[w][q][j - c0];
+            wave_sync();
         }
     }
     bool nz = false;
 #pragma unroll
     for (int k = 0; k < 9; ++k) nz |= d[k] != 0.f;
     const uint64_t m = __ballot(nz);
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         rec_flag[2 * wv] = (uint32_t)m;
         rec_flag[2 * wv + 1] = (uint32_t)(m >> 32);
     }
