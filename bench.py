@@ -211,6 +211,37 @@ def stage_times(ev: HipEvents, steps):
     return out
 
 
+def step_distribution(ev: HipEvents, steps):
+    """Median and 10th / 90th percentiles of the per-step GPU time, from the
+    first to the last stage event of each timed step."""
+    t = np.array([ev.elapsed(k * cgs.STAGE_EVENTS, k * cgs.STAGE_EVENTS + cgs.STAGE_EVENTS - 1)
+                  for k in range(steps)])
+    return {"median": float(np.median(t)), "p10": float(np.percentile(t, 10)), "p90": float(np.percentile(t, 90)),
+            "of": "per-step GPU time, first to last stage event"}
+
+
+def host_cpu():
+    """The host CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cpus = sorted(os.sched_getaffinity(0))
+    runs, a = [], None
+    for i, c in enumerate(cpus):     # compact "0-15,32-47" form of the affinity mask
+        if a is None:
+            a = c
+        if i + 1 == len(cpus) or cpus[i + 1] != c + 1:
+            runs.append(f"{a}-{c}" if c > a else f"{a}")
+            a = None
+    return model, ",".join(runs), os.cpu_count()
+
+
 def walked_instances(r: render.Renderer) -> int:
     """Instances the blends must read: per tile, list positions up to the
     largest n_last of its pixels (front-to-back termination)."""
@@ -275,7 +306,9 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
         n = int(min(4096, max(2 * n, n * 0.9 * target_s / max(dt, 1e-3))))
         dt, npix, ntiles = run(n)
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    model, affinity, nproc = host_cpu()
     return {"value": npix / dt / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "cpu": model, "affinity": affinity, "nproc": nproc,
             "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
                       f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}
 
@@ -449,6 +482,7 @@ def main():
     log(f"[bench] timing {args.workload} batched: {args.steps} steps after {args.warmup} warmup")
     ms = head.time(args.steps, args.warmup, ev)
     stages = stage_times(ev, args.steps)
+    step_dist = step_distribution(ev, args.steps)
     value = wl.n_pixels / (ms * 1e-3) / 1e6
     e_eval, e_blend, walked = pair_counts(head)
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
@@ -539,6 +573,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "stages_ms": stages,
+        "step_ms_dist": step_dist,
         "hbm_roofline_step": {"algorithmic_bytes": sb["total"], "bytes_by_stage": sb,
                               "frac": sb["total"] / HBM_PEAK / (ms * 1e-3)},
         "extra": extra_info,
