@@ -30,7 +30,7 @@ def small_workload(kind: str) -> sc.Workload:
     if kind == "uniform4k_128px":
         return sc.make_workload("uniform4k_128px")
     rng = np.random.default_rng({"clusters20k_d3": 71, "clusters20k_d3_bf16": 72, "views3": 73,
-                                 "scenes3": 74, "ragged_d1": 75, "wide258": 76}[kind])
+                                 "scenes3": 74, "ragged_d1": 75, "wide258": 76, "degenerate": 77}[kind])
     if kind in ("clusters20k_d3", "clusters20k_d3_bf16"):
         bf = kind.endswith("bf16")
         s = sc.make_scene(rng, 20000, 512, 3, sc.screen_matched_mu(200), clusters=True, bf16=bf)
@@ -61,6 +61,24 @@ def small_workload(kind: str) -> sc.Workload:
         cams = [sc.pinhole(4120, 72, (0.0, 0.0, -3.0))]
         return sc.Workload(kind, [s], cams, np.array([0], np.int32),
                            [rng.uniform(0, 1, (72, 4120, 3)).astype(np.float32)], False)
+    if kind == "degenerate":
+        # Gaussians that cover the whole 20 x 15-tile frame (records with
+        # ~300 tile slots), large ones centred outside the clamped frustum
+        # (the Jacobian's clamp branches), and Gaussians behind the camera
+        # or far off screen (culled)
+        s = sc.make_scene(rng, 3000, 128, 3, sc.screen_matched_mu(320), clusters=True)
+        cb, means, idx = s.cb.copy(), s.means.copy(), s.idx.copy()
+        cb[0, 0:3] = np.log(0.8)        # row 0: 3 sigma ~ 220 px at depth 3
+        cb[0, 7] = -1.5                 # low opacity: the scene behind still blends
+        idx[:9] = 0
+        means[:6] = rng.uniform(-0.3, 0.3, (6, 3))
+        means[6:9] = np.array([[3.0, 0.2, 0.0], [-3.2, -0.1, 0.3], [0.1, 2.6, 0.0]])
+        means[9:59, 2] = -4.5           # behind the camera at z = -3
+        means[59:109, 0] = 40.0         # far to the side
+        s = sc.Scene(means, idx, cb, 3)
+        cams = [sc.pinhole(320, 240, (0.0, 0.0, -3.0))]
+        return sc.Workload(kind, [s], cams, np.array([0], np.int32),
+                           [rng.uniform(0, 1, (240, 320, 3)).astype(np.float32)], False)
     raise KeyError(kind)
 
 
@@ -71,7 +89,8 @@ def gpu_renderer(wl: sc.Workload, **kw) -> render.Renderer:
     return r
 
 
-SMALL = ["uniform4k_128px", "clusters20k_d3", "clusters20k_d3_bf16", "views3", "scenes3", "ragged_d1", "wide258"]
+SMALL = ["uniform4k_128px", "clusters20k_d3", "clusters20k_d3_bf16", "views3", "scenes3", "ragged_d1", "wide258",
+         "degenerate"]
 
 
 @pytest.mark.parametrize("kind", SMALL)
