@@ -291,24 +291,26 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
         pix = np.concatenate(pix).astype(np.int32)
         t0 = time.perf_counter()
         o = oracle.render_view(s, cam, pix)
+        t_fwd = time.perf_counter() - t0
         tgt = wl.targets[0][pix[:, 1], pix[:, 0]].astype(np.float64)
         g = np.sign(o["color"] - tgt) / (3.0 * P)
         o2 = oracle.render_view(s, cam, pix, grad_color=g)
         oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
-        return time.perf_counter() - t0, pix.shape[0], ntiles
+        return time.perf_counter() - t0, pix.shape[0], ntiles, t_fwd
 
     # each call projects the whole scene once (a fixed cost) and then
     # composites its tiles; grow the tile count until one call takes about
     # target_s, so the fixed cost is spread as it would be over a larger sample
-    n = 2
-    dt, npix, ntiles = run(n)
-    while dt < 0.8 * target_s and n < 4096:
-        n = int(min(4096, max(2 * n, n * 0.9 * target_s / max(dt, 1e-3))))
-        dt, npix, ntiles = run(n)
+    n_max = min(4096, tx * ty)
+    n = min(2, n_max)
+    dt, npix, ntiles, dt_fwd = run(n)
+    while dt < 0.8 * target_s and n < n_max:
+        n = int(min(n_max, max(2 * n, n * 0.9 * target_s / max(dt, 1e-3))))
+        dt, npix, ntiles, dt_fwd = run(n)
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     model, affinity, nproc = host_cpu()
     return {"value": npix / dt / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-            "cpu": model, "affinity": affinity, "nproc": nproc,
+            "cpu": model, "affinity": affinity, "nproc": nproc, "forward_value": npix / dt_fwd / 1e6,
             "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
                       f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}
 
