@@ -14,7 +14,9 @@
 //   dS/dmxx = -S / B2,   dS/dmxy = 2 A1 / (B1 B2)   (mxx = w*(x x), mxy = w*(x y)),
 // and the window is symmetric, so
 //   d(sum_q S(q))/dx(p) = w*(dS/dmx)(p) + 2 x(p) w*(dS/dmxx)(p) + y(p) w*(dS/dmxy)(p)
-// with the partial maps taken as zero outside the image.
+// with the partial maps taken as zero outside the image.  Only sxx + syy
+// enters S, so the statistics pass blurs x^2 + y^2 as one map (four window
+// sums per channel: x, y, x^2 + y^2, x y); its partial is dS/dmxx above.
 //
 // Two tiled passes per 16x16 pixel tile (256 threads, one pixel each): the
 // statistics pass stages the tile plus a 5-pixel halo of image and target in
@@ -55,8 +57,8 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
                                                     const float* __restrict__ target, float* __restrict__ part,
                                                     double* __restrict__ sums) {
     __shared__ float s_xy[2][3][kSpan][kSpan];     // image, target (tile + halo); then the column sums
-    __shared__ float s_h[15][kSpan][kTile];
-    __shared__ double s_red[2][256];
+    __shared__ float s_h[12][kSpan][kTile];
+    __shared__ double s_red[2][4];
     auto s_x = s_xy[0];
     auto s_y = s_xy[1];
     const int64_t t = blockIdx.x;
@@ -78,8 +80,9 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
         }
     }
     __syncthreads();
-    // rows: five window sums per (row, output column, channel); a thread
-    // takes eight outputs of one row and slides the window in registers
+    // rows: four window sums per (row, output column, channel) -- x, y,
+    // x^2 + y^2 (only sxx + syy enters S) and x y; a thread takes eight
+    // outputs of one row and slides the window in registers
     if (threadIdx.x < kSpan * 3 * 2) {
         const int r = threadIdx.x / 6, ch = (threadIdx.x / 2) % 3, c0 = 8 * (threadIdx.x & 1);
         float a[18], b[18];
@@ -87,21 +90,19 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
         for (int k = 0; k < 18; ++k) { a[k] = s_x[ch][r][c0 + k]; b[k] = s_y[ch][r][c0 + k]; }
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
-            float hx = 0.f, hy = 0.f, hxx = 0.f, hyy = 0.f, hxy = 0.f;
+            float hx = 0.f, hy = 0.f, hs = 0.f, hxy = 0.f;
 #pragma unroll
             for (int k = 0; k < 11; ++k) {
                 const float aa = a[o + k], bb = b[o + k], w = kWin[k];
                 hx = fmaf(w, aa, hx);
                 hy = fmaf(w, bb, hy);
-                hxx = fmaf(w, aa * aa, hxx);
-                hyy = fmaf(w, bb * bb, hyy);
+                hs = fmaf(w, fmaf(aa, aa, bb * bb), hs);
                 hxy = fmaf(w, aa * bb, hxy);
             }
-            s_h[5 * ch + 0][r][c0 + o] = hx;
-            s_h[5 * ch + 1][r][c0 + o] = hy;
-            s_h[5 * ch + 2][r][c0 + o] = hxx;
-            s_h[5 * ch + 3][r][c0 + o] = hyy;
-            s_h[5 * ch + 4][r][c0 + o] = hxy;
+            s_h[4 * ch + 0][r][c0 + o] = hx;
+            s_h[4 * ch + 1][r][c0 + o] = hy;
+            s_h[4 * ch + 2][r][c0 + o] = hs;
+            s_h[4 * ch + 3][r][c0 + o] = hxy;
         }
     }
     __syncthreads();
@@ -112,8 +113,8 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
     for (int ch = 0; ch < 3; ++ch) { cx[ch] = s_x[ch][ty + kHalo][tx + kHalo]; cy[ch] = s_y[ch][ty + kHalo][tx + kHalo]; }
     __syncthreads();
     // columns: a thread takes one (quantity, column) and slides down it
-    float* s_m = &s_xy[0][0][0][0];     // [15][kTile][kTile]
-    if (threadIdx.x < 15 * kTile) {
+    float* s_m = &s_xy[0][0][0][0];     // [12][kTile][kTile]
+    if (threadIdx.x < 12 * kTile) {
         const int l = threadIdx.x / kTile, c = threadIdx.x % kTile;
         float col[kSpan];
 #pragma unroll
@@ -133,14 +134,14 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
         float* out = part + 9 * p;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            float m[5];
+            float m[4];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) m[q] = s_m[((5 * ch + q) * kTile + ty) * kTile + tx];
+            for (int q = 0; q < 4; ++q) m[q] = s_m[((4 * ch + q) * kTile + ty) * kTile + tx];
             const float mx = m[0], my = m[1];
             const float A1 = 2.f * mx * my + kC1;
-            const float A2 = 2.f * (m[4] - mx * my) + kC2;
+            const float A2 = 2.f * (m[3] - mx * my) + kC2;
             const float B1 = mx * mx + my * my + kC1;
-            const float B2 = (m[2] - mx * mx) + (m[3] - my * my) + kC2;
+            const float B2 = ((m[2] - mx * mx) - my * my) + kC2;
             const float inv = 1.f / (B1 * B2);
             const float S = A1 * A2 * inv;
             out[3 * ch + 0] = 2.f * inv * (my * (A2 - A1) - mx * S * (B2 - B1));
@@ -150,19 +151,19 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
             l1 += (double)fabsf(cx[ch] - cy[ch]);
         }
     }
-    s_red[0][threadIdx.x] = l1;
-    s_red[1][threadIdx.x] = ss;
-    __syncthreads();
-    for (int d = 128; d > 0; d >>= 1) {
-        if ((int)threadIdx.x < d) {
-            s_red[0][threadIdx.x] += s_red[0][threadIdx.x + d];
-            s_red[1][threadIdx.x] += s_red[1][threadIdx.x + d];
-        }
-        __syncthreads();
+    // tile sums: butterfly over each wave, then the four waves in order
+    for (int d = 32; d >= 1; d >>= 1) {
+        l1 += __shfl_xor(l1, d, 64);
+        ss += __shfl_xor(ss, d, 64);
     }
+    if ((threadIdx.x & 63) == 0) {
+        s_red[0][threadIdx.x >> 6] = l1;
+        s_red[1][threadIdx.x >> 6] = ss;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        sums[2 * t] = s_red[0][0];
-        sums[2 * t + 1] = s_red[1][0];
+        sums[2 * t] = (s_red[0][0] + s_red[0][1]) + (s_red[0][2] + s_red[0][3]);
+        sums[2 * t + 1] = (s_red[1][0] + s_red[1][1]) + (s_red[1][2] + s_red[1][3]);
     }
 }
 
