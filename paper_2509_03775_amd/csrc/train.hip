@@ -19,9 +19,10 @@
 // sums per channel: x, y, x^2 + y^2, x y); its partial is dS/dmxx above.
 //
 // Two tiled passes per 16x16 pixel tile (256 threads, one pixel each): the
-// statistics pass stages the tile plus a 5-pixel halo of image and target in
-// LDS, blurs rows then columns (each blur thread slides its 11-tap window
-// along one line in registers, the taps added in the same order for every
+// statistics pass blurs the tile plus a 5-pixel halo of image and target,
+// rows then columns (each blur thread loads its line -- a row straight from
+// memory, a column from the row sums in LDS -- and slides its 11-tap window
+// along it in registers, the taps added in the same order for every
 // output), and writes the three partials per channel
 // and the tile's L1 and SSIM sums; the gradient pass blurs the partial maps
 // the same way and combines them with the image, the target and the L1 term.
@@ -56,11 +57,9 @@ __device__ inline int loss_view_of(const LossViews& v, int64_t t) {
 __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* __restrict__ image,
                                                     const float* __restrict__ target, float* __restrict__ part,
                                                     double* __restrict__ sums) {
-    __shared__ float s_xy[2][3][kSpan][kSpan];     // image, target (tile + halo); then the column sums
     __shared__ float s_h[12][kSpan][kTile];
+    __shared__ float s_m[12][kTile][kTile];
     __shared__ double s_red[2][4];
-    auto s_x = s_xy[0];
-    auto s_y = s_xy[1];
     const int64_t t = blockIdx.x;
     const int v = loss_view_of(lv, t);
     const int H = lv.H[v], W = lv.W[v];
@@ -68,26 +67,24 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
     const int x0 = (int)(lt % lv.tiles_x[v]) * kTile, y0 = (int)(lt / lv.tiles_x[v]) * kTile;
     const float* img = image + 3 * lv.pix_off[v];
     const float* tgt = target + 3 * lv.pix_off[v];
-    for (int i = threadIdx.x; i < kSpan * kSpan; i += 256) {
-        const int r = i / kSpan, c = i % kSpan;
-        const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        const int64_t p = (int64_t)gy * W + gx;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            s_x[ch][r][c] = in ? img[3 * p + ch] : 0.f;
-            s_y[ch][r][c] = in ? tgt[3 * p + ch] : 0.f;
-        }
-    }
-    __syncthreads();
     // rows: four window sums per (row, output column, channel) -- x, y,
     // x^2 + y^2 (only sxx + syy enters S) and x y; a thread takes eight
-    // outputs of one row and slides the window in registers
+    // outputs of one row, loads its 18 values of image and target straight
+    // from memory (all in flight at once, no staging buffer) and slides the
+    // window in registers
     if (threadIdx.x < kSpan * 3 * 2) {
         const int r = threadIdx.x / 6, ch = (threadIdx.x / 2) % 3, c0 = 8 * (threadIdx.x & 1);
+        const int gy = y0 - kHalo + r;
+        const bool rin = gy >= 0 && gy < H;
+        const int64_t ro = 3 * (int64_t)(rin ? gy : 0) * W + ch;
         float a[18], b[18];
 #pragma unroll
-        for (int k = 0; k < 18; ++k) { a[k] = s_x[ch][r][c0 + k]; b[k] = s_y[ch][r][c0 + k]; }
+        for (int k = 0; k < 18; ++k) {
+            const int gx = x0 - kHalo + c0 + k;
+            const bool in = rin && gx >= 0 && gx < W;
+            a[k] = in ? img[ro + 3 * gx] : 0.f;
+            b[k] = in ? tgt[ro + 3 * gx] : 0.f;
+        }
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             float hx = 0.f, hy = 0.f, hs = 0.f, hxy = 0.f;
@@ -108,12 +105,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
     __syncthreads();
     const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
     const int gx = x0 + tx, gy = y0 + ty;
-    float cx[3], cy[3];     // this pixel's image and target values (the staging buffer is reused below)
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) { cx[ch] = s_x[ch][ty + kHalo][tx + kHalo]; cy[ch] = s_y[ch][ty + kHalo][tx + kHalo]; }
-    __syncthreads();
     // columns: a thread takes one (quantity, column) and slides down it
-    float* s_m = &s_xy[0][0][0][0];     // [12][kTile][kTile]
     if (threadIdx.x < 12 * kTile) {
         const int l = threadIdx.x / kTile, c = threadIdx.x % kTile;
         float col[kSpan];
@@ -124,7 +116,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
             float a = 0.f;
 #pragma unroll
             for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], col[o + k], a);
-            s_m[(l * kTile + o) * kTile + c] = a;
+            s_m[l][o][c] = a;
         }
     }
     __syncthreads();
@@ -132,11 +124,14 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
     if (gx < W && gy < H) {
         const int64_t p = lv.pix_off[v] + (int64_t)gy * W + gx;
         float* out = part + 9 * p;
+        float cx[3], cy[3];     // this pixel's image and target values, for the L1 term
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) { cx[ch] = image[3 * p + ch]; cy[ch] = target[3 * p + ch]; }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float m[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) m[q] = s_m[((4 * ch + q) * kTile + ty) * kTile + tx];
+            for (int q = 0; q < 4; ++q) m[q] = s_m[4 * ch + q][ty][tx];
             const float mx = m[0], my = m[1];
             const float A1 = 2.f * mx * my + kC1;
             const float A2 = 2.f * (m[3] - mx * my) + kC2;
@@ -170,29 +165,28 @@ __global__ __launch_bounds__(256) void k_ssim_stats(LossViews lv, const float* _
 __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __restrict__ image,
                                                    const float* __restrict__ target, const float* __restrict__ part,
                                                    float l1w, float ssw, float* __restrict__ grad) {
-    __shared__ float s_p[9][kSpan][kSpan];
     __shared__ float s_h[9][kSpan][kTile];
+    __shared__ float s_m[9][kTile][kTile];
     const int64_t t = blockIdx.x;
     const int v = loss_view_of(lv, t);
     const int H = lv.H[v], W = lv.W[v];
     const int64_t lt = t - lv.tile_off[v];
     const int x0 = (int)(lt % lv.tiles_x[v]) * kTile, y0 = (int)(lt / lv.tiles_x[v]) * kTile;
     const float* pp = part + 9 * lv.pix_off[v];
-    for (int i = threadIdx.x; i < kSpan * kSpan; i += 256) {
-        const int r = i / kSpan, c = i % kSpan;
-        const int gy = y0 - kHalo + r, gx = x0 - kHalo + c;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        const int64_t p = (int64_t)gy * W + gx;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) s_p[q][r][c] = in ? pp[9 * p + q] : 0.f;
-    }
-    __syncthreads();
-    // rows, then columns, each thread sliding an 11-tap window along one line
+    // rows, then columns, each thread sliding an 11-tap window along one
+    // line; a row thread loads its 26 values straight from the partial maps
+    // (all loads in flight at once, no staging buffer)
     if (threadIdx.x < kSpan * 9) {
         const int r = threadIdx.x / 9, q = threadIdx.x % 9;
+        const int gy = y0 - kHalo + r;
+        const bool rin = gy >= 0 && gy < H;
+        const float* src = pp + 9 * ((int64_t)(rin ? gy : 0) * W) + q;
         float row[kSpan];
 #pragma unroll
-        for (int k = 0; k < kSpan; ++k) row[k] = s_p[q][r][k];
+        for (int k = 0; k < kSpan; ++k) {
+            const int gx = x0 - kHalo + k;
+            row[k] = rin && gx >= 0 && gx < W ? src[9 * gx] : 0.f;
+        }
 #pragma unroll
         for (int o = 0; o < kTile; ++o) {
             float a = 0.f;
@@ -202,7 +196,6 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __
         }
     }
     __syncthreads();
-    float* s_m = &s_p[0][0][0];     // [9][kTile][kTile], the partials are no longer needed
     if (threadIdx.x < 9 * kTile) {
         const int q = threadIdx.x / kTile, c = threadIdx.x % kTile;
         float col[kSpan];
@@ -213,7 +206,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __
             float a = 0.f;
 #pragma unroll
             for (int k = 0; k < 11; ++k) a = fmaf(kWin[k], col[o + k], a);
-            s_m[(q * kTile + o) * kTile + c] = a;
+            s_m[q][o][c] = a;
         }
     }
     __syncthreads();
@@ -225,7 +218,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(LossViews lv, const float* __
     for (int ch = 0; ch < 3; ++ch) {
         float b[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) b[q] = s_m[((3 * ch + q) * kTile + ty) * kTile + tx];
+        for (int q = 0; q < 3; ++q) b[q] = s_m[3 * ch + q][ty][tx];
         const float x = image[3 * p + ch], y = target[3 * p + ch];
         const float d = x - y;
         const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
