@@ -74,10 +74,34 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
 }
 
 // ------------------------------------------------------------------ emission
+// Inclusive max over lanes 0..l of the wave (values >= 0, every lane active):
+// prefixes within each 16-lane row by DPP row shifts, then the totals of the
+// rows before it, read from lanes 15, 31 and 47.
+__device__ inline uint32_t wave_incl_max_u32(uint32_t v, int lane) {
+    uint32_t t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v = v > t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v = v > t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v = v > t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v = v > t ? v : t;
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    const uint32_t m01 = r0 > r1 ? r0 : r1, m012 = m01 > r2 ? m01 : r2;
+    const int row = lane >> 4;
+    const uint32_t pre = row == 0 ? 0u : (row == 1 ? r0 : (row == 2 ? m01 : m012));
+    return v > pre ? v : pre;
+}
+
 // Wave-cooperative emission: a wavefront owns 64 consecutive records of the
 // depth order; their instances occupy one contiguous range of the instance
-// array, which the 64 lanes write in order (each lane finds the record of an
-// instance by a binary search over the wave's offsets in LDS), so writes are
+// array, which the 64 lanes write in order, 64 instances at a time (each
+// record with tiles marks the lane of its first instance in the chunk, and
+// an inclusive max-scan of the marks over the wave gives every instance its
+// record, carried into the next chunk), so writes are
 // coalesced and a record with many tiles does not stall its wave.  Instance
 // (record, tile) keys are the view's tile offset + the row-major tile index;
 // tiles of a record follow row-major order.
@@ -85,7 +109,7 @@ __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc
                                               const uint32_t* __restrict__ offs, const uint2* __restrict__ rect_d,
                                               const uint32_t* __restrict__ cnt_d, const DevCounters* __restrict__ cnt,
                                               uint32_t* __restrict__ inst_key, uint32_t* __restrict__ inst_val) {
-    __shared__ uint32_t s_rel[4][64], s_w[4][64], s_base[4][64], s_tx[4][64], s_r[4][64];
+    __shared__ uint32_t s_rel[4][64], s_w[4][64], s_base[4][64], s_tx[4][64], s_r[4][64], s_mark[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * 64;
     if (j0 >= desc->n_rec) return;
@@ -120,20 +144,28 @@ __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc
     }
     s_rel[w][lane] = valid ? rel : endrel;
     wave_sync();
-    for (uint32_t i = (uint32_t)lane; i < endrel; i += 64) {
-        // last record of the wave whose range starts at or before i
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_rel[w][mid] <= i) lo = mid; else hi = mid - 1;
+    uint32_t carry = 0u;     // 1 + the lane of the record owning the last instance of the previous chunk
+    for (uint32_t c0 = 0; c0 < endrel; c0 += 64) {
+        s_mark[w][lane] = 0u;
+        wave_sync();
+        if (valid && c > 0 && rel >= c0 && rel < c0 + 64u) s_mark[w][rel - c0] = (uint32_t)lane + 1u;
+        wave_sync();
+        // the last record of the wave whose range starts at or before i
+        uint32_t m = wave_incl_max_u32(s_mark[w][lane], lane);
+        m = m > carry ? m : carry;
+        carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+        const uint32_t i = c0 + (uint32_t)lane;
+        if (i < endrel) {
+            const int lo = (int)m - 1;
+            const uint32_t local = i - s_rel[w][lo];
+            const uint32_t wq = s_w[w][lo];
+            uint32_t row = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wq));
+            if (row * wq > local) --row;
+            if ((row + 1) * wq <= local) ++row;
+            inst_key[o0 + i] = s_base[w][lo] + row * s_tx[w][lo] + (local - row * wq);
+            inst_val[o0 + i] = s_r[w][lo];
         }
-        const uint32_t local = i - s_rel[w][lo];
-        const uint32_t wq = s_w[w][lo];
-        uint32_t row = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wq));
-        if (row * wq > local) --row;
-        if ((row + 1) * wq <= local) ++row;
-        inst_key[o0 + i] = s_base[w][lo] + row * s_tx[w][lo] + (local - row * wq);
-        inst_val[o0 + i] = s_r[w][lo];
+        wave_sync();
     }
 }
 
