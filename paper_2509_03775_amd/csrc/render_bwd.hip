@@ -5,6 +5,7 @@
 #include "cgs_internal.h"
 #include "philox.h"
 #include "render_common.h"
+#include "wave_scan.h"
 
 namespace cgs {
 
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 //
 // Wave-cooperative: a wavefront owns 64 consecutive records, whose slots are
 // one contiguous range.  The lanes walk that range 64 slots at a time, one
-// slot each (its record by a search over the wave's slot offsets in LDS),
+// slot each (its record by a max-scan of per-record start marks),
 // so a record covering many tiles does not hold up the other 63; then each
 // lane adds its own record's slots of the chunk from LDS in slot order --
 // the same order, and so the same bits, as a sequential sum per record.
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                                                   const uint2* __restrict__ tile_cut,
                                                   const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad,
                                                   uint32_t* __restrict__ rec_flag) {
-    __shared__ uint32_t s_start[4][64], s_so[4][64], s_key[4][64], s_org[4][64], s_w[4][64];
+    __shared__ uint32_t s_start[4][64], s_so[4][64], s_key[4][64], s_org[4][64], s_w[4][64], s_mark[4][64];
     __shared__ float s_v[4][9][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t wv = wave_id(4);
@@ -272,16 +273,22 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
         const uint2* cutv = tile_cut + vd.tile_off;
         const uint32_t rec0 = (uint32_t)(vd.rec_off + i0);
         const uint32_t my_end = start + nt;
+        uint32_t carry = 0u;     // 1 + the lane of the record owning the last slot of the previous chunk
         for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+            // each record with slots marks the lane of its first slot in the
+            // chunk; a max-scan of the marks gives every slot its record
+            s_mark[w][lane] = 0u;
+            wave_sync();
+            if (nt > 0u && start >= c0 && start < c0 + 64u) s_mark[w][start - c0] = (uint32_t)lane + 1u;
+            wave_sync();
+            uint32_t mk = wave_incl_max_u32(s_mark[w][lane], lane);
+            mk = mk > carry ? mk : carry;
+            carry = (uint32_t)__builtin_amdgcn_readlane((int)mk, 63);
             const uint32_t k = c0 + (uint32_t)lane;
             float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             if (k < total) {
                 // the last record of the wave whose slots start at or before k
-                int lo = 0, hi = 63;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_start[w][mid] <= k) lo = mid; else hi = mid - 1;
-                }
+                const int lo = (int)mk - 1;
                 const uint32_t e = k - s_start[w][lo];
                 const uint32_t wq = s_w[w][lo];
                 uint32_t row = (uint32_t)((float)e * __builtin_amdgcn_rcpf((float)wq));

@@ -4,6 +4,7 @@
 // and the front-to-back blend (paper Sec. 2.1, Eq. 1-3).
 #include "cgs_internal.h"
 #include "render_common.h"
+#include "wave_scan.h"
 
 namespace cgs {
 
@@ -74,28 +75,6 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
 }
 
 // ------------------------------------------------------------------ emission
-// Inclusive max over lanes 0..l of the wave (values >= 0, every lane active):
-// prefixes within each 16-lane row by DPP row shifts, then the totals of the
-// rows before it, read from lanes 15, 31 and 47.
-__device__ inline uint32_t wave_incl_max_u32(uint32_t v, int lane) {
-    uint32_t t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
-    v = v > t ? v : t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
-    v = v > t ? v : t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
-    v = v > t ? v : t;
-    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
-    v = v > t ? v : t;
-    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
-    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
-    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
-    const uint32_t m01 = r0 > r1 ? r0 : r1, m012 = m01 > r2 ? m01 : r2;
-    const int row = lane >> 4;
-    const uint32_t pre = row == 0 ? 0u : (row == 1 ? r0 : (row == 2 ? m01 : m012));
-    return v > pre ? v : pre;
-}
-
 // Wave-cooperative emission: a wavefront owns 64 consecutive records of the
 // depth order; their instances occupy one contiguous range of the instance
 // array, which the 64 lanes write in order, 64 instances at a time (each
