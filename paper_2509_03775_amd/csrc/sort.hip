@@ -505,19 +505,18 @@ uint32_t sort_stalls() {
 // ranges[t] = [lower_bound(t), lower_bound(t+1)) over the sorted tile keys.
 __global__ void k_tile_ranges(const uint32_t* sorted, const unsigned long long* n_dev, int64_t n_max,
                               int64_t n_tiles, uint32_t* ranges) {
+    // thread t finds lower_bound(t), the start of tile t and the end of
+    // tile t - 1 (thread n_tiles finds the end of the last tile)
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
+    if (t > n_tiles) return;
     const int64_t n = live_count(n_max, n_dev);
-    auto lower = [&](uint64_t key) {
-        int64_t lo = 0, hi = n;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if ((uint64_t)sorted[mid] < key) lo = mid + 1; else hi = mid;
-        }
-        return lo;
-    };
-    ranges[2 * t] = (uint32_t)lower((uint64_t)t);
-    ranges[2 * t + 1] = (uint32_t)lower((uint64_t)t + 1);
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)sorted[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    if (t < n_tiles) ranges[2 * t] = (uint32_t)lo;
+    if (t > 0) ranges[2 * (t - 1) + 1] = (uint32_t)lo;
 }
 
 // Sort key of each tile for the heavy-first order: 0xffff - min(length, 0xffff).
@@ -538,7 +537,7 @@ hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key,
 hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                        int64_t n_tiles, uint32_t* ranges, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, st,
                        sorted_tile, n_dev, n_max, n_tiles, ranges);
     return hipGetLastError();
 }
