@@ -69,6 +69,9 @@ int bits_for(int64_t n) {   // bits needed for values in [0, n)
 
 int passes_for(int nbits) { return (nbits + kRadixBits - 1) / kRadixBits; }
 
+// Bits of the heavy-first tile sort key (k_tile_len_keys writes 255 - q(length)).
+constexpr int kTileLenKeyBits = 8;
+
 template <typename T>
 T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
 
@@ -219,7 +222,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     h->n_blend = sch ? sch->n_blend : nullptr;
     h->tile_bits = bits_for(d.n_tiles);
     h->inst_buf = (passes_for(h->tile_bits) - 1) & 1;
-    h->tperm_buf = (passes_for(16) - 1) & 1;
+    h->tperm_buf = (passes_for(kTileLenKeyBits) - 1) & 1;
     h->dsort_buf = (passes_for(31) - 1) & 1;
 
     // workspace plan
@@ -435,7 +438,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
         uint32_t* tk[2] = {at<uint32_t>(ws, p.tperm_key[0]), at<uint32_t>(ws, p.tperm_key[1])};
         uint32_t* tv[2] = {at<uint32_t>(ws, p.tperm_val[0]), at<uint32_t>(ws, p.tperm_val[1])};
         CGS_TRY(tile_len_keys(at<uint32_t>(ws, p.tile_range), h.d.n_tiles, tk[1], st));
-        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, 16, sws, st, &e);
+        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, kTileLenKeyBits, sws, st, &e);
         CGS_TRY(e);
         if (tb != h.tperm_buf) return CGS_EHIP;
     }

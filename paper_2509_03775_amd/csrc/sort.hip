@@ -519,12 +519,21 @@ __global__ void k_tile_ranges(const uint32_t* sorted, const unsigned long long* 
     if (t > 0) ranges[2 * (t - 1) + 1] = (uint32_t)lo;
 }
 
-// Sort key of each tile for the heavy-first order: 0xffff - min(length, 0xffff).
+// 8-bit sort key of each tile for the heavy-first order: 255 - q(length),
+// q exact below 128 and log-scaled above (16 steps per doubling, 255 from
+// 2^15 on), non-decreasing in the length, so one stable 8-bit pass orders
+// the tiles longest first (ties and lengths sharing a step by tile index).
 __global__ void k_tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
     const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    key[t] = 0xffffu - (len < 0xffffu ? len : 0xffffu);
+    uint32_t q = len;
+    if (len >= 128u) {
+        const int b = 32 - __clz((int)len);      // bit length, 8..32
+        q = 128u + 16u * (uint32_t)(b - 8) + ((len >> (b - 5)) & 15u);
+        if (q > 255u) q = 255u;
+    }
+    key[t] = 255u - q;
 }
 
 hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key, hipStream_t st) {
