@@ -11,8 +11,8 @@ BF16-codebook workload with its four 1957x1091 views in one batched call;
 the plain-FP32 form (FP32 codebook, one call per view) and the 1M-Gaussian
 workload are reported beside it in "forms".
 
-Prints ONE JSON line.  --gpus N with N > 1 is refused: this build measures a
-single GPU.
+Prints ONE JSON line.  --gpus N with N > 1 is refused: the benchmark
+measures a single GPU.
 """
 import argparse
 import ctypes
@@ -453,8 +453,8 @@ def main():
                          "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the path shards by view; see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the library runs on one GPU; multi-GPU use would shard the views)", file=sys.stderr)
         sys.exit(2)
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cgs.load()

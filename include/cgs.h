@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
     CGS_OK = 0,
     CGS_EINVAL = -1,        /* bad argument (null pointer, negative size, bad stride, ...) */
-    CGS_EUNSUPPORTED = -2,  /* valid but not supported by this build (e.g. sh_degree > 3) */
+    CGS_EUNSUPPORTED = -2,  /* valid but not supported by the library (e.g. sh_degree > 3) */
     CGS_ECAPACITY = -3,     /* instance capacity too small (device-side, via d_info) */
     CGS_EHIP = -4,          /* a HIP launch failed */
     CGS_EWORKSPACE = -5     /* workspace too small */
