@@ -311,8 +311,29 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
     model, affinity, nproc = host_cpu()
     return {"value": npix / dt / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "cpu": model, "affinity": affinity, "nproc": nproc, "forward_value": npix / dt_fwd / 1e6,
+            "full_frame": [cpu_full_frame("uniform4k_128px")],
             "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
                       f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}
+
+
+def cpu_full_frame(name: str):
+    """The FP64 oracle on every pixel of a small workload's first view:
+    forward alone, then forward, L1 gradient, backward and codebook
+    reduction."""
+    import oracle
+    wl = sc.make_workload(name)
+    s, cam = wl.scenes[int(wl.view_scene[0])], wl.cameras[0]
+    P = cam.width * cam.height
+    t0 = time.perf_counter()
+    o = oracle.render_view(s, cam)
+    t_fwd = time.perf_counter() - t0
+    tgt = wl.targets[0].reshape(-1, 3).astype(np.float64)
+    g = np.sign(o["color"] - tgt) / (3.0 * P)
+    o2 = oracle.render_view(s, cam, grad_color=g)
+    oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
+    t_all = time.perf_counter() - t0
+    return {"workload": name, "pixels": P, "forward": P / t_fwd / 1e6, "forward_backward": P / t_all / 1e6,
+            "unit": "Mpixel/s"}
 
 
 def blend_roofline(stage, ms, e_eval, e_blend, workload, schedule):
