@@ -540,3 +540,194 @@ def test_l1_loss_matches_torch():
     lt.backward()
     assert L == pytest.approx(lt.item(), rel=1e-14)
     np.testing.assert_allclose(g, ti.grad.numpy(), rtol=1e-14)
+
+
+# ------------------------------------ P-11 skeleton vs the FP64 projection
+def _cam_points_to_world(cam, pc):
+    """World points whose camera-space coordinates are pc (x right, y down,
+    z forward) for the camera cam (inverse of x_c = R x + t)."""
+    Rt = np.asarray(cam.Rt, np.float64)
+    return (pc - Rt[:, 3]) @ Rt[:, :3]
+
+
+def _anisotropic_population(seed, n, cam, n_clamped):
+    """Random anisotropic, rotated Gaussians seen by cam: most with camera
+    points inside the frustum, n_clamped large ones whose x/z or y/z lies
+    beyond 1.3 tan(half field of view) (the Jacobian's clamp) while their
+    3-sigma box still reaches the image, and a few behind the near plane."""
+    rng = np.random.default_rng(seed)
+    lim_x = 1.3 * (0.5 * cam.width / float(cam.fx))
+    lim_y = 1.3 * (0.5 * cam.height / float(cam.fy))
+    n_in = n - n_clamped
+    z = rng.uniform(0.1, 6.0, n)
+    tx = np.concatenate([rng.uniform(-0.9 * lim_x, 0.9 * lim_x, n_in), np.zeros(n_clamped)])
+    ty = np.concatenate([rng.uniform(-0.9 * lim_y, 0.9 * lim_y, n_in), np.zeros(n_clamped)])
+    side = rng.integers(0, 4, n_clamped)       # which frustum side each clamped one lies beyond
+    out = rng.uniform(1.02, 1.6, n_clamped)
+    cx_ = np.where(side == 0, out * lim_x, np.where(side == 1, -out * lim_x, rng.uniform(-lim_x, lim_x, n_clamped)))
+    cy_ = np.where(side == 2, out * lim_y, np.where(side == 3, -out * lim_y, rng.uniform(-lim_y, lim_y, n_clamped)))
+    tx[n_in:], ty[n_in:] = cx_, cy_
+    z[n_in:] = rng.uniform(1.5, 4.0, n_clamped)
+    pc = np.stack([tx * z, ty * z, z], 1)
+    means = _cam_points_to_world(cam, pc).astype(np.float32)
+    rows = np.zeros((n, 7), np.float64)
+    rows[:n_in, 0:3] = rng.normal(-3.5, 0.9, (n_in, 3))        # axis ratios up to ~100
+    rows[n_in:, 0:3] = rng.normal(-0.7, 0.4, (n_clamped, 3))
+    rows[:, 3:7] = rng.standard_normal((n, 4))
+    return means, rows.astype(np.float32)
+
+
+def _fp64_tile_rect(u, v, a, c, W, H):
+    ex, ey = 3.0 * np.sqrt(a), 3.0 * np.sqrt(c)
+    bounds = np.stack([u - ex, u + ex, v - ey, v + ey], 1)
+    xlo = np.maximum(np.ceil(u - ex), 0.0)
+    xhi = np.minimum(np.floor(u + ex), W - 1.0)
+    ylo = np.maximum(np.ceil(v - ey), 0.0)
+    yhi = np.minimum(np.floor(v + ey), H - 1.0)
+    kept = (xlo <= xhi) & (ylo <= yhi)
+    rect = np.stack([xlo.astype(np.int64) >> 4, ylo.astype(np.int64) >> 4,
+                     (xhi.astype(np.int64) >> 4) + 1, (yhi.astype(np.int64) >> 4) + 1], 1)
+    return kept, rect, bounds
+
+
+def test_skeleton_matches_fp64_projection_anisotropic():
+    """The FP32 skeleton's culling, depth key and tile rectangle equal the ones
+    derived from the FP64 projection (oracle.project, itself pinned to scipy
+    rotations and the numerical Jacobian of the pinhole map) for 2000 rotated,
+    anisotropic Gaussians, 300 of them beyond the Jacobian's clamp.  The only
+    allowed differences are straddlers: Gaussians whose FP64 box edge
+    u +- 3 sqrt(a) or v +- 3 sqrt(c) lies within 1e-4 + 1e-6 |x| of an
+    integer, or whose depth lies within 1e-6 of the near plane (FP32 rounding
+    of the box may then land on either side); they are counted and must stay
+    rare.  A transposed rotation, a swapped Jacobian row or a wrong clamp in
+    either program moves many boxes and fails this."""
+    cam = _cam(W=320, H=240, eye=(0.4, -0.3, -3.1), target=(0.1, 0.05, 0.0))
+    n, n_cl = 2000, 300
+    means, rows7 = _anisotropic_population(21, n, cam, n_cl)
+    key, trect, kept = oracle.keyspec(means, rows7, cam)
+    rows = np.zeros((n, 11))
+    rows[:, :7] = rows7
+    pr = oracle.project(torch.tensor(means.astype(np.float64)), torch.tensor(rows), cam, 0)
+    S2 = pr["Sigma2D"].numpy()
+    z = pr["xc"][:, 2].numpy()
+    u, v = pr["rec"][:, 0].detach().numpy(), pr["rec"][:, 1].detach().numpy()
+    vis, rect64, bounds = _fp64_tile_rect(u, v, S2[:, 0, 0], S2[:, 1, 1], cam.width, cam.height)
+    kept64 = (z > 0.2) & vis
+    frac = np.abs(bounds - np.round(bounds))
+    straddle = (frac < 1e-4 + 1e-6 * np.abs(bounds)).any(1) | (np.abs(z - 0.2) < 1e-6)
+    ok = ~straddle
+    assert straddle.sum() <= 0.01 * n, straddle.sum()
+    np.testing.assert_array_equal(kept[ok], kept64[ok])
+    both = ok & kept & kept64
+    np.testing.assert_array_equal(trect[both].astype(np.int64), rect64[both])
+    # depth key: the IEEE bits of the FP32 camera depth, within the FP32
+    # rounding of a four-term dot product (6 u sum |terms|) of the FP64 depth
+    zk = key[kept].view(np.float32).astype(np.float64)
+    Rt = np.asarray(cam.Rt, np.float64)
+    mag = np.abs(means.astype(np.float64) * Rt[2, :3]).sum(1) + abs(Rt[2, 3])
+    assert (np.abs(zk - z[kept]) <= 6 * 2.0 ** -24 * mag[kept]).all()
+    # the population exercises what it is meant to
+    lim_x = 1.3 * (0.5 * cam.width / float(cam.fx))
+    lim_y = 1.3 * (0.5 * cam.height / float(cam.fy))
+    xc = pr["xc"].numpy()
+    clamped = (np.abs(xc[:, 0] / z) > lim_x) | (np.abs(xc[:, 1] / z) > lim_y)
+    assert (clamped & kept).sum() >= 100
+    aniso = np.linalg.eigvalsh(S2)
+    assert (aniso[:, 1] / aniso[:, 0] > 10.0)[kept].sum() >= 100
+    assert (~kept).sum() >= 50 and kept.sum() >= 1000
+
+
+def test_sigma2d_clamped_equals_jacobian_at_clamped_point():
+    """Beyond the clamp the projection uses the pinhole map's Jacobian taken at
+    the camera point moved onto the clamp boundary (x/z and y/z clamped, z
+    kept): compared with the numerical Jacobian of the pinhole map there and
+    the scipy covariance, for anisotropic rotated Gaussians on every side."""
+    cam = _cam(W=320, H=240, eye=(0.4, -0.3, -3.1), target=(0.1, 0.05, 0.0))
+    means, rows7 = _anisotropic_population(22, 400, cam, 200)
+    rows = np.zeros((400, 11))
+    rows[:, :7] = rows7
+    pr = oracle.project(torch.tensor(means.astype(np.float64)), torch.tensor(rows), cam, 0)
+    Rt = np.asarray(cam.Rt, np.float64)
+    lim_x = 1.3 * (0.5 * cam.width / float(cam.fx))
+    lim_y = 1.3 * (0.5 * cam.height / float(cam.fy))
+    fx, fy = float(cam.fx), float(cam.fy)
+
+    def pi_cam(p):
+        return np.array([fx * p[0] / p[2] + cam.cx, fy * p[1] / p[2] + cam.cy], np.float64)
+
+    n_cl = 0
+    for i in range(200, 400):
+        pc = Rt[:, :3] @ means[i].astype(np.float64) + Rt[:, 3]
+        if pc[2] <= 0.2:
+            continue
+        tx, ty = pc[0] / pc[2], pc[1] / pc[2]
+        if abs(tx) <= lim_x and abs(ty) <= lim_y:
+            continue
+        n_cl += 1
+        pcl = np.array([np.clip(tx, -lim_x, lim_x) * pc[2], np.clip(ty, -lim_y, lim_y) * pc[2], pc[2]])
+        h = 1e-6
+        Jn = np.stack([(pi_cam(pcl + h * e) - pi_cam(pcl - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        Rq = Rotation.from_quat(rows7[i, [4, 5, 6, 3]].astype(np.float64)).as_matrix()
+        S3 = Rq @ np.diag(np.exp(2 * rows7[i, 0:3].astype(np.float64))) @ Rq.T
+        ref = Jn @ Rt[:, :3] @ S3 @ Rt[:, :3].T @ Jn.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(pr["Sigma2D"][i].numpy(), ref, rtol=1e-6)
+    assert n_cl >= 150
+
+
+def test_end_to_end_gradient_vs_central_differences_clamped():
+    """Central differences (frozen decisions) against the oracle's reverse mode
+    on a scene where large Gaussians lie beyond the Jacobian's clamp on every
+    side and still blend into the image: the clamped component of J is
+    constant, so its derivative with respect to the mean is zero."""
+    cam = _cam(W=48, H=40, eye=(0.3, -0.2, -3.0))
+    rng = np.random.default_rng(23)
+    base_sc = scenes.random_scene(24, 30, 6, 1, mu_s=-2.2)
+    lim_x = 1.3 * (0.5 * cam.width / float(cam.fx))
+    lim_y = 1.3 * (0.5 * cam.height / float(cam.fy))
+    n_cl = 8
+    z = rng.uniform(2.6, 3.4, n_cl)
+    t = np.array([[1.25 * lim_x, 0.1], [-1.3 * lim_x, -0.2], [0.2, 1.3 * lim_y], [-0.1, -1.25 * lim_y],
+                  [1.2 * lim_x, 0.5], [-1.15 * lim_x, 0.3], [0.4, 1.2 * lim_y], [-0.3, -1.3 * lim_y]])
+    pc = np.stack([t[:, 0] * z, t[:, 1] * z, z], 1)
+    cl_means = _cam_points_to_world(cam, pc)
+    R = base_sc.r
+    cl_rows = np.zeros((n_cl, R))
+    cl_rows[:, 0:3] = rng.normal(-0.9, 0.25, (n_cl, 3))
+    q = rng.standard_normal((n_cl, 4))
+    cl_rows[:, 3:7] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    cl_rows[:, 7] = rng.normal(-0.5, 0.3, n_cl)
+    cl_rows[:, 8:11] = rng.uniform(0, 1, (n_cl, 3))
+    cl_rows[:, 11:] = rng.normal(0, 0.05, (n_cl, R - 11))
+    sc = scenes.Scene(np.concatenate([base_sc.means, cl_means.astype(np.float32)]),
+                      np.concatenate([base_sc.idx, base_sc.k + np.arange(n_cl, dtype=np.int32)]).astype(np.int32),
+                      np.concatenate([base_sc.cb, cl_rows.astype(np.float32)]), base_sc.sh_degree)
+    base = oracle.render_view(sc, cam, want_lists=True)
+    fz = base["frozen"]
+    blended = set(int(r) for r in fz["order"][np.unique(fz["fz_rec"])])
+    cl_ids = [base_sc.n + i for i in range(n_cl) if base_sc.n + i in blended]
+    assert len(cl_ids) >= 6, cl_ids          # clamped Gaussians really blend
+    gcol = rng.standard_normal(base["color"].shape)
+    g = oracle.render_view(sc, cam, grad_color=gcol)
+    grad_cb = oracle.codebook_grad_reduce(g["grad_rows"], sc.idx, sc.k)
+    rows0 = oracle.decode_rows(sc)
+
+    def loss(cb=None, means=None):
+        rows = rows0 if cb is None else cb[sc.idx]
+        o = oracle.render_view(sc, cam, frozen=fz, rows32=rows, means32=means)
+        return float((o["color"] * gcol).sum())
+
+    h = 1e-4
+    cb64 = sc.cb.astype(np.float64)
+    for k in range(base_sc.k, sc.k):
+        for c in range(sc.r):
+            p = cb64.copy(); p[k, c] += h
+            m = cb64.copy(); m[k, c] -= h
+            fd = (loss(cb=p) - loss(cb=m)) / (2 * h)
+            assert fd == pytest.approx(grad_cb[k, c], rel=1e-5, abs=1e-7), (k, c)
+    m64 = sc.means.astype(np.float64)
+    for i in cl_ids:
+        for c in range(3):
+            p = m64.copy(); p[i, c] += h
+            m = m64.copy(); m[i, c] -= h
+            fd = (loss(means=p) - loss(means=m)) / (2 * h)
+            assert fd == pytest.approx(g["grad_means"][i, c], rel=1e-5, abs=1e-7), (i, c)
