@@ -227,3 +227,37 @@ def random_scene(seed: int, n: int, k: int, sh_degree: int, mu_s: float = -3.0,
                  clusters: bool = False, bf16: bool = False) -> Scene:
     """Small seeded scene for unit tests."""
     return make_scene(np.random.default_rng(seed), n, k, sh_degree, mu_s, clusters, bf16)
+
+
+def needle_scene(seed: int, n_needles: int = 12, n_background: int = 3000, k_background: int = 64,
+                 sh_degree: int = 1, ratio: float = 2000.0) -> Scene:
+    """Small seeded scene seen from (0,0,-3) with n_needles "needle" Gaussians:
+    one long axis lying in a plane facing the camera at an on-screen angle
+    drawn from 30-60 or 120-150 degrees, the two short axes `ratio` times
+    shorter, each on a codebook row of its own, plus n_background ordinary
+    Gaussians (uniform in [-1,1]^3) on k_background shared rows.  The needles'
+    projected footprints are elongated enough that the 2x2 determinant of
+    their projected covariance nearly cancels (the near-degenerate case)."""
+    rng = np.random.default_rng(seed)
+    R = row_width(sh_degree)
+    bg = make_scene(rng, n_background, k_background, sh_degree, -3.5, clusters=False)
+    cb = np.zeros((n_needles, R))
+    long_ls = np.log(rng.uniform(0.45, 0.75, n_needles))
+    cb[:, 0] = long_ls
+    cb[:, 1] = long_ls - math.log(ratio)
+    cb[:, 2] = long_ls - math.log(ratio)
+    ang = np.where(rng.uniform(size=n_needles) < 0.5, rng.uniform(30.0, 60.0, n_needles),
+                   rng.uniform(120.0, 150.0, n_needles))
+    half = np.radians(ang) / 2.0
+    cb[:, 3] = np.cos(half)          # rotation about the viewing axis (w, 0, 0, sin)
+    cb[:, 6] = np.sin(half)
+    cb[:, 7] = rng.normal(1.0, 0.5, n_needles)
+    cb[:, 8:11] = rng.uniform(0.0, 1.0, (n_needles, 3))
+    if sh_degree > 0:
+        cb[:, 11:] = rng.normal(0.0, 0.05, (n_needles, R - 11))
+    nm = np.stack([rng.uniform(-0.6, 0.6, n_needles), rng.uniform(-0.4, 0.4, n_needles),
+                   rng.uniform(-0.5, 0.5, n_needles)], 1)
+    means = np.concatenate([bg.means.astype(np.float64), nm]).astype(np.float32)
+    idx = np.concatenate([bg.idx, k_background + np.arange(n_needles, dtype=np.int32)]).astype(np.int32)
+    cb_all = np.concatenate([bg.cb.astype(np.float64), cb]).astype(np.float32)
+    return Scene(means, idx, np.ascontiguousarray(cb_all), sh_degree, None)

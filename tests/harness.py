@@ -36,6 +36,28 @@ def grad_errors(gpu_means, gpu_cb, ora_means, ora_cb) -> Dict[str, float]:
     return out
 
 
+def grad_error_stats(gpu_means, gpu_cb, ora_means, ora_cb) -> Dict[str, Dict[str, float]]:
+    """Per parameter block: relative L2 error, and the 99th percentile and
+    maximum of the element-wise relative error |g - o| / (|o| + 1e-6 max|o|)."""
+    out = {}
+    pairs = [("means", gpu_means, ora_means)] + [(k, gpu_cb[:, s], ora_cb[:, s]) for k, s in BLOCKS.items()]
+    for k, g, o in pairs:
+        g = np.asarray(g, np.float64).ravel()
+        o = np.asarray(o, np.float64).ravel()
+        if not o.size:
+            continue
+        e = np.abs(g - o) / (np.abs(o) + 1e-6 * max(np.abs(o).max(), 1e-300))
+        out[k] = {"rel_l2": rel_l2(g, o), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
+    return out
+
+
+def record(kind: str, **fields) -> None:
+    """One machine-readable line of measured parity errors (collected into the
+    design notes' error table)."""
+    import json
+    say("PARITY " + json.dumps({"case": kind, **fields}, sort_keys=True))
+
+
 def random_tiles(cam, n_tiles: int, seed: int) -> np.ndarray:
     """Pixels of n_tiles random 16x16 tiles of a view (clipped to the image)."""
     rng = np.random.default_rng(seed)

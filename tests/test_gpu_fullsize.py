@@ -13,14 +13,14 @@ import torch
 
 import oracle
 from paper_2509_03775_amd import cgs, render, scenes as sc
-from harness import (GRAD_TOL, IMAGE_TOL, compare_view, grad_errors, oracle_grad_image, oracle_render,
-                     oracle_scene_grads, random_tiles, say)
+from harness import (GRAD_TOL, IMAGE_TOL, compare_view, grad_error_stats, grad_errors, oracle_grad_image,
+                     oracle_render, oracle_scene_grads, random_tiles, record, say)
 
 pytestmark = pytest.mark.gpu
 
 FULL = ["clusters200k_800px", "clusters1m_1600x1064", "clusters4m_bf16_4x1957x1091", "uneven16_512px"]
-TILES_PER_VIEW = {"clusters200k_800px": 24, "clusters1m_1600x1064": 16, "clusters4m_bf16_4x1957x1091": 6,
-                  "uneven16_512px": 3}
+TILES_PER_VIEW = {"clusters200k_800px": 64, "clusters1m_1600x1064": 128, "clusters4m_bf16_4x1957x1091": 64,
+                  "uneven16_512px": 8}
 
 _cache = {}
 
@@ -111,10 +111,12 @@ def test_sampled_image_and_gradients(name):
     img, T, nl = r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()
     pix = [random_tiles(c, TILES_PER_VIEW[name], 100 + v) for v, c in enumerate(wl.cameras)]
     base = oracle_render(wl, pix)
+    views = []
     for v, cam in enumerate(wl.cameras):
         a, b = r.pix_off[v], r.pix_off[v + 1]
         ec, et, mism, namb = compare_view(img[a:b], T[a:b], nl[a:b], cam, pix[v], base[v])
         say(f"  view {v}: colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}/{len(pix[v])}")
+        views.append({"image_max_abs": ec, "T_max_abs": et, "ambiguous": namb, "pixels": int(len(pix[v]))})
         assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
         assert namb <= 0.02 * len(pix[v])
     gcols, gfull = oracle_grad_image(wl, pix, base)
@@ -122,11 +124,14 @@ def test_sampled_image_and_gradients(name):
     ogm, ogcb = oracle_scene_grads(wl, outs)
     gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
     torch.cuda.synchronize()
+    scenes_rec = []
     for i in range(len(wl.scenes)):
         errs = grad_errors(gm[i].cpu().numpy(), gcb[i].cpu().numpy(), ogm[i], ogcb[i])
+        scenes_rec.append(grad_error_stats(gm[i].cpu().numpy(), gcb[i].cpu().numpy(), ogm[i], ogcb[i]))
         say(f"  scene {i}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
         for k, e in errs.items():
             assert e <= GRAD_TOL, (k, e)
+    record(name, tiles_per_view=TILES_PER_VIEW[name], views=views, grads=scenes_rec)
 
 
 def test_batched_equals_per_view_calls():
@@ -217,7 +222,7 @@ def test_autograd_and_finite_differences_1m():
     wl, r = workload_and_renderer(name)
     s = wl.scenes[0]
     cam = wl.cameras[0]
-    pix = random_tiles(cam, 24, 7)
+    pix = random_tiles(cam, 64, 7)
     base = oracle.render_view(s, cam, pix, want_lists=True)
     gcol = np.zeros_like(base["color"])
     tgt = wl.targets[0][pix[:, 1], pix[:, 0]].astype(np.float64)
@@ -286,3 +291,46 @@ def test_sort_waits_never_hit_bound():
     """The radix passes' look-back waits (bounded so a pass always ends)
     never reached their bound in any call of this session's full-size runs."""
     assert cgs.load().cgs_sort_stalls() == 0
+
+
+def test_uncompressed_identity_rows_1m():
+    """The uncompressed baseline (one codebook row per Gaussian: K = N = 1M,
+    identity indices, the per-Gaussian parameter layout of the paper's MCMC
+    comparison): the row sort takes three radix passes (20-bit keys) and every
+    row's reduction is a single Gaussian.  Image and n_last on 64 random tiles,
+    and the gradient of every row against the oracle's per-Gaussian gradient."""
+    name = "clusters1m_1600x1064"
+    say(f"[uncompressed K = N] {name}")
+    _cache.clear()
+    torch.cuda.empty_cache()
+    wl = sc.make_workload(name)
+    s = wl.scenes[0]
+    su = sc.Scene(s.means, np.arange(s.n, dtype=np.int32), np.ascontiguousarray(s.cb[s.idx]), s.sh_degree)
+    wlu = sc.Workload(name + ":uncompressed", [su], wl.cameras, wl.view_scene, wl.targets, False)
+    r = render.Renderer([render.DeviceScene.from_host(su)], wlu.cameras, wlu.view_scene)
+    r.fit_capacity()
+    r.forward()
+    torch.cuda.synchronize()
+    cam = wlu.cameras[0]
+    pix = [random_tiles(cam, 64, 41)]
+    base = oracle_render(wlu, pix)
+    ec, et, mism, namb = compare_view(r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy(), cam,
+                                      pix[0], base[0])
+    say(f"  colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}/{len(pix[0])}")
+    assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
+    gcols, gfull = oracle_grad_image(wlu, pix, base)
+    outs = oracle_render(wlu, pix, gcols)
+    gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
+    torch.cuda.synchronize()
+    gcb, gm = gcb[0].cpu().numpy(), gm[0].cpu().numpy()
+    errs = grad_errors(gm, gcb, outs[0]["grad_means"], outs[0]["grad_rows"])
+    say("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
+    # rows of Gaussians no sampled pixel depends on are exactly zero
+    untouched = np.abs(outs[0]["grad_rows"]).max(1) == 0
+    assert untouched.sum() > 0.5 * s.n
+    assert (gcb[untouched] == 0).all()
+    record(name + ":uncompressed", views=[{"image_max_abs": ec, "T_max_abs": et, "ambiguous": namb,
+                                           "pixels": int(len(pix[0]))}],
+           grads=[grad_error_stats(gm, gcb, outs[0]["grad_means"], outs[0]["grad_rows"])])

@@ -11,8 +11,8 @@ import torch
 
 import oracle
 from paper_2509_03775_amd import cgs, render, scenes as sc
-from harness import (GRAD_TOL, IMAGE_TOL, compare_view, full_pixels, grad_errors, oracle_grad_image,
-                     oracle_render, oracle_scene_grads, rel_l2, say)
+from harness import (GRAD_TOL, IMAGE_TOL, compare_view, full_pixels, grad_error_stats, grad_errors,
+                     oracle_grad_image, oracle_render, oracle_scene_grads, record, rel_l2, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -129,12 +129,15 @@ def test_forward_full_frame(kind):
     img, T, nl = r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()
     pix = [full_pixels(c) for c in wl.cameras]
     outs = oracle_render(wl, pix)
+    views = []
     for v, cam in enumerate(wl.cameras):
         a, b = r.pix_off[v], r.pix_off[v + 1]
         ec, et, mism, namb = compare_view(img[a:b], T[a:b], nl[a:b], cam, pix[v], outs[v])
         say(f"  view {v}: colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}/{len(pix[v])}")
+        views.append({"image_max_abs": ec, "T_max_abs": et, "ambiguous": namb, "pixels": int(len(pix[v]))})
         assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
         assert namb <= 0.01 * len(pix[v])
+    record(kind + ":forward", views=views)
 
 
 @pytest.mark.parametrize("kind", SMALL)
@@ -150,11 +153,14 @@ def test_backward_full_frame(kind):
     r.forward()
     gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
     torch.cuda.synchronize()
+    scenes_rec = []
     for i in range(len(wl.scenes)):
         errs = grad_errors(gm[i].cpu().numpy(), gcb[i].cpu().numpy(), ogm[i], ogcb[i])
+        scenes_rec.append(grad_error_stats(gm[i].cpu().numpy(), gcb[i].cpu().numpy(), ogm[i], ogcb[i]))
         say(f"  scene {i}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
         for k, e in errs.items():
             assert e <= GRAD_TOL, (k, e)
+    record(kind + ":backward", grads=scenes_rec)
 
 
 def test_determinism():
@@ -386,3 +392,88 @@ def test_two_codebook_layout(bf16):
     say("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, e in errs.items():
         assert e <= GRAD_TOL, (k, e)
+
+
+def test_needle_gaussians_fp64_island():
+    """Needle Gaussians (long axis 2000x the short ones, 30-60 degrees on
+    screen, 35-90 px long sigma) whose projected 2x2 covariance is so
+    elongated that a c - b^2 cancels: the conic then comes from the FP64
+    determinant and inverse.  The host checks with the oracle's FP64 Sigma2D
+    that every needle has det <= 0.7 * 2^-10 a c (inside the island with room
+    for FP32 rounding of a, b, c), then compares the image and gradients.
+
+    Bounds: the island removes the cancellation in the determinant but not
+    the rounding already in the FP32 a, b, c, nor the FP32 storage of the
+    conic; inverting a matrix of condition number kappa = lambda_max /
+    lambda_min amplifies relative rounding by kappa, so the alpha of a pixel
+    a needle covers may be off by about kappa u (u = 2^-24).  Pixels whose
+    tile lies in a needle's rectangle are held to 1e-4 + 2^-23 kappa, the
+    largest kappa among those needles; every other pixel to 1e-4.  Gradients:
+    the background Gaussians' blocks to 1e-3, each needle's codebook row and
+    mean to 2^-20 kappa relative L2.  The measured errors are printed."""
+    say("[needles] FP64 determinant island")
+    s = sc.needle_scene(5)
+    cam = sc.pinhole(320, 240, (0.0, 0.0, -3.0))
+    rng = np.random.default_rng(31)
+    wl = sc.Workload("needles", [s], [cam], np.array([0], np.int32),
+                     [rng.uniform(0, 1, (240, 320, 3)).astype(np.float32)], False)
+    n_needle = 12
+    nd = np.arange(s.n - n_needle, s.n)
+    rows = oracle.decode_rows(s).astype(np.float64)
+    pr = oracle.project(torch.tensor(s.means[nd].astype(np.float64)), torch.tensor(rows[nd]), cam, s.sh_degree)
+    S2 = pr["Sigma2D"].numpy()
+    a, b, c = S2[:, 0, 0], S2[:, 0, 1], S2[:, 1, 1]
+    ratio = (a * c - b * b) / (a * c)
+    lam = np.linalg.eigvalsh(S2)
+    kappa = lam[:, 1] / lam[:, 0]
+    say("  det/(ac): " + " ".join(f"{x:.1e}" for x in ratio))
+    assert (ratio <= 0.7 * 2.0 ** -10).all()
+    # per-pixel bound from the needles whose tile rectangle holds the pixel
+    _, trect, kept = oracle.keyspec(s.means[nd], rows[nd, :7].astype(np.float32), cam)
+    assert kept.all()
+    W, H = cam.width, cam.height
+    tol = np.full((H, W), IMAGE_TOL)
+    kmax = np.zeros((H, W))
+    for i in range(n_needle):
+        x0, y0, x1, y1 = (int(t) for t in trect[i])
+        blk = kmax[16 * y0:16 * y1, 16 * x0:16 * x1]
+        np.maximum(blk, kappa[i], out=blk)
+    tol += 2.0 ** -23 * kmax
+    r = gpu_renderer(wl)
+    r.forward()
+    torch.cuda.synchronize()
+    pix = full_pixels(cam)
+    base = oracle_render(wl, [pix])[0]
+    img = r.image.cpu().numpy().astype(np.float64)
+    err = np.abs(img - base["color"]).max(1)
+    ok = ~base["ambiguous"]
+    t_flat = tol.ravel()
+    in_needle = kmax.ravel() > 0
+    nl = r.n_last.cpu().numpy()
+    say(f"  image: max err off needles {err[ok & ~in_needle].max():.2e}, on needles {err[ok & in_needle].max():.2e} "
+        f"(bound there {t_flat[ok & in_needle].min():.2e}..{t_flat[ok & in_needle].max():.2e}), "
+        f"max err / bound {(err[ok] / t_flat[ok]).max():.2f}, n_last mismatches {(nl[ok] != base['n_last'][ok]).sum()}, "
+        f"ambiguous {(~ok).sum()}")
+    assert (err[ok] <= t_flat[ok]).all()
+    assert (~ok).sum() <= 0.01 * len(pix)
+    # gradients
+    gcols, gfull = oracle_grad_image(wl, [pix], [base])
+    outs = oracle_render(wl, [pix], gcols)
+    ogm, ogcb = oracle_scene_grads(wl, outs)
+    gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
+    torch.cuda.synchronize()
+    gm, gcb = gm[0].cpu().numpy(), gcb[0].cpu().numpy()
+    kb = s.k - n_needle
+    bg_err = grad_errors(gm[:s.n - n_needle], gcb[:kb], ogm[0][:s.n - n_needle], ogcb[0][:kb])
+    say("  background: " + " ".join(f"{k}={v:.2e}" for k, v in bg_err.items()))
+    for k, e in bg_err.items():
+        assert e <= GRAD_TOL, (k, e)
+    worst = 0.0
+    for i in range(n_needle):
+        er = rel_l2(gcb[kb + i], ogcb[0][kb + i])
+        em = rel_l2(gm[nd[i]], ogm[0][nd[i]])
+        bound = 2.0 ** -20 * kappa[i]
+        worst = max(worst, max(er, em) / bound)
+        say(f"  needle {i}: kappa {kappa[i]:.0f} row rel err {er:.2e} mean rel err {em:.2e} (bound {bound:.2e})")
+        assert er <= bound and em <= bound, (i, er, em, bound)
+    say(f"  needle gradients: worst error / bound {worst:.2f}")
