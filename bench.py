@@ -33,7 +33,13 @@ from paper_2509_03775_amd import autotune, cgs, render, scenes as sc  # noqa: E4
 METRIC = "fwd+bwd rendered Mpixel/s at 1M/4M Gaussians, BF16-batched vs plain FP32"
 HEADLINE = "clusters4m_bf16_4x1957x1091"
 VALU_PEAK = 256 * 4 * 16 * 2.4e9        # FP32 lane-operations/s, non-packed issue rate
+FP32_PEAK = 157.3e12                    # MI355X FP32 vector peak (published; counts packed FMAs)
 HBM_PEAK = 8.0e12                       # bytes/s
+# The cost model of the blend stages: VALU operations per evaluated
+# (pixel, Gaussian) pair, forward and backward, each priced against the
+# published FP32 vector peak (the headline roofline and the combined
+# per-stage roofline use these).
+MODEL_OPS_FWD, MODEL_OPS_BWD = 20, 45
 # Algorithmic FP32 operations per (pixel, Gaussian) pair (an FMA, an exp, a
 # compare each count as one): alpha of a pair (2 sub, 5 for the quadratic
 # form, exp, opacity product, 0.99 clamp, 1/255 test) = 11; a blended pair
@@ -281,6 +287,8 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
     rng = np.random.default_rng(7)
     tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
 
+    last = {}
+
     def run(ntiles):
         pick = rng.choice(tx * ty, size=ntiles, replace=False)
         pix = []
@@ -294,9 +302,14 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
         t_fwd = time.perf_counter() - t0
         tgt = wl.targets[0][pix[:, 1], pix[:, 0]].astype(np.float64)
         g = np.sign(o["color"] - tgt) / (3.0 * P)
-        o2 = oracle.render_view(s, cam, pix, grad_color=g)
-        oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
-        return time.perf_counter() - t0, pix.shape[0], ntiles, t_fwd
+        g[o["ambiguous"]] = 0.0
+        g32 = g.astype(np.float32)
+        o2 = oracle.render_view(s, cam, pix, grad_color=g32.astype(np.float64))
+        gcb = oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
+        dt = time.perf_counter() - t0
+        last.update(pix=pix, color=o["color"], ambiguous=o["ambiguous"], n_last=o["n_last"], g32=g32,
+                    grad_means=o2["grad_means"], grad_cb=gcb)
+        return dt, pix.shape[0], ntiles, t_fwd
 
     # each call projects the whole scene once (a fixed cost) and then
     # composites its tiles; grow the tile count until one call takes about
@@ -313,7 +326,38 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
             "cpu": model, "affinity": affinity, "nproc": nproc, "forward_value": npix / dt_fwd / 1e6,
             "full_frame": [cpu_full_frame("uniform4k_128px")],
             "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
-                      f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}
+                      f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}, last
+
+
+def oracle_parity(form: "Form", sample: dict) -> dict:
+    """The timed batched form against the FP64 oracle on the CPU baseline's
+    sample (tiles of view 0): image error on non-ambiguous pixels, n_last
+    mismatches, and per-block gradient errors of the L1 loss restricted to the
+    sample (both sides given the same FP32 image gradient, zero elsewhere)."""
+    r = form.renderers[0]
+    cam = r.cameras[0]
+    pix = sample["pix"]
+    lin = pix[:, 1].astype(np.int64) * cam.width + pix[:, 0]
+    r.forward()
+    torch.cuda.synchronize()
+    img = r.image[:cam.width * cam.height].cpu().numpy().astype(np.float64)[lin]
+    nl = r.n_last[:cam.width * cam.height].cpu().numpy()[lin]
+    ok = ~sample["ambiguous"]
+    gimg = torch.zeros((r.n_pixels, 3), dtype=torch.float32)
+    gimg[torch.from_numpy(lin)] = torch.from_numpy(sample["g32"])
+    gm, gcb = r.backward(gimg.cuda())
+    torch.cuda.synchronize()
+    gcb, gm = gcb[0].cpu().numpy().astype(np.float64), gm[0].cpu().numpy().astype(np.float64)
+    ocb, om = sample["grad_cb"], sample["grad_means"]
+
+    def rel(a, b):
+        nb = np.linalg.norm(b)
+        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+    return {"pixels": int(len(lin)), "ambiguous": int((~ok).sum()),
+            "image_max_abs": float(np.abs(img[ok] - sample["color"][ok]).max()),
+            "n_last_mismatches": int((nl[ok] != sample["n_last"][ok]).sum()),
+            "grad_rel_l2": {"means": rel(gm, om), **{k: rel(gcb[:, sl], ocb[:, sl]) for k, sl in GRAD_BLOCKS.items()}},
+            "of": "view 0, the CPU baseline's sampled tiles"}
 
 
 def cpu_full_frame(name: str):
@@ -337,15 +381,38 @@ def cpu_full_frame(name: str):
 
 
 def blend_roofline(stage, ms, e_eval, e_blend, workload, schedule):
-    if stage == "blend_fwd":
-        ops = OPS_ALPHA * e_eval + OPS_FWD_BLEND * e_blend
-    else:
-        ops = OPS_ALPHA * e_eval + OPS_BWD_BLEND * e_blend
-    ach = ops / (ms * 1e-3)
+    """Roofline of one blend launch.  Headline figures: the cost model's VALU
+    operations per evaluated pair (MODEL_OPS_*) times the evaluated pairs of
+    the launch, divided by its measured duration, against the published FP32
+    vector peak.  issue_model: the finer count (11 per evaluated pair plus 8
+    or 30 per blended pair) against the non-packed issue rate."""
     kernel = "k_blend_bwd" if stage == "blend_bwd" else "k_blend_fwd"
-    return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
-            "frac": ach / VALU_PEAK, "traffic": measured_traffic(kernel, workload, schedule), "kernel": kernel,
-            "ops_per_launch": ops, "launch_ms": ms}
+    per_pair = MODEL_OPS_BWD if stage == "blend_bwd" else MODEL_OPS_FWD
+    ops = per_pair * e_eval
+    ach = ops / (ms * 1e-3)
+    fine = OPS_ALPHA * e_eval + (OPS_BWD_BLEND if stage == "blend_bwd" else OPS_FWD_BLEND) * e_blend
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": ach / FP32_PEAK, "traffic": measured_traffic(kernel, workload, schedule), "kernel": kernel,
+            "model": f"{per_pair} VALU ops per evaluated pair x {e_eval} evaluated pairs per launch",
+            "ops_per_launch": ops, "launch_ms": ms,
+            "issue_model": {"ops_per_launch": fine, "achieved": fine / (ms * 1e-3) / 1e12,
+                            "peak": VALU_PEAK / 1e12, "unit": "T lane-ops/s",
+                            "frac": fine / (ms * 1e-3) / VALU_PEAK}}
+
+
+def combined_roofline(stages_ms: dict, sb: dict, e_eval: int, step_ms: float) -> dict:
+    """Sum over stages of max(bytes / HBM peak, VALU ops / FP32 peak) against
+    the measured step: the blends priced by the cost model's operations per
+    evaluated pair, every other stage by its algorithmic bytes."""
+    ops = {"blend_fwd": MODEL_OPS_FWD * e_eval, "blend_bwd": MODEL_OPS_BWD * e_eval}
+    per = {}
+    for k in stages_ms:
+        t_b = sb.get(k, 0) / HBM_PEAK
+        t_o = ops.get(k, 0) / FP32_PEAK
+        per[k] = {"roof_ms": 1e3 * max(t_b, t_o), "bound": "alu" if t_o > t_b else "hbm",
+                  "measured_ms": stages_ms[k], "frac": 1e3 * max(t_b, t_o) / stages_ms[k] if stages_ms[k] else None}
+    t_roof = sum(v["roof_ms"] for v in per.values())
+    return {"roof_ms": t_roof, "step_ms": step_ms, "frac": t_roof / step_ms, "stages": per}
 
 
 def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
@@ -384,15 +451,52 @@ def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     return out
 
 
+GRAD_BLOCKS = {"ls": slice(0, 3), "q": slice(3, 7), "logit": slice(7, 8), "sh_dc": slice(8, 11),
+               "sh_rest": slice(11, None)}
+
+
+def _weighted_grads(form: "Form"):
+    """Codebook and mean gradients of a form, each call's share weighted by
+    its pixels over the batch's: the loss of every call is a mean over that
+    call's pixels, so this puts a one-call-per-view form on the same
+    normalisation (mean over the whole batch) as the batched form."""
+    gc = gm = 0
+    for r in form.renderers:
+        w = r.n_pixels / form.n_pixels
+        gc = gc + w * r.grad_cb[0].double()
+        gm = gm + w * r.grad_means[0].double()
+    return gc, gm
+
+
 def compare_forms(a: "Form", b: "Form"):
-    """Image and codebook-gradient difference between two forms of the same
-    scene (BF16 vs FP32 codebook storage: the quantisation effect)."""
+    """Image and gradient difference between two forms of the same scene
+    (BF16 vs FP32 codebook storage: the quantisation effect), after one step
+    of each; gradients per parameter block, relative L2 against b."""
     ia = torch.cat([r.image for r in a.renderers]).double()
     ib = torch.cat([r.image for r in b.renderers]).double()
-    ga = sum(g for r in a.renderers for g in r.grad_cb).double()
-    gb = sum(g for r in b.renderers for g in r.grad_cb).double()
-    return {"image_max_abs": float((ia - ib).abs().max()), "image_mean_abs": float((ia - ib).abs().mean()),
-            "codebook_grad_rel_l2": float(torch.linalg.norm(ga - gb) / torch.linalg.norm(gb))}
+    ga, ma = _weighted_grads(a)
+    gb, mb = _weighted_grads(b)
+
+    def rel(x, y):
+        return float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
+    out = {"image_max_abs": float((ia - ib).abs().max()), "image_mean_abs": float((ia - ib).abs().mean()),
+           "codebook_grad_rel_l2": rel(ga, gb), "means_grad_rel_l2": rel(ma, mb)}
+    out["codebook_grad_rel_l2_by_block"] = {k: rel(ga[:, sl], gb[:, sl]) for k, sl in GRAD_BLOCKS.items()}
+    return out
+
+
+def check_form(form: "Form") -> dict:
+    """Device-side conditions of the form's last step: every call had the
+    instance capacity it needed, and no radix-sort wait reached its bound
+    (either would make the timed step do less than the full work)."""
+    torch.cuda.synchronize()
+    info = [r.d_info.cpu().numpy() for r in form.renderers]
+    ok = all(int(i[0]) == cgs.CGS_OK for i in info)
+    stalls = int(cgs.load().cgs_sort_stalls())
+    if not ok or stalls != 0:
+        raise RuntimeError(f"bench: a timed step was incomplete (d_info {[list(map(int, i)) for i in info]}, "
+                           f"sort stalls {stalls})")
+    return {"capacity_ok": ok, "sort_stalls": stalls}
 
 
 def uncompressed_workload(wl: sc.Workload) -> sc.Workload:
@@ -507,6 +611,7 @@ def main():
     stages = stage_times(ev, args.steps)
     step_dist = step_distribution(ev, args.steps)
     value = wl.n_pixels / (ms * 1e-3) / 1e6
+    checks = {"batched": check_form(head)}
     e_eval, e_blend, walked = pair_counts(head)
     dom = max(("blend_fwd", "blend_bwd"), key=lambda k: stages[k])
     roof = blend_roofline(dom, stages[dom], e_eval, e_blend, args.workload, sched)
@@ -515,16 +620,24 @@ def main():
     extras = [x for x in args.extra_forms.split(",") if x and x != "none"]
     extra_info = {}
     nsteps = max(3, args.steps // 2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s) and the oracle check of its sample")
+        cpu, sample = cpu_baseline(wl, args.cpu_seconds)
+        extra_info["oracle_parity"] = oracle_parity(head, sample)
+        del sample
     if "graph" in extras:
         log("[bench] timing the batched step as HIP graph replays")
         extra_info["graph_ms_per_step"] = time_graph(head, nsteps)
+        checks["graph"] = check_form(head)
         forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_graph:{args.workload}"] = \
             wl.n_pixels / (extra_info["graph_ms_per_step"] * 1e-3) / 1e6
     if "fp32_plain" in extras:
         log(f"[bench] timing {args.workload} plain fp32")
         wl32 = sc.make_workload(args.workload, bf16=False)
-        f = Form(wl32, batched=False, waves_per_block=sched[0], tile_order=sched[1])
+        f = Form(wl32, batched=False)      # plain: default schedule, one call per view
         forms[f"fp32_plain:{args.workload}"] = wl32.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
+        checks["fp32_plain"] = check_form(f)
         if wl.bf16:
             head.step()
             torch.cuda.synchronize()
@@ -536,6 +649,7 @@ def main():
         f = Form(wl, batched=True, waves_per_block=sched[0], tile_order=sched[1], train=True)
         ev2 = HipEvents(nsteps * cgs.STAGE_EVENTS)
         ms_t = f.time(nsteps, 2, ev2)
+        checks["train"] = check_form(f)
         st2 = stage_times(ev2, nsteps)
         forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_train_ssim_sgld:{args.workload}"] = wl.n_pixels / (ms_t * 1e-3) / 1e6
         extra_info["train_step"] = {
@@ -552,6 +666,7 @@ def main():
         wu = uncompressed_workload(wl)
         f = Form(wu, batched=True, waves_per_block=sched[0], tile_order=sched[1])
         ms_u = f.time(nsteps, 2)
+        checks["uncompressed"] = check_form(f)
         forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_uncompressed:{args.workload}"] = wl.n_pixels / (ms_u * 1e-3) / 1e6
         extra_info["codebook_speedup_vs_uncompressed"] = ms_u / ms
         del f, wu
@@ -563,9 +678,10 @@ def main():
         for bf in (True, False):
             log(f"[bench] timing {name} {'bf16 batched' if bf else 'fp32 plain'}")
             w1 = sc.make_workload(name, bf16=bf)
-            f = Form(w1, batched=bf, waves_per_block=sched[0], tile_order=sched[1])
+            f = Form(w1, batched=bf, waves_per_block=sched[0] if bf else 1, tile_order=sched[1] if bf else 0)
             forms[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = \
                 w1.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
+            checks[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = check_form(f)
             del f
             torch.cuda.empty_cache()
     if "uneven16" in extras:
@@ -573,15 +689,13 @@ def main():
         for bf, batched in ((True, True), (False, False)):
             log(f"[bench] timing {name} {'bf16 batched' if batched else 'fp32 plain (16 calls)'}")
             w5 = sc.make_workload(name, bf16=bf)
-            f = Form(w5, batched=batched, waves_per_block=sched[0], tile_order=sched[1])
+            f = Form(w5, batched=batched, waves_per_block=sched[0] if batched else 1,
+                     tile_order=sched[1] if batched else 0)
             ms5 = time_graph(f, nsteps) if batched else f.time(nsteps, 2)
             forms[f"{'bf16_batched_graph' if batched else 'fp32_plain'}:{name}"] = w5.n_pixels / (ms5 * 1e-3) / 1e6
+            checks[f"{'bf16_batched_graph' if batched else 'fp32_plain'}:{name}"] = check_form(f)
             del f
             torch.cuda.empty_cache()
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        cpu = cpu_baseline(wl, args.cpu_seconds)
     cam = wl.cameras[0]
     sb = step_bytes(wl, n_inst, walked)
     out = {
@@ -599,6 +713,8 @@ def main():
         "step_ms_dist": step_dist,
         "hbm_roofline_step": {"algorithmic_bytes": sb["total"], "bytes_by_stage": sb,
                               "frac": sb["total"] / HBM_PEAK / (ms * 1e-3)},
+        "combined_roofline_step": combined_roofline(stages, sb, e_eval, ms),
+        "checks": checks,
         "extra": extra_info,
         "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst, "walked_instances": walked},
         "schedule": {"waves_per_block": sched[0], "tile_order": sched[1], "candidates_ms": tuned},

@@ -35,6 +35,13 @@
  *  - Floating-point results are FP32; codebooks may be stored in FP32 or BF16.
  *  - All entry points are thread-compatible: concurrent calls must use
  *    different workspaces.
+ *  - State the library keeps between calls (nothing else is global): per
+ *    device, the second stream and its two events described above (created
+ *    on first use, kept until the process ends; calls that fork to it are
+ *    serialised per device by a mutex from fork to join, and an error return
+ *    after the fork still joins it); a device counter of radix-sort waits
+ *    that reached their bound (cgs_sort_stalls); per host thread, a scratch
+ *    copy of the last batch plan (host memory, rebuilt by every call).
  */
 #ifndef CGS_H
 #define CGS_H

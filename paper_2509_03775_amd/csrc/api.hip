@@ -333,6 +333,23 @@ hipError_t side_join(Side* sd, hipStream_t st) {
     return e == hipSuccess ? hipStreamWaitEvent(st, sd->join, 0) : e;
 }
 
+// Joins the side stream back into the caller's stream when a call returns
+// early (an error after the fork), so no forked work is left outside the
+// caller's stream order or a capture of it.  The normal path joins
+// explicitly with join(), which reports the join's own error.
+struct SideGuard {
+    Side* sd = nullptr;
+    hipStream_t st = nullptr;
+    hipError_t join() {
+        Side* s = sd;
+        sd = nullptr;
+        return s ? side_join(s, st) : hipSuccess;
+    }
+    ~SideGuard() {
+        if (sd) (void)side_join(sd, st);
+    }
+};
+
 }  // namespace
 }  // namespace cgs
 
@@ -401,9 +418,12 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     // the backward, so scanned beside the depth sort on the side stream
     Side* side = side_stream(st);
     std::unique_lock<std::mutex> side_lk;
+    SideGuard guard;        // declared after the lock: joins before it is released
     if (side) {
         side_lk = std::unique_lock<std::mutex>(side->mu);
         CGS_TRY(side_fork(side, st));
+        guard.sd = side;
+        guard.st = st;
     }
     CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), nullptr, h.d.n_rec, at<uint32_t>(ws, p.slot_off), nullptr,
                      at<unsigned long long>(ws, p.scan_bsum2), side ? side->s : st));
@@ -445,7 +465,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(mark(h, 2, st));
     CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
                              at<float4>(ws, p.rec), at<uint8_t>(ws, p.qbits), image, T_final, n_last, h.n_blend, st));
-    if (side) CGS_TRY(side_join(side, st));
+    CGS_TRY(guard.join());
     CGS_TRY(mark(h, 3, st));
     return CGS_OK;
 }
@@ -539,10 +559,13 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     };
     Side* side = single ? side_stream(st) : nullptr;
     std::unique_lock<std::mutex> side_lk;
+    SideGuard guard;        // declared after the lock: joins before it is released
     int pb0 = 0;
     if (side) {
         side_lk = std::unique_lock<std::mutex>(side->mu);
         CGS_TRY(side_fork(side, st));
+        guard.sd = side;
+        guard.st = st;
         CGS_TRY(sort_rows(0, h.d.sr_rows_total, side->s, &pb0));
     }
     float* ginst = at<float>(ws, p.ginst);
@@ -565,7 +588,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
         else if (part_i == 0) { c0 = 0; D = h.opacity_mode ? 8 : 7; }
         else { c0 = 8; D = h.d.row_width - 8; }
         int pb = pb0;
-        if (side) CGS_TRY(side_join(side, st));
+        if (side) CGS_TRY(guard.join());
         else CGS_TRY(sort_rows(part_i, rows, st, &pb));
         CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
     }

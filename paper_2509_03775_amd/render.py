@@ -156,6 +156,10 @@ class Renderer:
         self.T_final = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
         self.n_last = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
         self.d_info = torch.zeros(4, dtype=torch.int64, device=self.device)
+        # forward() calls so far: the backward reads the binning, T_final and
+        # n_last the last forward left in the workspace, so a differentiable
+        # render checks that no other forward ran in between
+        self.generation = 0
         self.grad_means, self.grad_cb, self.grad_sr, self.grad_sh, self.grad_opacity = [], [], [], [], []
         gr = []
         for s in self.scenes:
@@ -207,6 +211,7 @@ class Renderer:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
 
     def forward(self, stream=None) -> torch.Tensor:
+        self.generation += 1
         cgs.render_forward(self.batch, self.image.data_ptr(), self.T_final.data_ptr(), self.n_last.data_ptr(),
                            self.ws.data_ptr(), self.ws_bytes, self.d_info.data_ptr(), _stream_ptr(stream))
         return self.image
@@ -262,17 +267,26 @@ class CgsRenderFunction(torch.autograd.Function):
     """image = render(means_0, codebook_0, means_1, codebook_1, ...).
 
     The backward recomputes each blended Gaussian's transmittance from the
-    per-pixel final transmittance instead of storing it per pair."""
+    per-pixel final transmittance instead of storing it per pair.  It reads
+    what the forward left in the renderer (binning, T_final, n_last), so it
+    raises if the renderer ran another forward since, and the inputs are saved
+    for backward so that autograd raises if one was modified in place."""
 
     @staticmethod
     def forward(ctx, renderer: Renderer, *tensors):
         ctx.renderer = renderer
         img = renderer.forward()
+        ctx.generation = renderer.generation
+        ctx.save_for_backward(*tensors)
         return img.clone()
 
     @staticmethod
     def backward(ctx, grad_image):
         r: Renderer = ctx.renderer
+        ctx.saved_tensors      # autograd's in-place modification check
+        if r.generation != ctx.generation:
+            raise RuntimeError("render backward: the renderer ran another forward after this one, so the "
+                               "binning and transmittance this backward needs are gone; call render() again")
         gm, gc = r.backward(grad_image.contiguous().float())
         out: List[Optional[torch.Tensor]] = [None]
         for s, m, c in zip(r.scenes, gm, gc):
