@@ -24,6 +24,11 @@
  * A pixel is flagged ambiguous when any of its FP64 threshold tests (alpha
  * against 1/255, T(1-alpha) against 1e-4) lies within a relative margin of
  * the threshold: FP32 arithmetic may legitimately decide those differently.
+ * rec_margin (optional, one per record) widens the margin of a record whose
+ * FP32 alpha is known to be less accurate (an ill-conditioned footprint): its
+ * alpha test uses max(margin, rec_margin[r]), and every transmittance test
+ * from that record on uses the largest margin of the records blended so far,
+ * since an error in an earlier alpha carries into T.
  *
  * Record layout per Gaussian (FP64): u v A B C o r g b.
  * Gradient layout matches; gradients are accumulated (+=) into grad_rec.
@@ -46,7 +51,7 @@ int oc_composite(int64_t n_rec, const double* rec, const int32_t* trect,
                  double* out_color, double* out_T, int32_t* out_nlast, int32_t* out_amb,
                  int32_t* out_ncontrib,
                  const double* grad_color, double* grad_rec, double margin,
-                 int32_t replay, const int64_t* fz_ptr, int64_t* fz_rec)
+                 int32_t replay, const int64_t* fz_ptr, int64_t* fz_rec, const double* rec_margin)
 {
     (void)W; (void)H;
     int fail = 0;
@@ -66,6 +71,7 @@ int oc_composite(int64_t n_rec, const double* rec, const int32_t* trect,
             double T = 1.0, col[3] = {0.0, 0.0, 0.0};
             int64_t pos = 0, nlast = 0, nc = 0, nblend = 0;
             int amb = 0;
+            double tmargin = margin;   /* margin of the transmittance test */
             const int64_t jend = replay ? fz_ptr[p + 1] - fz_ptr[p] : n_rec;
             for (int64_t j = 0; j < jend; ++j) {
                 const int64_t r = replay ? fz_rec[fz_ptr[p] + j] : j;
@@ -82,10 +88,12 @@ int oc_composite(int64_t n_rec, const double* rec, const int32_t* trect,
                 int clampa = 0;
                 double alpha = og;
                 if (alpha > 0.99) { alpha = 0.99; clampa = 1; }
-                if (fabs(alpha - 1.0 / 255.0) <= margin * (1.0 / 255.0)) amb = 1;
+                const double amargin = (rec_margin && rec_margin[r] > margin) ? rec_margin[r] : margin;
+                if (fabs(alpha - 1.0 / 255.0) <= amargin * (1.0 / 255.0)) amb = 1;
                 if (!replay && alpha < 1.0 / 255.0) continue;
+                if (amargin > tmargin) tmargin = amargin;
                 const double Tn = T * (1.0 - alpha);
-                if (fabs(Tn - 1e-4) <= margin * 1e-4) amb = 1;
+                if (fabs(Tn - 1e-4) <= tmargin * 1e-4) amb = 1;
                 if (!replay && Tn < 1e-4) break;
                 if (fz_rec && !replay) fz_rec[fz_ptr[p] + nblend] = r;
                 ++nblend;

@@ -59,7 +59,7 @@ def lib():
                                    ctypes.c_int64, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
-                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.oc_composite.restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -272,14 +272,17 @@ def render_view(scene, cam, pixels: Optional[np.ndarray] = None,
                 grad_color: Optional[np.ndarray] = None,
                 frozen: Optional[dict] = None, margin: float = AMBIGUITY_MARGIN,
                 rows32: Optional[np.ndarray] = None, means32: Optional[np.ndarray] = None,
-                want_lists: bool = False) -> dict:
+                want_lists: bool = False, rec_margin: Optional[np.ndarray] = None) -> dict:
     """Render the requested pixels of one view (all pixels if None).
 
     grad_color [n_pix,3]: dL/dC at those pixels -> returns per-Gaussian
     'grad_means' [N,3] and 'grad_rows' [N,R] (FP64).
     frozen: decisions of an earlier call ({'kept','order','trect','fz_ptr',
     'fz_rec'}), replayed exactly (finite differences with a frozen active set).
-    rows32/means32 override the scene's values (perturbed copies)."""
+    rows32/means32 override the scene's values (perturbed copies).
+    rec_margin [N] (optional, per Gaussian): a wider ambiguity margin for
+    Gaussians whose FP32 alpha is known to be less accurate; it applies to
+    their alpha test and to every transmittance test after them."""
     W, H = cam.width, cam.height
     if pixels is None:
         yy, xx = np.mgrid[0:H, 0:W]
@@ -332,10 +335,11 @@ def render_view(scene, cam, pixels: Optional[np.ndarray] = None,
     grad_rec = np.zeros_like(rec) if want_grad else None
     gc = np.ascontiguousarray(grad_color, np.float64) if want_grad else None
     L = lib()
+    rm = None if rec_margin is None else np.ascontiguousarray(np.asarray(rec_margin, np.float64)[order])
     if frozen is None:
         rc = L.oc_composite(rec.shape[0], _p(rec), _p(trect_o), W, H, _p(bg), npix, _p(pixels),
                             _p(color), _p(T), _p(nlast), _p(amb), _p(ncon), _p(gc), _p(grad_rec),
-                            margin, 0, None, None)
+                            margin, 0, None, None, _p(rm))
         fz_ptr = fz_rec = None
         if want_lists:
             fz_ptr = np.zeros(npix + 1, np.int64)
@@ -345,12 +349,12 @@ def render_view(scene, cam, pixels: Optional[np.ndarray] = None,
                                   np.empty_like(amb), np.empty_like(ncon))
             rc |= L.oc_composite(rec.shape[0], _p(rec), _p(trect_o), W, H, _p(bg), npix, _p(pixels),
                                  _p(c2), _p(T2), _p(n2), _p(a2), _p(k2), None, None,
-                                 margin, 0, _p(fz_ptr), _p(fz_rec))
+                                 margin, 0, _p(fz_ptr), _p(fz_rec), _p(rm))
     else:
         fz_ptr, fz_rec = frozen["fz_ptr"], frozen["fz_rec"]
         rc = L.oc_composite(rec.shape[0], _p(rec), _p(trect_o), W, H, _p(bg), npix, _p(pixels),
                             _p(color), _p(T), _p(nlast), _p(amb), _p(ncon), _p(gc), _p(grad_rec),
-                            margin, 1, _p(fz_ptr), _p(fz_rec))
+                            margin, 1, _p(fz_ptr), _p(fz_rec), _p(rm))
     if rc != 0:
         raise MemoryError("oracle compositing ran out of memory")
     out = {"color": color, "T": T, "n_last": nlast, "ambiguous": amb.astype(bool),

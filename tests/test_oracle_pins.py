@@ -172,7 +172,7 @@ def test_colour_degree0_closed_form():
 
 
 # -------------------------------------------------------- P-5..P-8 compositing
-def _composite(rec, trect, W, H, pix, bg=(0, 0, 0), grad=None, margin=1e-4):
+def _composite(rec, trect, W, H, pix, bg=(0, 0, 0), grad=None, margin=1e-4, rec_margin=None):
     rec = np.ascontiguousarray(rec, np.float64)
     trect = np.ascontiguousarray(trect, np.int32)
     pix = np.ascontiguousarray(pix, np.int32)
@@ -182,9 +182,10 @@ def _composite(rec, trect, W, H, pix, bg=(0, 0, 0), grad=None, margin=1e-4):
     bgv = np.asarray(bg, np.float64)
     gr = np.zeros_like(rec) if grad is not None else None
     g = None if grad is None else np.ascontiguousarray(grad, np.float64)
+    rm = None if rec_margin is None else np.ascontiguousarray(rec_margin, np.float64)
     rc = oracle.lib().oc_composite(rec.shape[0], orr._p(rec), orr._p(trect), W, H, orr._p(bgv), n,
                                    orr._p(pix), orr._p(col), orr._p(T), orr._p(nl), orr._p(amb),
-                                   orr._p(nc), orr._p(g), orr._p(gr), margin, 0, None, None)
+                                   orr._p(nc), orr._p(g), orr._p(gr), margin, 0, None, None, orr._p(rm))
     assert rc == 0
     return col, T, nl, amb, gr
 
@@ -216,6 +217,36 @@ def test_two_gaussians_closed_form_and_swap():
     col2, _, _, _, _ = _composite([r2, r1], [[0, 0, 1, 1]] * 2, 16, 16, pix)
     ref2 = a2 * np.array(r2[6:]) + (1 - a2) * a1 * np.array(r1[6:])
     np.testing.assert_allclose(col2[0], ref2, rtol=1e-14)
+
+
+def test_per_record_ambiguity_margin():
+    """A record's own margin widens its alpha test and every transmittance
+    test from it on, and changes nothing else.  Pixel-centred records make
+    alpha = o exactly: record 0 has alpha 1.05/255, 5% above the threshold
+    (ambiguous only under a margin >= 0.05); record 1 (alpha 0.99) leaves T
+    far from 1e-4; record 2 then takes T to 1.03e-4, within 3% of 1e-4
+    (ambiguous only under a margin >= 0.03, which its own test or the widened
+    margin of an earlier blended record must supply)."""
+    a0 = 1.05 / 255.0
+    T1 = (1.0 - a0) * (1.0 - 0.99)
+    T2 = 1e-4 * 1.03
+    a2 = 1.0 - T2 / T1
+    rec = np.array([[3.0, 3.0, 0.5, 0.0, 0.5, a0, 1.0, 0.0, 0.0],
+                    [3.0, 3.0, 0.5, 0.0, 0.5, 0.99, 0.0, 1.0, 0.0],
+                    [3.0, 3.0, 0.5, 0.0, 0.5, a2, 0.0, 0.0, 1.0]])
+    tr = [[0, 0, 1, 1]] * 3
+    ref = [a0, (1 - a0) * 0.99, T1 * a2]
+    for rm, expect in [(None, 0), ([0.0, 0.0, 0.0], 0), ([0.06, 0.0, 0.0], 1), ([0.04, 0.0, 0.0], 1),
+                       ([0.0, 0.04, 0.0], 1), ([0.0, 0.0, 0.04], 1), ([0.02, 0.02, 0.02], 0)]:
+        col, T, nl, amb, _ = _composite(rec, tr, 16, 16, [[3, 3]], rec_margin=rm)
+        assert amb[0] == expect, (rm, amb[0])
+        assert nl[0] == 3 and T[0] == pytest.approx(T2, rel=1e-12)
+        np.testing.assert_allclose(col[0], ref, rtol=1e-12)
+    # record 0 alone: a margin of 0.04 does not reach its 5% gap, 0.06 does
+    _, _, _, amb, _ = _composite(rec[:1], tr[:1], 16, 16, [[3, 3]], rec_margin=[0.04])
+    assert amb[0] == 0
+    _, _, _, amb, _ = _composite(rec[:1], tr[:1], 16, 16, [[3, 3]], rec_margin=[0.06])
+    assert amb[0] == 1
 
 
 def _random_records(rng, n, W, H, white=False):
@@ -296,16 +327,16 @@ def test_composite_reverse_mode_vs_central_differences():
     bg = np.array([0.2, 0.1, 0.3])
     recc = np.ascontiguousarray(rec); trc = np.ascontiguousarray(tr, np.int32); pc = np.ascontiguousarray(pix, np.int32)
     L.oc_composite(60, orr._p(recc), orr._p(trc), W, H, orr._p(bg), n, orr._p(pc), orr._p(col), orr._p(T),
-                   orr._p(nl), orr._p(am), orr._p(nc), None, None, 1e-4, 0, None, None)
+                   orr._p(nl), orr._p(am), orr._p(nc), None, None, 1e-4, 0, None, None, None)
     ptr = np.zeros(n + 1, np.int64); ptr[1:] = np.cumsum(nc)
     lst = np.empty(int(ptr[-1]), np.int64)
     L.oc_composite(60, orr._p(recc), orr._p(trc), W, H, orr._p(bg), n, orr._p(pc), orr._p(col), orr._p(T),
-                   orr._p(nl), orr._p(am), orr._p(nc), None, None, 1e-4, 0, orr._p(ptr), orr._p(lst))
+                   orr._p(nl), orr._p(am), orr._p(nc), None, None, 1e-4, 0, orr._p(ptr), orr._p(lst), None)
 
     def loss(r):
         r = np.ascontiguousarray(r)
         L.oc_composite(60, orr._p(r), orr._p(trc), W, H, orr._p(bg), n, orr._p(pc), orr._p(col), orr._p(T),
-                       orr._p(nl), orr._p(am), orr._p(nc), None, None, 1e-4, 1, orr._p(ptr), orr._p(lst))
+                       orr._p(nl), orr._p(am), orr._p(nc), None, None, 1e-4, 1, orr._p(ptr), orr._p(lst), None)
         return float((col * gcol).sum())
 
     for i in rng.choice(60, 12, replace=False):
