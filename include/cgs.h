@@ -59,7 +59,8 @@ typedef enum {
     CGS_EUNSUPPORTED = -2,  /* valid but not supported by the library (e.g. sh_degree > 3) */
     CGS_ECAPACITY = -3,     /* instance capacity too small (device-side, via d_info) */
     CGS_EHIP = -4,          /* a HIP launch failed */
-    CGS_EWORKSPACE = -5     /* workspace too small */
+    CGS_EWORKSPACE = -5,    /* workspace too small */
+    CGS_ELIMIT = -6         /* sizes beyond the fixed scratch of cgs_codebook_grad_reduce_noalloc */
 } cgs_status;
 
 typedef enum { CGS_F32 = 0, CGS_BF16 = 1 } cgs_dtype;
@@ -315,6 +316,26 @@ size_t cgs_codebook_grad_reduce_workspace_bytes(int64_t n, int64_t k, int32_t d)
 cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* idx, const int32_t* perm,
                                     int64_t n, int64_t k, int32_t d, float* grad_cb, int64_t ld_out,
                                     void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reduction as cgs_codebook_grad_reduce, same arguments and the same kernels
+ * (so the same bits), with its workspace taken from a scratch array the
+ * library holds in device memory instead of a caller workspace.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * Limit: cgs_codebook_grad_reduce_workspace_bytes(n, k, d) must not exceed
+ * 32 MiB (about n = 1.9M Gaussians at k = 65536 rows); larger sizes return
+ * CGS_ELIMIT before any launch.  The scratch is one array per device, taken
+ * when the library is loaded there and held until the process ends; its
+ * address is looked up on the first call on each device (with that device
+ * current), which may return CGS_EHIP if the lookup fails.  Every call on a
+ * device shares that device's array and the array keeps what the last call
+ * left in it (everything the reduction needs zeroed it clears itself), so
+ * calls that overlap in time on one device -- on different streams or from
+ * different host threads -- race and must not be issued. */
+cgs_status cgs_codebook_grad_reduce_noalloc(const float* g, int64_t ld, const int32_t* idx, const int32_t* perm,
+                                            int64_t n, int64_t k, int32_t d, float* grad_cb, int64_t ld_out,
+                                            void* stream);
 
 /* Tile binning of the 3DGS tile renderer the paper builds on (Sec. 2.1):
  * every (Gaussian i, tile t in its rectangle) instance gets the key

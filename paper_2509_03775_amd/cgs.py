@@ -11,7 +11,7 @@ from ctypes import POINTER, c_float, c_int32, c_int64, c_size_t, c_void_p
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcgs.so")
 
-CGS_OK, CGS_EINVAL, CGS_EUNSUPPORTED, CGS_ECAPACITY, CGS_EHIP, CGS_EWORKSPACE = 0, -1, -2, -3, -4, -5
+CGS_OK, CGS_EINVAL, CGS_EUNSUPPORTED, CGS_ECAPACITY, CGS_EHIP, CGS_EWORKSPACE, CGS_ELIMIT = 0, -1, -2, -3, -4, -5, -6
 CGS_F32, CGS_BF16 = 0, 1
 MAX_VIEWS = MAX_SCENES = 64
 
@@ -20,7 +20,8 @@ EXPORTS = ("cgs_workspace_bytes", "cgs_render_forward", "cgs_render_backward",
            "cgs_bin_tiles_workspace_bytes", "cgs_bin_tiles", "cgs_loss_l1_workspace_bytes",
            "cgs_loss_l1", "cgs_workspace_layout", "cgs_status_str", "cgs_version", "cgs_sort_stalls",
            "cgs_render_backward_sgld", "cgs_sgld_normals", "cgs_loss_recon_workspace_bytes", "cgs_loss_recon",
-           "cgs_mh_workspace_bytes", "cgs_mh_split", "cgs_mh_merge", "cgs_mh_transition")
+           "cgs_mh_workspace_bytes", "cgs_mh_split", "cgs_mh_merge", "cgs_mh_transition",
+           "cgs_codebook_grad_reduce_noalloc")
 
 
 class Camera(ctypes.Structure):
@@ -115,6 +116,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.cgs_codebook_grad_reduce.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int64, c_int32,
                                            c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
     L.cgs_codebook_grad_reduce.restype = c_int32
+    L.cgs_codebook_grad_reduce_noalloc.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_int64, c_int32,
+                                                   c_void_p, c_int64, c_void_p]
+    L.cgs_codebook_grad_reduce_noalloc.restype = c_int32
     L.cgs_bin_tiles_workspace_bytes.argtypes = [c_int64, c_int32, c_int32, c_int32, c_int64]
     L.cgs_bin_tiles_workspace_bytes.restype = c_size_t
     L.cgs_bin_tiles.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p,
@@ -194,6 +198,11 @@ def codebook_grad_reduce_workspace_bytes(n: int, k: int, d: int) -> int:
 def codebook_grad_reduce(g, ld, idx, perm, n, k, d, grad_cb, ld_out, ws, ws_bytes, stream) -> None:
     check("cgs_codebook_grad_reduce", load().cgs_codebook_grad_reduce(g, ld, idx, perm, n, k, d, grad_cb, ld_out,
                                                                       ws, ws_bytes, stream))
+
+
+def codebook_grad_reduce_noalloc(g, ld, idx, perm, n, k, d, grad_cb, ld_out, stream) -> None:
+    check("cgs_codebook_grad_reduce_noalloc",
+          load().cgs_codebook_grad_reduce_noalloc(g, ld, idx, perm, n, k, d, grad_cb, ld_out, stream))
 
 
 def bin_tiles_workspace_bytes(n, tiles_x, tiles_y, n_views, capacity) -> int:

@@ -350,6 +350,29 @@ struct SideGuard {
     }
 };
 
+// Device scratch of cgs_codebook_grad_reduce_noalloc (its workspace): one
+// copy per device, loaded with the library's code and held until the process
+// ends.  Host code never passes `scratch` itself (on the host it is only a
+// stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+void* noalloc_scratch() {
+    static void* addr[64];
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
 }  // namespace
 }  // namespace cgs
 
@@ -369,6 +392,7 @@ const char* cgs_status_str(int32_t s) {
         case CGS_ECAPACITY: return "instance capacity exceeded";
         case CGS_EHIP: return "HIP launch failed";
         case CGS_EWORKSPACE: return "workspace too small";
+        case CGS_ELIMIT: return "sizes exceed the fixed device scratch of the allocation-free call";
         default: return "unknown status";
     }
 }
@@ -670,6 +694,17 @@ cgs_status cgs_codebook_grad_reduce(const float* g, int64_t ld, const int32_t* i
     CGS_TRY(tile_ranges(pk[pb], nullptr, n, k, rr, st));
     CGS_TRY(launch_reduce(dd, 0, g, ld, 0, d, 0, pk[pb], pv[pb], n, k, rr, st));
     return CGS_OK;
+}
+
+cgs_status cgs_codebook_grad_reduce_noalloc(const float* g, int64_t ld, const int32_t* idx, const int32_t* perm,
+                                            int64_t n, int64_t k, int32_t d, float* grad_cb, int64_t ld_out,
+                                            void* stream) {
+    const size_t need = cgs_codebook_grad_reduce_workspace_bytes(n, k, d);
+    if (need == 0) return CGS_EINVAL;
+    if (need > kNoAllocScratchBytes) return CGS_ELIMIT;
+    void* ws = noalloc_scratch();
+    if (!ws) return CGS_EHIP;
+    return cgs_codebook_grad_reduce(g, ld, idx, perm, n, k, d, grad_cb, ld_out, ws, kNoAllocScratchBytes, stream);
 }
 
 size_t cgs_bin_tiles_workspace_bytes(int64_t n, int32_t tiles_x, int32_t tiles_y, int32_t n_views, int64_t capacity) {

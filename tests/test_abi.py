@@ -112,6 +112,10 @@ def test_reduce_and_bin_validation():
     assert L.cgs_bin_tiles(0x1, 0x2, None, 10, 4, 4, 1, None, 0x3, 0x4, 100, None, 0x5, 1, None) == cgs.CGS_EWORKSPACE
     assert L.cgs_loss_l1(0x1, 0x2, -1, 0x3, 0x4, 0x5, 1 << 20, None) == cgs.CGS_EINVAL
     assert L.cgs_status_str(cgs.CGS_ECAPACITY) == b"instance capacity exceeded"
+    # the allocation-free reduction refuses, on the host, sizes beyond its fixed scratch
+    assert L.cgs_codebook_grad_reduce_noalloc(0x1, 4, 0x2, None, 10, 0, 4, 0x3, 4, None) == cgs.CGS_EINVAL
+    assert cgs.codebook_grad_reduce_workspace_bytes(2_100_000, 65536, 56) > 32 << 20
+    assert L.cgs_codebook_grad_reduce_noalloc(0x1, 56, 0x2, None, 2_100_000, 65536, 56, 0x3, 56, None) == cgs.CGS_ELIMIT
 
 
 def test_backward_sgld_validation():
