@@ -30,7 +30,7 @@ hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, con
                             const int32_t*, float*, uint2*, hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, int64_t, const float*, const uint32_t*, const uint32_t*,
                         const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*, float*,
-                        hipStream_t);
+                        uint32_t*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
@@ -56,7 +56,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
     size_t radix_ws, scan_bsum, scan_bsum2;
-    size_t slot_off, ginst, rec_grad, rec_flag, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t slot_off, ginst, rec_grad, rec_flag, isl_flag, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t scan_blocks_max;
 };
@@ -256,6 +256,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.ginst = take(4 * 9 * (size_t)cap);
     p.rec_grad = take(4 * 9 * (size_t)R);
     p.rec_flag = take(8 * (size_t)d.n_rec_waves + 8);
+    p.isl_flag = take(8 * (size_t)d.n_gauss_waves + 8);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
     p.row_start = take(8 * (size_t)(h->rows_total + 1));
@@ -602,7 +603,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.slot_off),
                          at<uint32_t>(ws, p.ntiles), at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key),
                          at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), at<uint32_t>(ws, p.rec_flag),
-                         gth, st));
+                         gth, at<uint32_t>(ws, p.isl_flag), st));
     CGS_TRY(mark(h, 6, st));
     const int nparts = single ? 1 : 2;
     for (int part_i = 0; part_i < nparts; ++part_i) {

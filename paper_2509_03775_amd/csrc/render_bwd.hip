@@ -428,13 +428,211 @@ struct ShRegs<CGS_BF16, SHD> {
     }
 };
 
+// fma in the arithmetic of the chain rule: FP32 for every Gaussian, FP64 for
+// the near-degenerate ones (below).
+__device__ inline float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fma_r(double a, double b, double c) { return fma(a, b, c); }
+
+// One view's projected-parameter gradient d = dL/d(u, v, -A/2, -B, -C/2,
+// opacity, r, g, b) pulled back through the conic (A, B, C) = Sigma2D^-1,
+// Sigma2D = T Sigma T^T (T = J W) and the perspective Jacobian to the camera
+// point and the mean: accumulates dL/dSigma (3x3) and dL/dmean.  In `Real`
+// arithmetic (the inputs -- the FP32 projection, shape and record gradient --
+// are exact in either).
+template <typename Real>
+__device__ inline void chain_geometry(const ViewDesc& vd, const ViewProj& p, const GaussShape& sh, Real A, Real B,
+                                      Real C, const float* d, Real (&dSig)[3][3], Real (&dmu)[3]) {
+    // conic (A, B, C) gradient from the stored (-A/2, -B, -C/2)
+    const Real dA = Real(-0.5f) * d[2], dB = -Real(d[3]), dC = Real(-0.5f) * d[4];
+    // dL/dSigma2D (symmetric-matrix gradient) = -K Gk K, Gk = [[dA, dB/2], [dB/2, dC]]
+    const Real hb = Real(0.5f) * dB;
+    const Real m00 = A * dA + B * hb, m01 = A * hb + B * dC;
+    const Real m10 = B * dA + C * hb, m11 = B * hb + C * dC;
+    const Real G00 = -(m00 * A + m01 * B);
+    const Real G01 = -(m00 * B + m01 * C);
+    const Real G11 = -(m10 * B + m11 * C);
+    // dSigma3D += T^T G T ; dT = 2 G T Sigma
+    Real GT[2][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        GT[0][j] = G00 * p.T[0][j] + G01 * p.T[1][j];
+        GT[1][j] = G01 * p.T[0][j] + G11 * p.T[1][j];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            dSig[i][j] = fma_r(Real(p.T[0][i]), GT[0][j], fma_r(Real(p.T[1][i]), GT[1][j], dSig[i][j]));
+    Real dT[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            dT[a][j] = Real(2.f) * (GT[a][0] * sh.S[0][j] + GT[a][1] * sh.S[1][j] + GT[a][2] * sh.S[2][j]);
+    // T = J W  ->  dJ = dT W^T (only the non-zero entries of J matter)
+    const float* Wm = vd.Rt;   // rows at 0, 4, 8
+    const Real dJ00 = dT[0][0] * Wm[0] + dT[0][1] * Wm[1] + dT[0][2] * Wm[2];
+    const Real dJ02 = dT[0][0] * Wm[8] + dT[0][1] * Wm[9] + dT[0][2] * Wm[10];
+    const Real dJ11 = dT[1][0] * Wm[4] + dT[1][1] * Wm[5] + dT[1][2] * Wm[6];
+    const Real dJ12 = dT[1][0] * Wm[8] + dT[1][1] * Wm[9] + dT[1][2] * Wm[10];
+    const Real iz = Real(1.f) / Real(p.zc), iz2 = iz * iz;
+    // camera-space gradient
+    Real gx = Real(d[0]) * vd.fx * iz;
+    Real gy = Real(d[1]) * vd.fy * iz;
+    Real gz = -(Real(d[0]) * vd.fx * p.xc + Real(d[1]) * vd.fy * p.yc) * iz2;
+    gz += -(dJ00 * vd.fx + dJ11 * vd.fy) * iz2;
+    if (!p.clx) {   // J02 = -fx x / z^2
+        gx += dJ02 * (-vd.fx * iz2);
+        gz += dJ02 * (Real(2.f) * vd.fx * p.xc * iz2 * iz);
+    } else {        // J02 = -fx txc / z, txc constant
+        gz += dJ02 * (Real(vd.fx) * p.txc * iz2);
+    }
+    if (!p.cly) {
+        gy += dJ12 * (-vd.fy * iz2);
+        gz += dJ12 * (Real(2.f) * vd.fy * p.yc * iz2 * iz);
+    } else {
+        gz += dJ12 * (Real(vd.fy) * p.tyc * iz2);
+    }
+    // x_c = W mu + t  ->  dmu += W^T dx_c
+    dmu[0] += Wm[0] * gx + Wm[4] * gy + Wm[8] * gz;
+    dmu[1] += Wm[1] * gx + Wm[5] * gy + Wm[9] * gz;
+    dmu[2] += Wm[2] * gx + Wm[6] * gy + Wm[10] * gz;
+}
+
+// One view's colour gradient: c = max(0, sum Y k + 1/2) with Y of the unit
+// direction camera -> mean.  Accumulates dL/dk into dk and, for SH degree >= 1,
+// writes the direction's contribution to dL/dmean into gdir.
+template <int DT, int SHD>
+__device__ inline void chain_colour(const ViewDesc& vd, const GaussParams& gp, ShRegs<DT, SHD>& shc, const float* d,
+                                    float* dk, float* gdir) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+        shc.pin();
+        float ex = gp.mean[0] - vd.campos[0], ey = gp.mean[1] - vd.campos[1], ez = gp.mean[2] - vd.campos[2];
+        const float il = rsqrtf(ex * ex + ey * ey + ez * ez);
+        const float x = ex * il, y = ey * il, z = ez * il;
+        float Y[16];
+        sh_basis<SHD>(x, y, z, Y);
+        float dcol[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], shc[3 * j + ch], acc);
+            dcol[ch] = acc > 0.f ? d[6 + ch] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < NCO; ++j)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) dk[3 * j + ch] = fmaf(Y[j], dcol[ch], dk[3 * j + ch]);
+        if constexpr (SHD >= 1) {
+            shc.pin();
+            float e[16];
+#pragma unroll
+            for (int j = 0; j < NCO; ++j)
+                e[j] = dcol[0] * shc[3 * j] + dcol[1] * shc[3 * j + 1] + dcol[2] * shc[3 * j + 2];
+            float qx = -kY1 * e[3], qy = -kY1 * e[1], qz = kY1 * e[2];
+            if constexpr (SHD >= 2) {
+                qx += kY2a * y * e[4] - kY2a * z * e[7] - 2.f * kY2b * x * e[6] + 2.f * kY2c * x * e[8];
+                qy += kY2a * x * e[4] - kY2a * z * e[5] - 2.f * kY2b * y * e[6] - 2.f * kY2c * y * e[8];
+                qz += -kY2a * y * e[5] - kY2a * x * e[7] + 4.f * kY2b * z * e[6];
+                if constexpr (SHD >= 3) {
+                    const float xx = x * x, yy = y * y, zz = z * z;
+                    qx += -kY3a * 6.f * x * y * e[9] + kY3b * y * z * e[10] + kY3c * 2.f * x * y * e[11]
+                          - kY3d * 6.f * x * z * e[12] - kY3c * (4.f * zz - 3.f * xx - yy) * e[13]
+                          + kY3e * 2.f * x * z * e[14] - kY3a * (3.f * xx - 3.f * yy) * e[15];
+                    qy += -kY3a * (3.f * xx - 3.f * yy) * e[9] + kY3b * x * z * e[10]
+                          - kY3c * (4.f * zz - xx - 3.f * yy) * e[11] - kY3d * 6.f * y * z * e[12]
+                          + kY3c * 2.f * x * y * e[13] - kY3e * 2.f * y * z * e[14] + kY3a * 6.f * x * y * e[15];
+                    qz += kY3b * x * y * e[10] - kY3c * 8.f * y * z * e[11]
+                          + kY3d * (6.f * zz - 3.f * xx - 3.f * yy) * e[12] - kY3c * 8.f * x * z * e[13]
+                          + kY3e * (xx - yy) * e[14];
+                }
+            }
+            // through the normalisation dir = e / |e|
+            const float dd = qx * x + qy * y + qz * z;
+            gdir[0] = (qx - x * dd) * il;
+            gdir[1] = (qy - y * dd) * il;
+            gdir[2] = (qz - z * dd) * il;
+        }
+}
+
+// Sigma = M M^T -> dM = (G + G^T) M with M = R diag(s): dL/ds and, through
+// R(q) and the normalisation of q, dL/dq (stored quaternion).
+template <typename Real>
+__device__ inline void chain_shape(const Real (&dSig)[3][3], const GaussShape& sh, Real (&ds)[3], Real (&dq)[4]) {
+    Real dR[3][3];
+    ds[0] = ds[1] = ds[2] = Real(0.f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const Real dM = (dSig[i][0] + dSig[0][i]) * sh.M[0][j] + (dSig[i][1] + dSig[1][i]) * sh.M[1][j] +
+                            (dSig[i][2] + dSig[2][i]) * sh.M[2][j];
+            dR[i][j] = dM * sh.s[j];
+            ds[j] = fma_r(dM, Real(sh.R[i][j]), ds[j]);
+        }
+    const Real w = sh.qn[0], x = sh.qn[1], y = sh.qn[2], z = sh.qn[3];
+    const Real two = Real(2.f);
+    Real dqw = two * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
+    Real dqx = two * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - two * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
+                      w * dR[2][1] - two * x * dR[2][2]);
+    Real dqy = two * (-two * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
+                      z * dR[2][1] - two * y * dR[2][2]);
+    Real dqz = two * (-two * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - two * z * dR[1][1] +
+                      y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+    dq[0] = dq[1] = dq[2] = dq[3] = Real(0.f);
+    if (sh.qlen > 0.f) {
+        const Real proj = dqw * w + dqx * x + dqy * y + dqz * z;
+        const Real il = Real(1.f) / Real(sh.qlen);
+        dq[0] = (dqw - w * proj) * il;
+        dq[1] = (dqx - x * proj) * il;
+        dq[2] = (dqy - y * proj) * il;
+        dq[3] = (dqz - z * proj) * il;
+    }
+}
+
+// Writes one Gaussian's gradients: the row [dls 3, dq 4, dlogit 1, dsh 3 NCO]
+// (16-byte stores when the row is a whole number of float4s), dL/dmean and,
+// for per-Gaussian opacity, dL/dlogit.
+template <int SHD>
+__device__ inline void store_gaussian_grad(const SceneDesc& sd, float* out, int64_t g, const float* dls,
+                                           const float* dq, float dlogit, const float* dk, const float* dmu) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    if constexpr ((8 + 3 * NCO) % 4 == 0) {     // row is a whole number of float4s (16-byte aligned)
+        float4* o4 = reinterpret_cast<float4*>(out);
+        o4[0] = make_float4(dls[0], dls[1], dls[2], dq[0]);
+        o4[1] = make_float4(dq[1], dq[2], dq[3], dlogit);
+#pragma unroll
+        for (int i = 0; i < (3 * NCO) / 4; ++i)
+            o4[2 + i] = make_float4(dk[4 * i], dk[4 * i + 1], dk[4 * i + 2], dk[4 * i + 3]);
+    } else {
+        out[0] = dls[0];
+        out[1] = dls[1];
+        out[2] = dls[2];
+        out[3] = dq[0]; out[4] = dq[1]; out[5] = dq[2]; out[6] = dq[3];
+        out[7] = dlogit;
+#pragma unroll
+        for (int i = 0; i < 3 * NCO; ++i) out[8 + i] = dk[i];
+    }
+    if (sd.g_means) {
+        sd.g_means[3 * g + 0] = dmu[0];
+        sd.g_means[3 * g + 1] = dmu[1];
+        sd.g_means[3 * g + 2] = dmu[2];
+    }
+    if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
+}
+
 // One thread per Gaussian: recompute the projection of every view of its
 // scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
-// the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].
+// the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].  A
+// Gaussian whose footprint took the FP64 conic in some view (near-degenerate,
+// very elongated) is marked in isl_flag (a bit per Gaussian, two words per
+// wavefront, zeroed before the launch): k_chain_fp64 redoes its chain rule in
+// FP64 and overwrites what this kernel wrote, and applies its SGLD update.
 template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ rec_grad,
                                                const uint32_t* __restrict__ rec_flag,
-                                               float* __restrict__ gtheta) {
+                                               float* __restrict__ gtheta, uint32_t* __restrict__ isl_flag) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
@@ -484,6 +682,7 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
     };
     if (sd.vcount > 0) load_rec(0, dn);
 
+    bool isl = false;
     for (int vi = 0; vi < sd.vcount; ++vi) {
         const int v = desc->view_list[sd.vfirst + vi];
         const ViewDesc& vd = desc->views[v];
@@ -498,112 +697,17 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         ViewProj p;
         if (!project_view(vd, gp.mean, sh, p)) continue;
         float A, B, C;
-        conic_of(p.a, p.b, p.c, A, B, C);
+        isl |= conic_of(p.a, p.b, p.c, A, B, C);
         dop += d[5];
-        // conic (A, B, C) gradient from the stored (-A/2, -B, -C/2)
-        const float dA = -0.5f * d[2], dB = -d[3], dC = -0.5f * d[4];
-        // dL/dSigma2D (symmetric-matrix gradient) = -K Gk K, Gk = [[dA, dB/2], [dB/2, dC]]
-        const float hb = 0.5f * dB;
-        const float m00 = A * dA + B * hb, m01 = A * hb + B * dC;
-        const float m10 = B * dA + C * hb, m11 = B * hb + C * dC;
-        const float G00 = -(m00 * A + m01 * B);
-        const float G01 = -(m00 * B + m01 * C);
-        const float G11 = -(m10 * B + m11 * C);
-        // dSigma3D += T^T G T ; dT = 2 G T Sigma
-        float GT[2][3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            GT[0][j] = G00 * p.T[0][j] + G01 * p.T[1][j];
-            GT[1][j] = G01 * p.T[0][j] + G11 * p.T[1][j];
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) dSig[i][j] = fmaf(p.T[0][i], GT[0][j], fmaf(p.T[1][i], GT[1][j], dSig[i][j]));
-        float dT[2][3];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                dT[a][j] = 2.f * (GT[a][0] * sh.S[0][j] + GT[a][1] * sh.S[1][j] + GT[a][2] * sh.S[2][j]);
-        // T = J W  ->  dJ = dT W^T (only the non-zero entries of J matter)
-        const float* Wm = vd.Rt;   // rows at 0, 4, 8
-        const float dJ00 = dT[0][0] * Wm[0] + dT[0][1] * Wm[1] + dT[0][2] * Wm[2];
-        const float dJ02 = dT[0][0] * Wm[8] + dT[0][1] * Wm[9] + dT[0][2] * Wm[10];
-        const float dJ11 = dT[1][0] * Wm[4] + dT[1][1] * Wm[5] + dT[1][2] * Wm[6];
-        const float dJ12 = dT[1][0] * Wm[8] + dT[1][1] * Wm[9] + dT[1][2] * Wm[10];
-        const float iz = 1.f / p.zc, iz2 = iz * iz;
-        // camera-space gradient
-        float gx = d[0] * vd.fx * iz;
-        float gy = d[1] * vd.fy * iz;
-        float gz = -(d[0] * vd.fx * p.xc + d[1] * vd.fy * p.yc) * iz2;
-        gz += -(dJ00 * vd.fx + dJ11 * vd.fy) * iz2;
-        if (!p.clx) {   // J02 = -fx x / z^2
-            gx += dJ02 * (-vd.fx * iz2);
-            gz += dJ02 * (2.f * vd.fx * p.xc * iz2 * iz);
-        } else {        // J02 = -fx txc / z, txc constant
-            gz += dJ02 * (vd.fx * p.txc * iz2);
-        }
-        if (!p.cly) {
-            gy += dJ12 * (-vd.fy * iz2);
-            gz += dJ12 * (2.f * vd.fy * p.yc * iz2 * iz);
+        chain_geometry<float>(vd, p, sh, A, B, C, d, dSig, dmu);
+        if constexpr (SHD >= 1) {
+            float gdir[3];
+            chain_colour<DT, SHD>(vd, gp, shc, d, dk, gdir);
+            dmu[0] += gdir[0];
+            dmu[1] += gdir[1];
+            dmu[2] += gdir[2];
         } else {
-            gz += dJ12 * (vd.fy * p.tyc * iz2);
-        }
-        // x_c = W mu + t  ->  dmu += W^T dx_c
-        dmu[0] += Wm[0] * gx + Wm[4] * gy + Wm[8] * gz;
-        dmu[1] += Wm[1] * gx + Wm[5] * gy + Wm[9] * gz;
-        dmu[2] += Wm[2] * gx + Wm[6] * gy + Wm[10] * gz;
-        // colour: c = max(0, sum Y k + 1/2), Y of the unit direction camera -> mean
-        {
-            shc.pin();
-            float ex = gp.mean[0] - vd.campos[0], ey = gp.mean[1] - vd.campos[1], ez = gp.mean[2] - vd.campos[2];
-            const float il = rsqrtf(ex * ex + ey * ey + ez * ez);
-            const float x = ex * il, y = ey * il, z = ez * il;
-            float Y[16];
-            sh_basis<SHD>(x, y, z, Y);
-            float dcol[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float acc = 0.5f;
-#pragma unroll
-                for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], shc[3 * j + ch], acc);
-                dcol[ch] = acc > 0.f ? d[6 + ch] : 0.f;
-            }
-#pragma unroll
-            for (int j = 0; j < NCO; ++j)
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) dk[3 * j + ch] = fmaf(Y[j], dcol[ch], dk[3 * j + ch]);
-            if constexpr (SHD >= 1) {
-                shc.pin();
-                float e[16];
-#pragma unroll
-                for (int j = 0; j < NCO; ++j)
-                    e[j] = dcol[0] * shc[3 * j] + dcol[1] * shc[3 * j + 1] + dcol[2] * shc[3 * j + 2];
-                float qx = -kY1 * e[3], qy = -kY1 * e[1], qz = kY1 * e[2];
-                if constexpr (SHD >= 2) {
-                    qx += kY2a * y * e[4] - kY2a * z * e[7] - 2.f * kY2b * x * e[6] + 2.f * kY2c * x * e[8];
-                    qy += kY2a * x * e[4] - kY2a * z * e[5] - 2.f * kY2b * y * e[6] - 2.f * kY2c * y * e[8];
-                    qz += -kY2a * y * e[5] - kY2a * x * e[7] + 4.f * kY2b * z * e[6];
-                    if constexpr (SHD >= 3) {
-                        const float xx = x * x, yy = y * y, zz = z * z;
-                        qx += -kY3a * 6.f * x * y * e[9] + kY3b * y * z * e[10] + kY3c * 2.f * x * y * e[11]
-                              - kY3d * 6.f * x * z * e[12] - kY3c * (4.f * zz - 3.f * xx - yy) * e[13]
-                              + kY3e * 2.f * x * z * e[14] - kY3a * (3.f * xx - 3.f * yy) * e[15];
-                        qy += -kY3a * (3.f * xx - 3.f * yy) * e[9] + kY3b * x * z * e[10]
-                              - kY3c * (4.f * zz - xx - 3.f * yy) * e[11] - kY3d * 6.f * y * z * e[12]
-                              + kY3c * 2.f * x * y * e[13] - kY3e * 2.f * y * z * e[14] + kY3a * 6.f * x * y * e[15];
-                        qz += kY3b * x * y * e[10] - kY3c * 8.f * y * z * e[11]
-                              + kY3d * (6.f * zz - 3.f * xx - 3.f * yy) * e[12] - kY3c * 8.f * x * z * e[13]
-                              + kY3e * (xx - yy) * e[14];
-                    }
-                }
-                // through the normalisation dir = e / |e|
-                const float dd = qx * x + qy * y + qz * z;
-                dmu[0] += (qx - x * dd) * il;
-                dmu[1] += (qy - y * dd) * il;
-                dmu[2] += (qz - z * dd) * il;
-            }
+            chain_colour<DT, SHD>(vd, gp, shc, d, dk, nullptr);
         }
     }
     // the shape again (bitwise the same) rather than R, M held across the loop
@@ -612,58 +716,89 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
 #pragma unroll
     for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(gp.q[i]));
     gaussian_shape(gp, sh);
-    // Sigma = M M^T -> dM = (G + G^T) M ; M = R diag(s)
-    float dR[3][3], ds[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const float dM = (dSig[i][0] + dSig[0][i]) * sh.M[0][j] + (dSig[i][1] + dSig[1][i]) * sh.M[1][j] +
-                             (dSig[i][2] + dSig[2][i]) * sh.M[2][j];
-            dR[i][j] = dM * sh.s[j];
-            ds[j] = fmaf(dM, sh.R[i][j], ds[j]);
-        }
-    const float w = sh.qn[0], x = sh.qn[1], y = sh.qn[2], z = sh.qn[3];
-    float dqw = 2.f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] + x * dR[2][1]);
-    float dqx = 2.f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.f * x * dR[1][1] - w * dR[1][2] + z * dR[2][0] +
-                       w * dR[2][1] - 2.f * x * dR[2][2]);
-    float dqy = 2.f * (-2.f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] - w * dR[2][0] +
-                       z * dR[2][1] - 2.f * y * dR[2][2]);
-    float dqz = 2.f * (-2.f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] - 2.f * z * dR[1][1] +
-                       y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
-    float dq[4] = {0.f, 0.f, 0.f, 0.f};
-    if (sh.qlen > 0.f) {
-        const float proj = dqw * w + dqx * x + dqy * y + dqz * z;
-        const float il = 1.f / sh.qlen;
-        dq[0] = (dqw - w * proj) * il;
-        dq[1] = (dqx - x * proj) * il;
-        dq[2] = (dqy - y * proj) * il;
-        dq[3] = (dqz - z * proj) * il;
-    }
+    float ds[3], dq[4];
+    chain_shape<float>(dSig, sh, ds, dq);
     const float dlogit = dop * opac * (1.f - opac);
-    if constexpr ((8 + 3 * NCO) % 4 == 0) {     // row is a whole number of float4s (16-byte aligned)
-        float4* o4 = reinterpret_cast<float4*>(out);
-        o4[0] = make_float4(ds[0] * sh.s[0], ds[1] * sh.s[1], ds[2] * sh.s[2], dq[0]);
-        o4[1] = make_float4(dq[1], dq[2], dq[3], dlogit);
+    const float dls[3] = {ds[0] * sh.s[0], ds[1] * sh.s[1], ds[2] * sh.s[2]};
+    store_gaussian_grad<SHD>(sd, out, g, dls, dq, dlogit, dk, dmu);
+    if (isl) atomicOr(&isl_flag[2 * wv + ((threadIdx.x & 63) >> 5)], 1u << (threadIdx.x & 31));
+    else if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmu, dlogit);
+}
+
+// The chain rule of the Gaussians k_chain marked, in FP64 from the conic on:
+// the conic is the FP64 inverse of the FP32 Sigma2D (the forward's island),
+// and dL/dSigma2D = -K Gk K, dL/dSigma, dL/dmean through the Jacobian and
+// dL/d(s, q) are carried in FP64.  For such a footprint the rotation's share
+// of dL/dSigma2D is about 1e-3 of its largest entry, below what FP32 keeps.
+// One thread per flag word; its set bits are processed in order.
+template <int DT, int SHD>
+__global__ __launch_bounds__(256) void k_chain_fp64(const BatchDesc* __restrict__ desc,
+                                                    const float* __restrict__ rec_grad,
+                                                    const uint32_t* __restrict__ rec_flag, float* __restrict__ gtheta,
+                                                    const uint32_t* __restrict__ isl_flag) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= 2 * desc->n_gauss_waves) return;
+    uint32_t bits = isl_flag[w];
+    if (!bits) return;
+    const int64_t wv = w >> 1;
+    const int s = find_scene_by_wave(desc, wv);
+    const SceneDesc& sd = desc->scenes[s];
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1;
+        const int64_t g = (wv - sd.wave_off) * kWave + 32 * (w & 1) + b;
+        if (g >= sd.n) break;
+        GaussParams gp;
+        if (!load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0)) continue;
+        GaussShape sh;
+        gaussian_shape(gp, sh);
+        const float opac = 1.0f / (1.0f + __expf(-gp.logit));
+        ShRegs<DT, SHD> shc;
+        shc.load(sd, g, gp, desc->vec_rows != 0);
+        double dmu[3] = {0.0, 0.0, 0.0};
+        double dSig[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+        float dk[48];
 #pragma unroll
-        for (int i = 0; i < (3 * NCO) / 4; ++i)
-            o4[2 + i] = make_float4(dk[4 * i], dk[4 * i + 1], dk[4 * i + 2], dk[4 * i + 3]);
-    } else {
-        out[0] = ds[0] * sh.s[0];
-        out[1] = ds[1] * sh.s[1];
-        out[2] = ds[2] * sh.s[2];
-        out[3] = dq[0]; out[4] = dq[1]; out[5] = dq[2]; out[6] = dq[3];
-        out[7] = dlogit;
+        for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
+        float dop = 0.f;
+        for (int vi = 0; vi < sd.vcount; ++vi) {
+            const ViewDesc& vd = desc->views[desc->view_list[sd.vfirst + vi]];
+            const int64_t fw = 2 * (vd.rec_wave_off + (g >> 6)) + ((g >> 5) & 1);
+            if (!((rec_flag[fw] >> (g & 31)) & 1u)) continue;
+            float d[9];
+            const float* src = rec_grad + 9 * (vd.rec_off + g);
 #pragma unroll
-        for (int i = 0; i < 3 * NCO; ++i) out[8 + i] = dk[i];
+            for (int i = 0; i < 9; ++i) d[i] = src[i];
+            bool nz = false;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) nz |= d[i] != 0.f;
+            if (!nz) continue;
+            ViewProj p;
+            if (!project_view(vd, gp.mean, sh, p)) continue;
+            double A, B, C;
+            conic_of_f64(p.a, p.b, p.c, A, B, C);
+            dop += d[5];
+            chain_geometry<double>(vd, p, sh, A, B, C, d, dSig, dmu);
+            if constexpr (SHD >= 1) {
+                float gdir[3];
+                chain_colour<DT, SHD>(vd, gp, shc, d, dk, gdir);
+                dmu[0] += gdir[0];
+                dmu[1] += gdir[1];
+                dmu[2] += gdir[2];
+            } else {
+                chain_colour<DT, SHD>(vd, gp, shc, d, dk, nullptr);
+            }
+        }
+        double ds[3], dq[4];
+        chain_shape<double>(dSig, sh, ds, dq);
+        const float dlogit = dop * opac * (1.f - opac);
+        const float dls[3] = {(float)(ds[0] * sh.s[0]), (float)(ds[1] * sh.s[1]), (float)(ds[2] * sh.s[2])};
+        const float dqf[4] = {(float)dq[0], (float)dq[1], (float)dq[2], (float)dq[3]};
+        const float dmuf[3] = {(float)dmu[0], (float)dmu[1], (float)dmu[2]};
+        store_gaussian_grad<SHD>(sd, gtheta + (sd.g_off + g) * desc->row_width, g, dls, dqf, dlogit, dk, dmuf);
+        if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmuf, dlogit);
     }
-    if (sd.g_means) {
-        sd.g_means[3 * g + 0] = dmu[0];
-        sd.g_means[3 * g + 1] = dmu[1];
-        sd.g_means[3 * g + 2] = dmu[2];
-    }
-    if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
-    if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmu, dlogit);
 }
 
 // ------------------------------------------------- codebook row reduction
@@ -869,13 +1004,21 @@ hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, c
 hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, int64_t n_rec_waves,
                         const float* ginst, const uint32_t* eo, const uint32_t* nt, const uint2* tr, const uint32_t* dk,
                         const uint2* cut, const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, float* gtheta,
-                        hipStream_t st) {
+                        uint32_t* isl_flag, hipStream_t st) {
     if (n_rec_waves > 0)
         hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
                            nt, tr, dk, cut, cnt, rec_grad, rec_flag);
     if (n_gauss_waves <= 0) return hipGetLastError();
+    hipError_t e = fill_u32(isl_flag, 0u, (size_t)(2 * n_gauss_waves), st);
+    if (e != hipSuccess) return e;
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_CH(DT, SHD) hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta)
+    dim3 grid64((unsigned)((2 * n_gauss_waves + 255) / 256));
+#define CGS_CH(DT, SHD)                                                                                     \
+    do {                                                                                                    \
+        hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta, isl_flag); \
+        hipLaunchKernelGGL((k_chain_fp64<DT, SHD>), grid64, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta,      \
+                           isl_flag);                                                                       \
+    } while (0)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_CH(CGS_F32, 0); break; case 1: CGS_CH(CGS_F32, 1); break;
                        case 2: CGS_CH(CGS_F32, 2); break; default: CGS_CH(CGS_F32, 3); break; }

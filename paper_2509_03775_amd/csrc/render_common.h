@@ -269,18 +269,28 @@ __device__ inline bool project_view(const ViewDesc& vd, const float* mu, const G
 
 // Conic = inverse of [[a, b], [b, c]].  The FP32 determinant loses the
 // leading digits when the footprint is very elongated (a c ~ b^2); then
-// determinant and inverse are taken in FP64.
-__device__ inline void conic_of(float a, float b, float c, float& A, float& B, float& C) {
+// determinant and inverse are taken in FP64.  Returns true in that case (a
+// near-degenerate footprint).
+__device__ inline bool conic_of(float a, float b, float c, float& A, float& B, float& C) {
     const float det = a * c - b * b;
     if (det > 0x1p-10f * (a * c)) {
         const float id = 1.0f / det;
         A = c * id; B = -b * id; C = a * id;
-    } else {
-        const double da = a, db = b, dc = c;
-        const double dd = da * dc - db * db;
-        const double id = 1.0 / dd;
-        A = (float)(dc * id); B = (float)(-db * id); C = (float)(da * id);
+        return false;
     }
+    const double da = a, db = b, dc = c;
+    const double dd = da * dc - db * db;
+    const double id = 1.0 / dd;
+    A = (float)(dc * id); B = (float)(-db * id); C = (float)(da * id);
+    return true;
+}
+
+// The FP64 inverse itself (for the FP64 chain rule of near-degenerate
+// footprints).
+__device__ inline void conic_of_f64(float a, float b, float c, double& A, double& B, double& C) {
+    const double da = a, db = b, dc = c;
+    const double id = 1.0 / (da * dc - db * db);
+    A = dc * id; B = -db * id; C = da * id;
 }
 
 // ---------------------------------------------------------------- colour

@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_2509_03775_amd import cgs, render, scenes as sc
-from harness import (GRAD_TOL, IMAGE_TOL, compare_view, full_pixels, grad_error_stats, grad_errors,
+from harness import (BLOCKS, GRAD_TOL, IMAGE_TOL, compare_view, full_pixels, grad_error_stats, grad_errors,
                      oracle_grad_image, oracle_render, oracle_scene_grads, record, rel_l2, say)
 
 pytestmark = pytest.mark.gpu
@@ -402,16 +402,31 @@ def test_needle_gaussians_fp64_island():
     that every needle has det <= 0.7 * 2^-10 a c (inside the island with room
     for FP32 rounding of a, b, c), then compares the image and gradients.
 
-    Bounds: the island removes the cancellation in the determinant but not
-    the rounding already in the FP32 a, b, c, nor the FP32 storage of the
-    conic; inverting a matrix of condition number kappa = lambda_max /
-    lambda_min amplifies relative rounding by kappa, so the alpha of a pixel
-    a needle covers may be off by about kappa u (u = 2^-24).  Pixels whose
-    tile lies in a needle's rectangle are held to 1e-4 + 2^-23 kappa, the
-    largest kappa among those needles; every other pixel to 1e-4.  Gradients:
-    the background Gaussians' blocks to 1e-3, each needle's codebook row and
-    mean to 2^-20 kappa relative L2.  The measured errors are printed."""
+    Error model (the known limit of the island: it removes the cancellation
+    in the determinant, not the rounding already in the FP32 a, b, c).  a, b, c
+    come out of an FP32 chain of about 40 roundings (quaternion, rotation,
+    R S, Sigma, J W Sigma W^T J^T); by the probabilistic rounding-error bound
+    (Higham and Mary, SIAM J. Sci. Comput. 41, 2019) their error is about
+    sqrt(40) u relative to lambda_max, taken as EPS = 8u = 2^-21 (u = 2^-24).
+    The determinant, the FP32 conic entries and the FP32 quadratic form along
+    the needle each turn that into a relative error of the power of about
+    kappa EPS (2 + 3 + 1 terms; kappa = lambda_max / lambda_min of Sigma2D):
+    |d power| <= 6 kappa EPS |power|.  Hence, per needle:
+      - alpha's decision against 1/255 (|power| <= ln(255 * 0.99)) is
+        ambiguous within a relative margin of 6 ln(252.45) kappa EPS, passed
+        to the oracle as that Gaussian's margin (it also widens every
+        transmittance test after it);
+      - alpha's error is <= 6 kappa EPS max_p(o e^p |p|) <= 2.21 kappa EPS, and
+        colour and T move by at most that (|c - behind| <= 1 here): pixels of
+        tiles in needle rectangles are held to 1e-4 + sum over those needles
+        of 3 kappa EPS, every other pixel to 1e-4;
+      - a needle's gradient (a sum of per-pixel terms each off by at most
+        6 kappa EPS |power| <= 33 kappa EPS, plus 2 kappa EPS through the
+        derivative of the inverse) to 36 kappa EPS relative L2; the
+        background Gaussians' blocks to 1e-3.
+    The measured errors are printed and recorded."""
     say("[needles] FP64 determinant island")
+    EPS = 2.0 ** -21
     s = sc.needle_scene(5)
     cam = sc.pinhole(320, 240, (0.0, 0.0, -3.0))
     rng = np.random.default_rng(31)
@@ -427,38 +442,44 @@ def test_needle_gaussians_fp64_island():
     lam = np.linalg.eigvalsh(S2)
     kappa = lam[:, 1] / lam[:, 0]
     say("  det/(ac): " + " ".join(f"{x:.1e}" for x in ratio))
+    say("  kappa: " + " ".join(f"{x:.0f}" for x in kappa))
     assert (ratio <= 0.7 * 2.0 ** -10).all()
     # per-pixel bound from the needles whose tile rectangle holds the pixel
     _, trect, kept = oracle.keyspec(s.means[nd], rows[nd, :7].astype(np.float32), cam)
     assert kept.all()
     W, H = cam.width, cam.height
-    tol = np.full((H, W), IMAGE_TOL)
-    kmax = np.zeros((H, W))
+    ksum = np.zeros((H, W))
     for i in range(n_needle):
         x0, y0, x1, y1 = (int(t) for t in trect[i])
-        blk = kmax[16 * y0:16 * y1, 16 * x0:16 * x1]
-        np.maximum(blk, kappa[i], out=blk)
-    tol += 2.0 ** -23 * kmax
+        ksum[16 * y0:16 * y1, 16 * x0:16 * x1] += kappa[i]
+    tol = IMAGE_TOL + 3.0 * EPS * ksum
+    rec_margin = np.zeros(s.n)
+    rec_margin[nd] = 6.0 * np.log(255.0 * 0.99) * kappa * EPS
     r = gpu_renderer(wl)
     r.forward()
     torch.cuda.synchronize()
     pix = full_pixels(cam)
-    base = oracle_render(wl, [pix])[0]
+    base = oracle.render_view(s, cam, pix, rec_margin=rec_margin)
     img = r.image.cpu().numpy().astype(np.float64)
     err = np.abs(img - base["color"]).max(1)
+    terr = np.abs(r.T_final.cpu().numpy().astype(np.float64) - base["T"])
     ok = ~base["ambiguous"]
     t_flat = tol.ravel()
-    in_needle = kmax.ravel() > 0
+    in_needle = ksum.ravel() > 0
     nl = r.n_last.cpu().numpy()
+    mism = int((nl[ok] != base["n_last"][ok]).sum())
+    worst_img = float((err[ok] / t_flat[ok]).max())
     say(f"  image: max err off needles {err[ok & ~in_needle].max():.2e}, on needles {err[ok & in_needle].max():.2e} "
         f"(bound there {t_flat[ok & in_needle].min():.2e}..{t_flat[ok & in_needle].max():.2e}), "
-        f"max err / bound {(err[ok] / t_flat[ok]).max():.2f}, n_last mismatches {(nl[ok] != base['n_last'][ok]).sum()}, "
-        f"ambiguous {(~ok).sum()}")
+        f"max err / bound {worst_img:.3f}, T max err / bound {(terr[ok] / t_flat[ok]).max():.3f}, "
+        f"n_last mismatches {mism}, ambiguous {(~ok).sum()} of {len(pix)}")
     assert (err[ok] <= t_flat[ok]).all()
-    assert (~ok).sum() <= 0.01 * len(pix)
+    assert (terr[ok] <= t_flat[ok]).all()
+    assert mism == 0
+    assert (~ok).sum() <= 0.02 * len(pix)
     # gradients
     gcols, gfull = oracle_grad_image(wl, [pix], [base])
-    outs = oracle_render(wl, [pix], gcols)
+    outs = [oracle.render_view(s, cam, pix, grad_color=gcols[0], rec_margin=rec_margin)]
     ogm, ogcb = oracle_scene_grads(wl, outs)
     gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
     torch.cuda.synchronize()
@@ -469,11 +490,21 @@ def test_needle_gaussians_fp64_island():
     for k, e in bg_err.items():
         assert e <= GRAD_TOL, (k, e)
     worst = 0.0
+    needle_errs = []
     for i in range(n_needle):
         er = rel_l2(gcb[kb + i], ogcb[0][kb + i])
         em = rel_l2(gm[nd[i]], ogm[0][nd[i]])
-        bound = 2.0 ** -20 * kappa[i]
+        bound = 36.0 * EPS * kappa[i]
         worst = max(worst, max(er, em) / bound)
-        say(f"  needle {i}: kappa {kappa[i]:.0f} row rel err {er:.2e} mean rel err {em:.2e} (bound {bound:.2e})")
+        needle_errs.append((float(kappa[i]), er, em))
+        blk = " ".join(f"{k}={rel_l2(gcb[kb + i][sl], ogcb[0][kb + i][sl]):.1e}"
+                       for k, sl in BLOCKS.items() if ogcb[0][kb + i][sl].size)
+        say(f"  needle {i}: kappa {kappa[i]:.0f} row rel err {er:.2e} mean rel err {em:.2e} (bound {bound:.2e}) [{blk}]")
         assert er <= bound and em <= bound, (i, er, em, bound)
+    record("needles_fp64_island", kappa_min=float(kappa.min()), kappa_max=float(kappa.max()),
+           det_ratio_max=float(ratio.max()), image_err_needle=float(err[ok & in_needle].max()),
+           image_err_other=float(err[ok & ~in_needle].max()), image_err_over_bound=worst_img,
+           ambiguous=int((~ok).sum()), pixels=len(pix),
+           row_rel_l2_max=max(e[1] for e in needle_errs), mean_rel_l2_max=max(e[2] for e in needle_errs),
+           grad_err_over_bound=worst, background=bg_err)
     say(f"  needle gradients: worst error / bound {worst:.2f}")
