@@ -14,7 +14,7 @@ namespace cgs {
 
 // launchers defined in the other translation units
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*, uint32_t*,
-                             hipStream_t);
+                             uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
                        const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
@@ -56,7 +56,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
     size_t radix_ws, scan_bsum, scan_bsum2;
-    size_t slot_off, ginst, rec_grad, rec_flag, isl_flag, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t chunk_tot, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t scan_blocks_max;
 };
@@ -252,7 +252,8 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.scan_blocks_max = (int64_t)scan_bsum_count(nmax);
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
     p.scan_bsum2 = take(8 * (size_t)p.scan_blocks_max);
-    p.slot_off = take(4 * (size_t)R);
+    p.chunk_tot = take(4 * (size_t)d.n_rec_waves + 4);
+    p.chunk_base = take(4 * (size_t)d.n_rec_waves + 4);
     p.ginst = take(4 * 9 * (size_t)cap);
     p.rec_grad = take(4 * 9 * (size_t)R);
     p.rec_flag = take(8 * (size_t)d.n_rec_waves + 8);
@@ -437,10 +438,12 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
-                              at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect), st));
+                              at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect),
+                              at<uint32_t>(ws, p.chunk_tot), st));
     CGS_TRY(mark(h, 1, st));
-    // backward gradient slots of each record, in record order: needed only by
-    // the backward, so scanned beside the depth sort on the side stream
+    // backward gradient slots: each 64-record chunk owns a contiguous range
+    // (chunks in record order); its base, needed only by the backward, is
+    // scanned from the chunk totals beside the depth sort on the side stream
     Side* side = side_stream(st);
     std::unique_lock<std::mutex> side_lk;
     SideGuard guard;        // declared after the lock: joins before it is released
@@ -450,7 +453,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
         guard.sd = side;
         guard.st = st;
     }
-    CGS_TRY(scan_u32(at<uint32_t>(ws, p.ntiles), nullptr, h.d.n_rec, at<uint32_t>(ws, p.slot_off), nullptr,
+    CGS_TRY(scan_u32(at<uint32_t>(ws, p.chunk_tot), nullptr, h.d.n_rec_waves, at<uint32_t>(ws, p.chunk_base), nullptr,
                      at<unsigned long long>(ws, p.scan_bsum2), side ? side->s : st));
     // depth order of every record (stable: ties keep record order)
     uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
@@ -596,11 +599,11 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
                              at<float4>(ws, p.rec), at<const uint8_t>(ws, p.qbits), at<uint32_t>(ws, p.depth_key),
-                             at<uint32_t>(ws, p.slot_off),
+                             at<uint32_t>(ws, p.chunk_base),
                              grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
-    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.slot_off),
+    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.chunk_base),
                          at<uint32_t>(ws, p.ntiles), at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key),
                          at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), at<uint32_t>(ws, p.rec_flag),
                          gth, at<uint32_t>(ws, p.isl_flag), st));

@@ -21,7 +21,8 @@ constexpr int kMaxRowWidth = 8 + 48;    // ls3 q4 logit1 + degree-3 SH
 constexpr uint32_t kCulledKey = 0x7f800000u;   // +inf bits: sorts after every depth
 // One blend record per (view, Gaussian): 64 B, i.e. four float4 at rec[4r]:
 //   [0] (u, v, -A/2 log2e, -B log2e)   [1] (-C/2 log2e, opacity, red, green)
-//   [2] (blue, tile rect lo, tile rect hi, 0)   [3] unused padding
+//   [2] (blue, tile rect lo, tile rect hi, first gradient slot within the
+//   record's 64-record chunk)   [3] unused padding
 // so the blends' gather of a record is one 64-byte segment.
 constexpr int kRecF4 = 4;
 

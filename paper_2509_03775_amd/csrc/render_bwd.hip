@@ -32,7 +32,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                                                          const float4* __restrict__ rec,
                                                          const uint8_t* __restrict__ qbits,
                                                          const uint32_t* __restrict__ depth_key,
-                                                         const uint32_t* __restrict__ slot_off,
+                                                         const uint32_t* __restrict__ chunk_base,
                                                          const float* __restrict__ grad_image,
                                                          const float* __restrict__ T_final,
                                                          const int32_t* __restrict__ n_last,
@@ -104,7 +104,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             bl = x.x;
             const uint32_t rlo = __float_as_uint(x.y), rhi = __float_as_uint(x.z);
             const int rx0 = (int)(rlo & 0xffffu), ry0 = (int)(rlo >> 16), rx1 = (int)(rhi & 0xffffu);
-            slot = (int64_t)slot_off[r] + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
+            // the record's slots: its chunk's base (a small table, cached) +
+            // its offset in the chunk (the record's spare word) + the tile's
+            // row-major index in the record's rectangle
+            const uint32_t cb = chunk_base[vd.rec_wave_off + ((int64_t)(r - (uint32_t)vd.rec_off) >> 6)];
+            slot = (int64_t)cb + __float_as_uint(x.w) + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
             qm = qbits[start + li];     // the forward's quadrant mask of this record
         }
         const uint64_t km = __ballot(qm != 0u);
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 __device__ float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 
 __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
-                                                  const uint32_t* __restrict__ slot_off,
+                                                  const uint32_t* __restrict__ chunk_base,
                                                   const uint32_t* __restrict__ ntiles,
                                                   const uint2* __restrict__ tile_rect,
                                                   const uint32_t* __restrict__ depth_key,
@@ -255,13 +259,13 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     // the wave's first record and own no slots)
     const int64_t r = vd.rec_off + (valid ? i : i0);
     const uint2 tr = tile_rect[r];
-    const uint32_t so = slot_off[r];
     const uint32_t key = depth_key[r];
     const uint32_t ntr = ntiles[r];
     const uint32_t nt = valid && cnt->n_inst_ok != 0ull ? ntr : 0u;
     const uint32_t incl = wave_incl_scan(nt, lane);
     const uint32_t start = incl - nt;
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t so = chunk_base[wv] + start;     // the chunk's slots are contiguous
     float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (total != 0u) {
         s_start[w][lane] = start;

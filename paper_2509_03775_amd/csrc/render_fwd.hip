@@ -13,16 +13,18 @@ template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict__ desc,
                                                     float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles,
-                                                    uint32_t* __restrict__ prect) {
+                                                    uint32_t* __restrict__ prect, uint32_t* __restrict__ chunk_tot) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
     const SceneDesc& sd = desc->scenes[find_scene_by_wave(desc, wv)];
-    const int64_t g = (wv - sd.wave_off) * kWave + (threadIdx.x & 63);
-    if (g >= sd.n) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t q = wv - sd.wave_off;            // the wave's 64-Gaussian chunk of its scene
+    const int64_t g = q * kWave + lane;
+    const bool inb = g < sd.n;                     // lanes past the scene's end write nothing
 
     GaussParams gp;
-    const bool valid = load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
+    const bool valid = inb && load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
     GaussShape sh;
     if (valid) gaussian_shape(gp, sh);
     const float opac = valid ? 1.0f / (1.0f + __expf(-gp.logit)) : 0.0f;
@@ -33,6 +35,14 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         const int64_t r = vd.rec_off + g;
         ViewProj vp;
         const bool keep = valid && project_view(vd, gp.mean, sh, vp);
+        // The records of this chunk own one contiguous range of backward
+        // gradient slots: the chunk's total goes to chunk_tot (scanned into
+        // the chunk's base later) and each record keeps its offset within
+        // the chunk in the spare word of its record.
+        const uint32_t nt = keep ? (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0)) : 0u;
+        const uint32_t incl = wave_incl_sum_u32(nt, lane);
+        if (lane == 63) chunk_tot[vd.rec_wave_off + q] = incl;
+        if (!inb) continue;
         if (!keep) {
             depth_key[r] = kCulledKey;
             tile_rect[r] = make_uint2(0u, 0u);
@@ -40,7 +50,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
             if (desc->pack_rect) prect[r] = 0u;
             rec[kRecF4 * r + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[kRecF4 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[kRecF4 * r + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[kRecF4 * r + 2] = make_float4(0.f, 0.f, 0.f, __uint_as_float(incl - nt));
             rec[kRecF4 * r + 3] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
         }
@@ -52,12 +62,12 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         const uint32_t rlo = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16);
         const uint32_t rhi = (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16);
         tile_rect[r] = make_uint2(rlo, rhi);
-        ntiles[r] = (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0));
+        ntiles[r] = nt;
         if (desc->pack_rect)
             prect[r] = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 8) | ((uint32_t)vp.tx1 << 16) | ((uint32_t)vp.ty1 << 24);
         rec[kRecF4 * r + 0] = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
         rec[kRecF4 * r + 1] = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
-        rec[kRecF4 * r + 2] = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), 0.f);
+        rec[kRecF4 * r + 2] = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), __uint_as_float(incl - nt));
         rec[kRecF4 * r + 3] = make_float4(0.f, 0.f, 0.f, 0.f);   // whole 64-byte lines are written
         (void)NCO;
     }
@@ -325,10 +335,11 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, float4* rec,
-                             uint32_t* dk, uint2* tr, uint32_t* nt, uint32_t* prect, hipStream_t st) {
+                             uint32_t* dk, uint2* tr, uint32_t* nt, uint32_t* prect, uint32_t* chunk_tot,
+                             hipStream_t st) {
     if (n_gauss_waves <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect)
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
                        case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }

@@ -302,8 +302,12 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
                                                         const uint32_t* pay_in, uint32_t* pay_out) {
     constexpr bool PAY = MODE == kPassCarry || MODE == kPassUnpack;
     __shared__ uint32_t cnt[kOsWaves][kRadixBins];
-    __shared__ unsigned long long s_peer[kOsWaves][kRadixBins];
-    __shared__ uint32_t s_buf[kOsTile];
+    // The peer masks are needed only while ranking, the staging buffer only
+    // after it (two barriers later): they share the same LDS, which keeps the
+    // workgroup at 41 KB (three per CU instead of two).
+    __shared__ __align__(16) uint32_t s_buf[kOsTile];
+    static_assert(sizeof(unsigned long long) * kOsWaves * kRadixBins <= sizeof(uint32_t) * kOsTile, "peer masks");
+    unsigned long long (*s_peer)[kRadixBins] = reinterpret_cast<unsigned long long (*)[kRadixBins]>(s_buf);
     __shared__ uint32_t s_goff[kRadixBins];
     __shared__ uint32_t s_wave[kOsWaves];
     __shared__ uint32_t s_ticket;

@@ -26,4 +26,19 @@ __device__ inline uint32_t wave_incl_max_u32(uint32_t v, int lane) {
     return v > pre ? v : pre;
 }
 
+// Inclusive sum over lanes 0..l of the wave (every lane active), the same
+// way: row prefixes by DPP row shifts, then the totals of the earlier rows.
+__device__ inline uint32_t wave_incl_sum_u32(uint32_t v, int lane) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    const int row = lane >> 4;
+    const uint32_t pre = row == 0 ? 0u : (row == 1 ? r0 : (row == 2 ? r0 + r1 : r0 + r1 + r2));
+    return v + pre;
+}
+
 }  // namespace cgs
