@@ -132,7 +132,7 @@ class Form:
     issues one call per view."""
 
     def __init__(self, wl: sc.Workload, batched: bool, capacity_slack=1.08, waves_per_block=1, tile_order=0,
-                 train: bool = False):
+                 train: bool = False, persistent: int = 0):
         self.wl = wl
         self.batched = batched
         self.train = train
@@ -149,7 +149,7 @@ class Form:
             remap = {s: i for i, s in enumerate(used)}
             r = render.Renderer([ds[s] for s in used], [wl.cameras[v] for v in gidx],
                                 [remap[int(wl.view_scene[v])] for v in gidx], waves_per_block=waves_per_block,
-                                tile_order=tile_order)
+                                tile_order=tile_order, persistent=persistent)
             m = r.fit_capacity()
             r.set_capacity(int(m * capacity_slack) + 4096)
             r.fit_capacity()
@@ -603,8 +603,9 @@ def main():
         sched, tuned = autotune.tune(head.renderers[0], head.grads[0], reps=3, use_cache=False)
     else:
         sched = tuple(int(x) for x in args.schedule.split(","))
+        sched = sched + (0,) * (3 - len(sched))
         head.renderers[0].set_schedule(*sched)
-    log(f"[bench] schedule waves_per_block={sched[0]} tile_order={sched[1]}")
+    log(f"[bench] schedule waves_per_block={sched[0]} tile_order={sched[1]} persistent={sched[2]}")
     ev = HipEvents(args.steps * cgs.STAGE_EVENTS)
     log(f"[bench] timing {args.workload} batched: {args.steps} steps after {args.warmup} warmup")
     ms = head.time(args.steps, args.warmup, ev)
@@ -646,7 +647,7 @@ def main():
         torch.cuda.empty_cache()
     if "train" in extras:
         log(f"[bench] timing {args.workload} training step: SSIM loss + fused SGLD update")
-        f = Form(wl, batched=True, waves_per_block=sched[0], tile_order=sched[1], train=True)
+        f = Form(wl, batched=True, waves_per_block=sched[0], tile_order=sched[1], train=True, persistent=sched[2])
         ev2 = HipEvents(nsteps * cgs.STAGE_EVENTS)
         ms_t = f.time(nsteps, 2, ev2)
         checks["train"] = check_form(f)
@@ -664,7 +665,7 @@ def main():
     if "uncompressed" in extras:
         log(f"[bench] timing {args.workload} uncompressed (K = N)")
         wu = uncompressed_workload(wl)
-        f = Form(wu, batched=True, waves_per_block=sched[0], tile_order=sched[1])
+        f = Form(wu, batched=True, waves_per_block=sched[0], tile_order=sched[1], persistent=sched[2])
         ms_u = f.time(nsteps, 2)
         checks["uncompressed"] = check_form(f)
         forms[f"{'bf16' if wl.bf16 else 'fp32'}_batched_uncompressed:{args.workload}"] = wl.n_pixels / (ms_u * 1e-3) / 1e6
@@ -678,24 +679,45 @@ def main():
         for bf in (True, False):
             log(f"[bench] timing {name} {'bf16 batched' if bf else 'fp32 plain'}")
             w1 = sc.make_workload(name, bf16=bf)
-            f = Form(w1, batched=bf, waves_per_block=sched[0] if bf else 1, tile_order=sched[1] if bf else 0)
+            f = Form(w1, batched=bf, waves_per_block=sched[0] if bf else 1, tile_order=sched[1] if bf else 0,
+                     persistent=sched[2] if bf else 0)
             forms[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = \
                 w1.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
             checks[f"{'bf16_batched' if bf else 'fp32_plain'}:{name}"] = check_form(f)
             del f
             torch.cuda.empty_cache()
     if "uneven16" in extras:
+        # 16 uneven scenes: plain FP32 (16 sequential calls, default schedule)
+        # against one batched BF16 call per stage, graph-replayed, with the
+        # schedule tuned on this batch; the grid launch and the persistent
+        # tile queue are both timed under replay and the faster is the form.
         name = "uneven16_512px"
-        for bf, batched in ((True, True), (False, False)):
-            log(f"[bench] timing {name} {'bf16 batched' if batched else 'fp32 plain (16 calls)'}")
-            w5 = sc.make_workload(name, bf16=bf)
-            f = Form(w5, batched=batched, waves_per_block=sched[0] if batched else 1,
-                     tile_order=sched[1] if batched else 0)
-            ms5 = time_graph(f, nsteps) if batched else f.time(nsteps, 2)
-            forms[f"{'bf16_batched_graph' if batched else 'fp32_plain'}:{name}"] = w5.n_pixels / (ms5 * 1e-3) / 1e6
-            checks[f"{'bf16_batched_graph' if batched else 'fp32_plain'}:{name}"] = check_form(f)
-            del f
-            torch.cuda.empty_cache()
+        log(f"[bench] timing {name} fp32 plain (16 calls)")
+        w5 = sc.make_workload(name, bf16=False)
+        f = Form(w5, batched=False)
+        forms[f"fp32_plain:{name}"] = w5.n_pixels / (f.time(nsteps, 2) * 1e-3) / 1e6
+        checks[f"fp32_plain:{name}"] = check_form(f)
+        del f
+        torch.cuda.empty_cache()
+        w5 = sc.make_workload(name, bf16=True)
+        f = Form(w5, batched=True)
+        f.step()
+        s5, tuned5 = autotune.tune(f.renderers[0], f.grads[0], reps=3, use_cache=False)
+        grid = min((c for c in autotune.CANDIDATES if c[2] == 0), key=lambda c: tuned5[",".join(map(str, c))])
+        pers = min((c for c in autotune.CANDIDATES if c[2] == 1), key=lambda c: tuned5[",".join(map(str, c))])
+        by = {}
+        for label, c in (("grid", grid), ("persistent", pers)):
+            log(f"[bench] timing {name} bf16 batched graph, {label} schedule {c}")
+            f.renderers[0].set_schedule(*c)
+            by[label] = {"schedule": list(c), "ms": time_graph(f, nsteps)}
+            checks[f"bf16_batched_graph_{label}:{name}"] = check_form(f)
+        best = min(by, key=lambda k: by[k]["ms"])
+        forms[f"bf16_batched_graph:{name}"] = w5.n_pixels / (by[best]["ms"] * 1e-3) / 1e6
+        extra_info["uneven16_batched"] = {"tuned_ms": tuned5, "graph_ms": by, "kept": best,
+                                          "grid_mpix_s": w5.n_pixels / (by["grid"]["ms"] * 1e-3) / 1e6,
+                                          "persistent_mpix_s": w5.n_pixels / (by["persistent"]["ms"] * 1e-3) / 1e6}
+        del f
+        torch.cuda.empty_cache()
     cam = wl.cameras[0]
     sb = step_bytes(wl, n_inst, walked)
     out = {
@@ -717,7 +739,8 @@ def main():
         "checks": checks,
         "extra": extra_info,
         "pairs": {"evaluated": e_eval, "blended": e_blend, "instances": n_inst, "walked_instances": walked},
-        "schedule": {"waves_per_block": sched[0], "tile_order": sched[1], "candidates_ms": tuned},
+        "schedule": {"waves_per_block": sched[0], "tile_order": sched[1], "persistent": sched[2],
+                     "candidates_ms": tuned},
     }
     print(json.dumps(out), flush=True)
 

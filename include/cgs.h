@@ -140,7 +140,10 @@ enum { CGS_STAGE_EVENTS = 8 };
 typedef struct {
     int32_t blend_waves_per_block;   /* waves (one 16x16 tile each) per workgroup: 1 (default), 2 or 4 */
     int32_t tile_order;              /* 0: row-major tiles, 1: XCD-grouped, 2: heaviest tile lists first */
-    int32_t reserved[2];
+    int32_t persistent;              /* 1: the blends run as a resident grid whose wavefronts take tiles from a
+                                        queue in tile order (0 and 1 then both mean row-major), one wave per
+                                        workgroup; 0 (default): one workgroup per group of tiles */
+    int32_t reserved;
     void** stage_events;
     int32_t* n_blend;
 } cgs_schedule;

@@ -1,7 +1,8 @@
 """Launch-schedule autotuning for the blend kernels.
 
-The schedule (waves per workgroup, tile order) changes only the order in
-which tiles are issued, never a result, so it is chosen by timing: tune()
+The schedule (waves per workgroup, tile order, persistent tile queue) changes
+only the order in which tiles are issued, never a result, so it is chosen by
+timing: tune()
 runs forward + backward under each candidate on the caller's own batch and
 keeps the fastest.  Winners are cached per workload shape in a JSON file so
 that later runs of the same shape skip the timing.
@@ -17,8 +18,11 @@ import torch
 
 from . import render
 
-# (waves per workgroup, tile order): 0 row-major, 1 XCD-grouped, 2 heaviest first
-CANDIDATES: Tuple[Tuple[int, int], ...] = ((1, 0), (2, 0), (4, 0), (1, 1), (1, 2), (2, 2), (4, 2))
+# (waves per workgroup, tile order, persistent): tile order 0 row-major, 1
+# XCD-grouped, 2 heaviest first; persistent 1 runs the blends as a resident
+# grid that takes tiles from a queue in that order (one wave per workgroup)
+CANDIDATES: Tuple[Tuple[int, int, int], ...] = ((1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 1, 0), (1, 2, 0), (2, 2, 0),
+                                                (4, 2, 0), (1, 0, 1), (1, 2, 1))
 
 
 def default_cache_path() -> str:
@@ -73,28 +77,29 @@ def time_schedule(r: render.Renderer, grad_image: torch.Tensor, reps: int) -> fl
 
 
 def tune(r: render.Renderer, grad_image: Optional[torch.Tensor] = None, reps: int = 5,
-         candidates: Iterable[Tuple[int, int]] = CANDIDATES, cache_path: Optional[str] = None,
-         use_cache: bool = True) -> Tuple[Tuple[int, int], Dict[str, float]]:
+         candidates: Iterable[Tuple[int, int, int]] = CANDIDATES, cache_path: Optional[str] = None,
+         use_cache: bool = True) -> Tuple[Tuple[int, int, int], Dict[str, float]]:
     """Pick the fastest schedule for this renderer's batch and apply it.
-    Returns ((waves_per_block, tile_order), {candidate: ms}); the timings are
-    empty when the cache answered."""
+    Returns ((waves_per_block, tile_order, persistent), {candidate: ms}); the
+    timings are empty when the cache answered."""
     path = cache_path or default_cache_path()
     key = shape_key(r)
     cache = _load(path) if use_cache else {}
     hit = cache.get(key)
+    candidates = tuple(tuple(c) for c in candidates)
     if hit and tuple(hit) in set(candidates):
         r.set_schedule(*hit)
-        return (int(hit[0]), int(hit[1])), {}
+        return tuple(int(x) for x in hit), {}
     if grad_image is None:
         grad_image = torch.full((r.n_pixels, 3), 1e-6, dtype=torch.float32, device=r.device)
     timings: Dict[str, float] = {}
     best, best_ms = None, float("inf")
-    for wpb, order in candidates:
-        r.set_schedule(wpb, order)
+    for cand in candidates:
+        r.set_schedule(*cand)
         ms = time_schedule(r, grad_image, reps)
-        timings[f"{wpb},{order}"] = round(ms, 4)
+        timings[",".join(str(x) for x in cand)] = round(ms, 4)
         if ms < best_ms:
-            best, best_ms = (wpb, order), ms
+            best, best_ms = cand, ms
     r.set_schedule(*best)
     if use_cache:
         cache = _load(path)

@@ -50,7 +50,8 @@ STAGE_EVENTS = 8
 
 
 class Schedule(ctypes.Structure):
-    _fields_ = [("blend_waves_per_block", c_int32), ("tile_order", c_int32), ("reserved", c_int32 * 2),
+    _fields_ = [("blend_waves_per_block", c_int32), ("tile_order", c_int32), ("persistent", c_int32),
+                ("reserved", c_int32),
                 ("stage_events", POINTER(c_void_p)), ("n_blend", c_void_p)]
 
 

@@ -23,11 +23,11 @@ hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, c
                              int32_t, const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_plain_keys(const uint32_t*, const uint32_t*, const uint32_t*, const DevCounters*, int64_t,
                              uint64_t*, uint32_t*, hipStream_t);
-hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
-                            uint8_t*, float*, float*, int32_t*, int32_t*, hipStream_t);
-hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, const uint32_t*, const uint32_t*, const float4*,
+hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, bool, const uint32_t*, const uint32_t*, const float4*,
+                            uint8_t*, float*, float*, int32_t*, int32_t*, DevCounters*, hipStream_t);
+hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, bool, const uint32_t*, const uint32_t*, const float4*,
                             const uint8_t*, const uint32_t*, const uint32_t*, const float*, const float*,
-                            const int32_t*, float*, uint2*, hipStream_t);
+                            const int32_t*, float*, uint2*, DevCounters*, hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, int64_t, const float*, const uint32_t*, const uint32_t*,
                         const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*, float*,
                         uint32_t*, hipStream_t);
@@ -79,6 +79,7 @@ struct Host {
     BatchDesc d;
     WsPlan p;
     int wpb;
+    bool persist;
     int inst_buf;          // buffer pair holding the tile-sorted instances
     int dsort_buf;         // buffer pair holding the depth-sorted records
     int tile_bits;
@@ -218,6 +219,9 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
                                                                                             : 1;
     d.tile_order = sch ? sch->tile_order : 0;
     if (d.tile_order < 0 || d.tile_order > 2) return CGS_EINVAL;
+    if (sch && (sch->persistent < 0 || sch->persistent > 1)) return CGS_EINVAL;
+    h->persist = sch && sch->persistent == 1;
+    if (h->persist) h->wpb = 1;
     h->events = sch ? reinterpret_cast<hipEvent_t*>(sch->stage_events) : nullptr;
     h->n_blend = sch ? sch->n_blend : nullptr;
     h->tile_bits = bits_for(d.n_tiles);
@@ -491,8 +495,9 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
         if (tb != h.tperm_buf) return CGS_EHIP;
     }
     CGS_TRY(mark(h, 2, st));
-    CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), iv[ib],
-                             at<float4>(ws, p.rec), at<uint8_t>(ws, p.qbits), image, T_final, n_last, h.n_blend, st));
+    CGS_TRY(launch_blend_fwd(dd, h.d.n_tiles, h.wpb, h.persist, at<uint32_t>(ws, p.tile_range), iv[ib],
+                             at<float4>(ws, p.rec), at<uint8_t>(ws, p.qbits), image, T_final, n_last, h.n_blend, cnt,
+                             st));
     CGS_TRY(guard.join());
     CGS_TRY(mark(h, 3, st));
     return CGS_OK;
@@ -597,10 +602,11 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
         CGS_TRY(sort_rows(0, h.d.sr_rows_total, side->s, &pb0));
     }
     float* ginst = at<float>(ws, p.ginst);
-    CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, at<uint32_t>(ws, p.tile_range), at<uint32_t>(ws, p.inst_val[h.inst_buf]),
+    CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, h.persist, at<uint32_t>(ws, p.tile_range),
+                             at<uint32_t>(ws, p.inst_val[h.inst_buf]),
                              at<float4>(ws, p.rec), at<const uint8_t>(ws, p.qbits), at<uint32_t>(ws, p.depth_key),
                              at<uint32_t>(ws, p.chunk_base),
-                             grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), st));
+                             grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), cnt, st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
     CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.chunk_base),

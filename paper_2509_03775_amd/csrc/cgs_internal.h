@@ -111,11 +111,22 @@ struct MhWs {
     unsigned long long *tot, *bsum;
 };
 
+constexpr int kQueues = 8;          // tile queues of a persistent blend (one per XCD)
+constexpr int kQueueStride = 16;    // u64 words between queues (128 bytes)
+
 // Device counters kept in the workspace.
 struct DevCounters {
     unsigned long long n_inst;     // instances needed
     unsigned long long n_inst_ok;  // instances emitted (0 on overflow)
-    unsigned long long pad[6];
+    unsigned long long done_fwd, done_bwd;   // retired wavefronts of the persistent blends
+    unsigned long long pad[4];
+    // tile queues of the persistent blends, one per XCD (workgroups are
+    // dispatched to the 8 XCDs round-robin), each on its own 128-byte line:
+    // queue x hands out positions x, x + 8, x + 16, ... of the tile order.
+    // Zeroed by the forward's capacity check and reset by the last wavefront
+    // of each persistent launch.
+    unsigned long long q_fwd[kQueues * kQueueStride];
+    unsigned long long q_bwd[kQueues * kQueueStride];
 };
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -315,6 +326,12 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
 uint32_t sort_stalls();
 
 hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key, hipStream_t st);
+
+// Workgroups of `kernel` (a __global__ function) at `block` threads that the
+// current device holds at once: CUs x the occupancy its registers and LDS
+// allow (the grid of a persistent launch); 0 if the query fails.  Cached per
+// (device, kernel, block).
+int64_t resident_blocks(const void* kernel, int block);
 
 hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                        int64_t n_tiles, uint32_t* ranges, hipStream_t st);

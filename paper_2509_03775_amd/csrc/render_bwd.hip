@@ -25,7 +25,10 @@ namespace cgs {
 // a fixed order, so the backward is deterministic.  Instances the walk never
 // reaches (beyond every pixel's n_last) are not touched: the tile's cut,
 // written here, tells the chain-rule kernel which slots hold values.
-template <int WPB>
+//
+// PERSIST: the grid is resident and each wavefront takes tiles from the
+// backward's tile queue until it runs dry (same per-tile work and results).
+template <int WPB, bool PERSIST>
 __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
@@ -36,7 +39,8 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                                                          const float* __restrict__ grad_image,
                                                          const float* __restrict__ T_final,
                                                          const int32_t* __restrict__ n_last,
-                                                         float* __restrict__ ginst, uint2* __restrict__ tile_cut) {
+                                                         float* __restrict__ ginst, uint2* __restrict__ tile_cut,
+                                                         DevCounters* __restrict__ cnt) {
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
@@ -44,180 +48,192 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
     __shared__ uint32_t s_s[WPB][64];                          // gradient slot of each staged record
     __shared__ __align__(16) float s_red[WPB][2][9][64];        // per-lane sums of a pair of records, by value
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
-    if (tile >= desc->n_tiles) return;
-    const int v = find_view_by_tile(desc, tile);
-    const ViewDesc& vd = desc->views[v];
-    const int64_t lt = tile - vd.tile_off;
-    const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
-    const int x0 = tx * kTile, y0 = ty * kTile;
-
-    float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpx[4], fpy[4];
-    uint32_t last[4];
-    uint32_t maxlast = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
-        fpx[k] = (float)px;
-        fpy[k] = (float)py;
-        bh0[k] = vd.bg[0]; bh1[k] = vd.bg[1]; bh2[k] = vd.bg[2];
-        if (px < vd.W && py < vd.H) {
-            const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
-            T[k] = T_final[p];
-            last[k] = (uint32_t)n_last[p];
-            dC0[k] = grad_image[3 * p + 0];
-            dC1[k] = grad_image[3 * p + 1];
-            dC2[k] = grad_image[3 * p + 2];
+    uint32_t fetched = 0u;
+    if constexpr (PERSIST) fetched = fetch_pos(cnt->q_bwd, lane);
+    for (int it = 0;; ++it) {
+        int64_t tile;
+        if constexpr (PERSIST) {
+            tile = tile_at(desc, fetched);
+            if (tile < desc->n_tiles) fetched = fetch_pos(cnt->q_bwd, lane);   // the next one, waited for at the top
         } else {
-            T[k] = 1.f; last[k] = 0; dC0[k] = dC1[k] = dC2[k] = 0.f;
+            if (it > 0) break;
+            tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
         }
-        maxlast = last[k] > maxlast ? last[k] : maxlast;
-    }
-    maxlast = wave_max_u32(maxlast);
-    const uint32_t start = ranges[2 * tile];
-    const uint32_t len = ranges[2 * tile + 1] - start;
-    if (maxlast > len) maxlast = len;     // n_last inconsistent with this binning: stay in the list
-    // The walk covers list positions [0, maxlast).  Lists are ordered by
-    // (depth key, record), so the first position it does not reach is named
-    // by that pair; the chain-rule kernel reads only slots ordered before it
-    // and the slots beyond are never written.
-    if (lane == 0) {
-        uint2 cut = make_uint2(0xffffffffu, 0xffffffffu);
-        if (maxlast < len) {
-            const uint32_t c = inst_rec[start + maxlast];
-            cut = make_uint2(depth_key[c], c);
-        }
-        tile_cut[tile] = cut;
-    }
-    for (int64_t bend = maxlast; bend > 0; bend -= 64) {
-        const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
-        const int64_t li = bbeg + lane;
-        int64_t slot = -1;
-        uint32_t qm = 0u;
-        float4 g, c;
-        float bl = 0.f;
-        if (li < bend) {
-            const uint32_t r = inst_rec[start + li];
-            g = rec[kRecF4 * (int64_t)r + 0];
-            c = rec[kRecF4 * (int64_t)r + 1];
-            const float4 x = rec[kRecF4 * (int64_t)r + 2];
-            bl = x.x;
-            const uint32_t rlo = __float_as_uint(x.y), rhi = __float_as_uint(x.z);
-            const int rx0 = (int)(rlo & 0xffffu), ry0 = (int)(rlo >> 16), rx1 = (int)(rhi & 0xffffu);
-            // the record's slots: its chunk's base (a small table, cached) +
-            // its offset in the chunk (the record's spare word) + the tile's
-            // row-major index in the record's rectangle
-            const uint32_t cb = chunk_base[vd.rec_wave_off + ((int64_t)(r - (uint32_t)vd.rec_off) >> 6)];
-            slot = (int64_t)cb + __float_as_uint(x.w) + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
-            qm = qbits[start + li];     // the forward's quadrant mask of this record
-        }
-        const uint64_t km = __ballot(qm != 0u);
-        const uint32_t mine = popc_below(km);
-        if (qm != 0u) {
-            s_g[w][mine] = g;
-            s_c[w][mine] = c;
-            s_b[w][mine] = bl;
-            s_p[w][mine] = ((uint32_t)li << 4) | qm;
-            s_s[w][mine] = (uint32_t)slot;
-        }
-        wave_sync();
-        const int cnt = (int)__popcll(km);
-        for (int j = cnt - 1; j >= 0; --j) {
-            const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
-            const uint32_t pos = pq >> 4;     // 0-based list position
-            const float4 gg = s_g[w][j];
-            const float4 cc = s_c[w][j];
-            const float bb = s_b[w][j];
-            float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
+        if (tile >= desc->n_tiles) break;
+        const int v = find_view_by_tile(desc, tile);
+        const ViewDesc& vd = desc->views[v];
+        const int64_t lt = tile - vd.tile_off;
+        const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
+        const int x0 = tx * kTile, y0 = ty * kTile;
+
+        float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpx[4], fpy[4];
+        uint32_t last[4];
+        uint32_t maxlast = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
-                const float dx = fpx[k] - gg.x;
-                const float dy = fpy[k] - gg.y;
-                float G;
-                bool pcl;
-                const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
-                const bool use = (pos < last[k]) && (alpha >= kMinAlpha);
-                if (__ballot(use) == 0ull) continue;       // no pixel of the quadrant blended it
-                // Branch-free for the lanes of the quadrant: pairs the forward
-                // did not blend get alpha 0 and zero gradients, which leaves T
-                // and the background sum unchanged.
-                const float am = use ? alpha : 0.f;
-                const float Tb = use ? T[k] * __builtin_amdgcn_rcpf(1.f - alpha) : T[k];
-                const float wgt = am * Tb;
-                a_r = fmaf(wgt, dC0[k], a_r);
-                a_g = fmaf(wgt, dC1[k], a_g);
-                a_bl = fmaf(wgt, dC2[k], a_bl);
-                const float e0 = cc.z - bh0[k], e1 = cc.w - bh1[k], e2 = bb - bh2[k];
-                const float dal = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
-                bh0[k] = fmaf(am, e0, bh0[k]);
-                bh1[k] = fmaf(am, e1, bh1[k]);
-                bh2[k] = fmaf(am, e2, bh2[k]);
-                T[k] = Tb;
-                const bool open = use && (alpha < kMaxAlpha);      // alpha not saturated at 0.99
-                const float dao = open ? dal : 0.f;
-                a_o = fmaf(dao, G, a_o);
-                const float dp = (open && !pcl) ? dal * alpha : 0.f;  // dL/dpower
-                const float dpx = dp * dx, dpy = dp * dy;
-                a_a = fmaf(dpx, dx, a_a);
-                a_b = fmaf(dpx, dy, a_b);
-                a_c = fmaf(dpy, dy, a_c);
-                // dL/du = -(2 a' Sx + b' Sy), dL/dv = -(2 c' Sy + b' Sx) with
-                // Sx = sum dp dx, Sy = sum dp dy (a' = -A/2, b' = -B, c' = -C/2);
-                // the conic is the record's, so the sums are taken first.
-                a_u += dpx;
-                a_v += dpy;
+        for (int k = 0; k < 4; ++k) {
+            const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
+            fpx[k] = (float)px;
+            fpy[k] = (float)py;
+            bh0[k] = vd.bg[0]; bh1[k] = vd.bg[1]; bh2[k] = vd.bg[2];
+            if (px < vd.W && py < vd.H) {
+                const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
+                T[k] = T_final[p];
+                last[k] = (uint32_t)n_last[p];
+                dC0[k] = grad_image[3 * p + 0];
+                dC1[k] = grad_image[3 * p + 1];
+                dC2[k] = grad_image[3 * p + 2];
+            } else {
+                T[k] = 1.f; last[k] = 0; dC0[k] = dC1[k] = dC2[k] = 0.f;
             }
-            // This lane's nine sums for record j, the position sums already
-            // turned into dL/du, dL/dv by the record's natural-log conic (a
-            // linear map, so it is applied before the sum over lanes).
-            {
-                const float na2 = 2.f * kLn2 * gg.z, nb = kLn2 * gg.w, nc2 = 2.f * kLn2 * cc.x;
-                float* red = &s_red[w][j & 1][0][lane];
-                red[0 * 64] = -fmaf(na2, a_u, nb * a_v);
-                red[1 * 64] = -fmaf(nc2, a_v, nb * a_u);
-                red[2 * 64] = a_a;
-                red[3 * 64] = a_b;
-                red[4 * 64] = a_c;
-                red[5 * 64] = a_o;
-                red[6 * 64] = a_r;
-                red[7 * 64] = a_g;
-                red[8 * 64] = a_bl;
+            maxlast = last[k] > maxlast ? last[k] : maxlast;
+        }
+        maxlast = wave_max_u32(maxlast);
+        const uint32_t start = ranges[2 * tile];
+        const uint32_t len = ranges[2 * tile + 1] - start;
+        if (maxlast > len) maxlast = len;     // n_last inconsistent with this binning: stay in the list
+        // The walk covers list positions [0, maxlast).  Lists are ordered by
+        // (depth key, record), so the first position it does not reach is named
+        // by that pair; the chain-rule kernel reads only slots ordered before it
+        // and the slots beyond are never written.
+        if (lane == 0) {
+            uint2 cut = make_uint2(0xffffffffu, 0xffffffffu);
+            if (maxlast < len) {
+                const uint32_t c = inst_rec[start + maxlast];
+                cut = make_uint2(depth_key[c], c);
             }
-            if ((j & 1) == 0) {
-                // Sum the pair (records j, j + 1 if staged) over the lanes: the
-                // 2 x 9 value vectors are split into 8-lane segments; lane l of
-                // round t takes segment l & 7 of vector (64 t + l) >> 3, adds its
-                // eight values, the segments of a vector are combined by DPP row
-                // shifts into its last lane, which writes the record's slot.
-                wave_sync();
-                const int nrec = cnt - j < 2 ? cnt - j : 2;
+            tile_cut[tile] = cut;
+        }
+        for (int64_t bend = maxlast; bend > 0; bend -= 64) {
+            const int64_t bbeg = bend - 64 > 0 ? bend - 64 : 0;
+            const int64_t li = bbeg + lane;
+            int64_t slot = -1;
+            uint32_t qm = 0u;
+            float4 g, c;
+            float bl = 0.f;
+            if (li < bend) {
+                const uint32_t r = inst_rec[start + li];
+                g = rec[kRecF4 * (int64_t)r + 0];
+                c = rec[kRecF4 * (int64_t)r + 1];
+                const float4 x = rec[kRecF4 * (int64_t)r + 2];
+                bl = x.x;
+                const uint32_t rlo = __float_as_uint(x.y), rhi = __float_as_uint(x.z);
+                const int rx0 = (int)(rlo & 0xffffu), ry0 = (int)(rlo >> 16), rx1 = (int)(rhi & 0xffffu);
+                // the record's slots: its chunk's base (a small table, cached) +
+                // its offset in the chunk (the record's spare word) + the tile's
+                // row-major index in the record's rectangle
+                const uint32_t cb = chunk_base[vd.rec_wave_off + ((int64_t)(r - (uint32_t)vd.rec_off) >> 6)];
+                slot = (int64_t)cb + __float_as_uint(x.w) + (int64_t)(ty - ry0) * (rx1 - rx0) + (tx - rx0);
+                qm = qbits[start + li];     // the forward's quadrant mask of this record
+            }
+            const uint64_t km = __ballot(qm != 0u);
+            const uint32_t mine = popc_below(km);
+            if (qm != 0u) {
+                s_g[w][mine] = g;
+                s_c[w][mine] = c;
+                s_b[w][mine] = bl;
+                s_p[w][mine] = ((uint32_t)li << 4) | qm;
+                s_s[w][mine] = (uint32_t)slot;
+            }
+            wave_sync();
+            const int cnt = (int)__popcll(km);
+            for (int j = cnt - 1; j >= 0; --j) {
+                const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
+                const uint32_t pos = pq >> 4;     // 0-based list position
+                const float4 gg = s_g[w][j];
+                const float4 cc = s_c[w][j];
+                const float bb = s_b[w][j];
+                float a_u = 0.f, a_v = 0.f, a_a = 0.f, a_b = 0.f, a_c = 0.f, a_o = 0.f, a_r = 0.f, a_g = 0.f, a_bl = 0.f;
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const int p = 64 * t + lane;
-                    const int rec = p >= 72 ? 1 : 0;
-                    const int val = (p - 72 * rec) >> 3;
-                    const bool ok = p < 144 && rec < nrec;
-                    float x = 0.f;
-                    if (ok) {
-                        const float4 lo = *reinterpret_cast<const float4*>(&s_red[w][rec][val][8 * (lane & 7)]);
-                        const float4 hi = *reinterpret_cast<const float4*>(&s_red[w][rec][val][8 * (lane & 7) + 4]);
-                        x = ((lo.x + lo.y) + (lo.z + lo.w)) + ((hi.x + hi.y) + (hi.z + hi.w));
-                    }
-                    x = group8_sum_to_last(x);
-                    if (ok && (lane & 7) == 7) ginst[9 * (int64_t)s_s[w][j + rec] + val] = x;
+                for (int k = 0; k < 4; ++k) {
+                    if (!((pq >> k) & 1u)) continue;          // wave-uniform quadrant skip
+                    const float dx = fpx[k] - gg.x;
+                    const float dy = fpy[k] - gg.y;
+                    float G;
+                    bool pcl;
+                    const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
+                    const bool use = (pos < last[k]) && (alpha >= kMinAlpha);
+                    if (__ballot(use) == 0ull) continue;       // no pixel of the quadrant blended it
+                    // Branch-free for the lanes of the quadrant: pairs the forward
+                    // did not blend get alpha 0 and zero gradients, which leaves T
+                    // and the background sum unchanged.
+                    const float am = use ? alpha : 0.f;
+                    const float Tb = use ? T[k] * __builtin_amdgcn_rcpf(1.f - alpha) : T[k];
+                    const float wgt = am * Tb;
+                    a_r = fmaf(wgt, dC0[k], a_r);
+                    a_g = fmaf(wgt, dC1[k], a_g);
+                    a_bl = fmaf(wgt, dC2[k], a_bl);
+                    const float e0 = cc.z - bh0[k], e1 = cc.w - bh1[k], e2 = bb - bh2[k];
+                    const float dal = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
+                    bh0[k] = fmaf(am, e0, bh0[k]);
+                    bh1[k] = fmaf(am, e1, bh1[k]);
+                    bh2[k] = fmaf(am, e2, bh2[k]);
+                    T[k] = Tb;
+                    const bool open = use && (alpha < kMaxAlpha);      // alpha not saturated at 0.99
+                    const float dao = open ? dal : 0.f;
+                    a_o = fmaf(dao, G, a_o);
+                    const float dp = (open && !pcl) ? dal * alpha : 0.f;  // dL/dpower
+                    const float dpx = dp * dx, dpy = dp * dy;
+                    a_a = fmaf(dpx, dx, a_a);
+                    a_b = fmaf(dpx, dy, a_b);
+                    a_c = fmaf(dpy, dy, a_c);
+                    // dL/du = -(2 a' Sx + b' Sy), dL/dv = -(2 c' Sy + b' Sx) with
+                    // Sx = sum dp dx, Sy = sum dp dy (a' = -A/2, b' = -B, c' = -C/2);
+                    // the conic is the record's, so the sums are taken first.
+                    a_u += dpx;
+                    a_v += dpy;
                 }
-                wave_sync();
-            }
-        }
-        wave_sync();
-        if (slot >= 0 && qm == 0u) {       // a record no pixel of the tile blended
-            float* dst = ginst + 9 * slot;
+                // This lane's nine sums for record j, the position sums already
+                // turned into dL/du, dL/dv by the record's natural-log conic (a
+                // linear map, so it is applied before the sum over lanes).
+                {
+                    const float na2 = 2.f * kLn2 * gg.z, nb = kLn2 * gg.w, nc2 = 2.f * kLn2 * cc.x;
+                    float* red = &s_red[w][j & 1][0][lane];
+                    red[0 * 64] = -fmaf(na2, a_u, nb * a_v);
+                    red[1 * 64] = -fmaf(nc2, a_v, nb * a_u);
+                    red[2 * 64] = a_a;
+                    red[3 * 64] = a_b;
+                    red[4 * 64] = a_c;
+                    red[5 * 64] = a_o;
+                    red[6 * 64] = a_r;
+                    red[7 * 64] = a_g;
+                    red[8 * 64] = a_bl;
+                }
+                if ((j & 1) == 0) {
+                    // Sum the pair (records j, j + 1 if staged) over the lanes: the
+                    // 2 x 9 value vectors are split into 8-lane segments; lane l of
+                    // round t takes segment l & 7 of vector (64 t + l) >> 3, adds its
+                    // eight values, the segments of a vector are combined by DPP row
+                    // shifts into its last lane, which writes the record's slot.
+                    wave_sync();
+                    const int nrec = cnt - j < 2 ? cnt - j : 2;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) dst[k] = 0.f;
+                    for (int t = 0; t < 3; ++t) {
+                        const int p = 64 * t + lane;
+                        const int rec = p >= 72 ? 1 : 0;
+                        const int val = (p - 72 * rec) >> 3;
+                        const bool ok = p < 144 && rec < nrec;
+                        float x = 0.f;
+                        if (ok) {
+                            const float4 lo = *reinterpret_cast<const float4*>(&s_red[w][rec][val][8 * (lane & 7)]);
+                            const float4 hi = *reinterpret_cast<const float4*>(&s_red[w][rec][val][8 * (lane & 7) + 4]);
+                            x = ((lo.x + lo.y) + (lo.z + lo.w)) + ((hi.x + hi.y) + (hi.z + hi.w));
+                        }
+                        x = group8_sum_to_last(x);
+                        if (ok && (lane & 7) == 7) ginst[9 * (int64_t)s_s[w][j + rec] + val] = x;
+                    }
+                    wave_sync();
+                }
+            }
+            wave_sync();
+            if (slot >= 0 && qm == 0u) {       // a record no pixel of the tile blended
+                float* dst = ginst + 9 * slot;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) dst[k] = 0.f;
+            }
+            wave_sync();
         }
-        wave_sync();
     }
+    if constexpr (PERSIST) retire_wave(cnt->q_bwd, &cnt->done_bwd, (unsigned long long)gridDim.x * WPB, lane);
 }
 
 // ------------------------------------------------------- record gradients
@@ -986,21 +1002,28 @@ __global__ __launch_bounds__(256) void k_l1_final(const float* __restrict__ part
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
+
+hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, bool persist, const uint32_t* ranges,
                             const uint32_t* inst_rec, const float4* rec, const uint8_t* qbits, const uint32_t* dk,
                             const uint32_t* eo,
                             const float* grad_image, const float* T_final, const int32_t* n_last, float* ginst,
-                            uint2* cut, hipStream_t st) {
+                            uint2* cut, DevCounters* cnt, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    if (wpb == 1) {
-        hipLaunchKernelGGL(k_blend_bwd<1>, dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec, rec,
-                           qbits, dk, eo, grad_image, T_final, n_last, ginst, cut);
+    if (persist) {
+        int64_t nb = resident_blocks(reinterpret_cast<const void*>(&k_blend_bwd<1, true>), 64);
+        if (nb <= 0) return hipErrorInvalidValue;
+        if (nb > n_tiles) nb = n_tiles;
+        hipLaunchKernelGGL((k_blend_bwd<1, true>), dim3((unsigned)nb), dim3(64), 0, st, d_desc, ranges, inst_rec, rec,
+                           qbits, dk, eo, grad_image, T_final, n_last, ginst, cut, cnt);
+    } else if (wpb == 1) {
+        hipLaunchKernelGGL((k_blend_bwd<1, false>), dim3((unsigned)n_tiles), dim3(64), 0, st, d_desc, ranges, inst_rec,
+                           rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut, cnt);
     } else if (wpb == 2) {
-        hipLaunchKernelGGL(k_blend_bwd<2>, dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc, ranges,
-                           inst_rec, rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut);
+        hipLaunchKernelGGL((k_blend_bwd<2, false>), dim3((unsigned)((n_tiles + 1) / 2)), dim3(128), 0, st, d_desc,
+                           ranges, inst_rec, rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut, cnt);
     } else {
-        hipLaunchKernelGGL(k_blend_bwd<4>, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc, ranges,
-                           inst_rec, rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut);
+        hipLaunchKernelGGL((k_blend_bwd<4, false>), dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, d_desc,
+                           ranges, inst_rec, rec, qbits, dk, eo, grad_image, T_final, n_last, ginst, cut, cnt);
     }
     return hipGetLastError();
 }

@@ -430,4 +430,35 @@ __device__ inline int64_t tile_index(const BatchDesc* d, int64_t b, int64_t nb, 
     return b * wpb + w;
 }
 
+// Persistent blends: a resident grid whose wavefronts take tiles from
+// queues (atomic counters) until they run dry.  A workgroup uses the queue of
+// its XCD (blockIdx mod 8, the dispatch order), which hands out every 8th
+// position of the tile order; the position maps to a tile through the
+// heavy-first permutation (tile order 2) or directly.  fetch_pos issues the
+// atomic (lane 0) and returns without waiting; tile_at reads the result.
+__device__ inline uint32_t fetch_pos(unsigned long long* q, int lane) {
+    uint32_t t = 0xffffffffu;
+    if (lane == 0) t = (uint32_t)atomicAdd(&q[(blockIdx.x % kQueues) * kQueueStride], 1ull);
+    return t;
+}
+
+__device__ inline int64_t tile_at(const BatchDesc* d, uint32_t fetched) {
+    const uint64_t pos = (uint64_t)__builtin_amdgcn_readfirstlane(fetched) * kQueues + blockIdx.x % kQueues;
+    if (pos >= (uint64_t)d->n_tiles) return d->n_tiles;
+    return d->tile_order == 2 ? (int64_t)d->tile_perm[pos] : (int64_t)pos;
+}
+
+// A wavefront that found its queue dry retires; the last of the launch's
+// `waves` wavefronts resets the queues for the next launch.
+__device__ inline void retire_wave(unsigned long long* q, unsigned long long* done, unsigned long long waves,
+                                   int lane) {
+    if (lane == 0) {
+        const unsigned long long d = atomicAdd(done, 1ull);
+        if (d + 1ull == waves) {
+            for (int x = 0; x < kQueues; ++x) atomicExch(&q[x * kQueueStride], 0ull);
+            atomicExch(done, 0ull);
+        }
+    }
+}
+
 }  // namespace cgs

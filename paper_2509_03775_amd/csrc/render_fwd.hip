@@ -2,6 +2,8 @@
 // Gaussian, looping over the views of its scene so the gather and the
 // view-independent activations are done once per batch), instance emission,
 // and the front-to-back blend (paper Sec. 2.1, Eq. 1-3).
+#include <algorithm>
+
 #include "cgs_internal.h"
 #include "render_common.h"
 #include "wave_scan.h"
@@ -78,6 +80,12 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
     unsigned long long m = cnt->n_inst;
     bool ok = (int64_t)m <= capacity;
     cnt->n_inst_ok = ok ? m : 0ull;
+    cnt->done_fwd = 0ull;
+    cnt->done_bwd = 0ull;
+    for (int x = 0; x < kQueues; ++x) {
+        cnt->q_fwd[x * kQueueStride] = 0ull;
+        cnt->q_bwd[x * kQueueStride] = 0ull;
+    }
     if (d_info) {
         d_info[0] = ok ? CGS_OK : CGS_ECAPACITY;
         d_info[1] = (int64_t)m;
@@ -214,123 +222,139 @@ __global__ __launch_bounds__(256) void k_plain_keys(const uint32_t* __restrict__
 // (qbits, one byte per position, written up to where every pixel of the tile
 // has terminated), or 0 when no pixel of the tile blended the record: the
 // backward then skips it without re-deriving alpha.
-template <int WPB, bool STATS>
+//
+// PERSIST: the grid is resident and each wavefront takes tiles from the
+// forward's tile queue until it runs dry (same per-tile work and results).
+template <int WPB, bool STATS, bool PERSIST>
 __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ ranges,
                                                          const uint32_t* __restrict__ inst_rec,
                                                          const float4* __restrict__ rec,
                                                          uint8_t* __restrict__ qbits,
                                                          float* __restrict__ image, float* __restrict__ T_final,
-                                                         int32_t* __restrict__ n_last, int32_t* __restrict__ n_blend) {
+                                                         int32_t* __restrict__ n_last, int32_t* __restrict__ n_blend,
+                                                         DevCounters* __restrict__ cnt) {
     __shared__ float4 s_g[WPB][64];
     __shared__ float4 s_c[WPB][64];
     __shared__ float s_b[WPB][64];
     __shared__ uint32_t s_p[WPB][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
-    if (tile >= desc->n_tiles) return;
-    const int v = find_view_by_tile(desc, tile);
-    const ViewDesc& vd = desc->views[v];
-    const int64_t lt = tile - vd.tile_off;
-    const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
-    const int x0 = tx * kTile, y0 = ty * kTile;
-    const float bx0 = (float)x0, by0 = (float)y0;
-    const float bxm = (float)min(x0 + kTile - 1, vd.W - 1), bym = (float)min(y0 + kTile - 1, vd.H - 1);
+    uint32_t fetched = 0u;
+    if constexpr (PERSIST) fetched = fetch_pos(cnt->q_fwd, lane);
+    for (int it = 0;; ++it) {
+        int64_t tile;
+        if constexpr (PERSIST) {
+            tile = tile_at(desc, fetched);
+            if (tile < desc->n_tiles) fetched = fetch_pos(cnt->q_fwd, lane);   // the next one, waited for at the top
+        } else {
+            if (it > 0) break;
+            tile = __builtin_amdgcn_readfirstlane((int)tile_index(desc, blockIdx.x, gridDim.x, w, WPB));
+        }
+        if (tile >= desc->n_tiles) break;
+        const int v = find_view_by_tile(desc, tile);
+        const ViewDesc& vd = desc->views[v];
+        const int64_t lt = tile - vd.tile_off;
+        const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
+        const int x0 = tx * kTile, y0 = ty * kTile;
+        const float bx0 = (float)x0, by0 = (float)y0;
+        const float bxm = (float)min(x0 + kTile - 1, vd.W - 1), bym = (float)min(y0 + kTile - 1, vd.H - 1);
 
-    // T > 0 while the pixel is live; a finished (or outside) pixel keeps -T,
-    // so a dead lane takes the termination branch and changes nothing
-    float T[4], C0[4], C1[4], C2[4], fpx[4], fpy[4];
-    uint32_t last[4], nb[4];
+        // T > 0 while the pixel is live; a finished (or outside) pixel keeps -T,
+        // so a dead lane takes the termination branch and changes nothing
+        float T[4], C0[4], C1[4], C2[4], fpx[4], fpy[4];
+        uint32_t last[4], nb[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
-        T[k] = (px < vd.W && py < vd.H) ? 1.f : -1.f;
-        C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
-        fpx[k] = (float)px;
-        fpy[k] = (float)py;
-    }
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    for (uint32_t b = start; b < end; b += 64) {
-        if (__ballot((T[0] > 0.f) | (T[1] > 0.f) | (T[2] > 0.f) | (T[3] > 0.f)) == 0ull) break;
-        const uint32_t idx = b + lane;
-        uint32_t qm = 0u;
-        float4 g, c;
-        float bl = 0.f;
-        if (idx < end) {
-            const int64_t r = inst_rec[idx];
-            g = rec[kRecF4 * r + 0];
-            c = rec[kRecF4 * r + 1];
-            bl = rec[kRecF4 * r + 2].x;
-            qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
+        for (int k = 0; k < 4; ++k) {
+            const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
+            T[k] = (px < vd.W && py < vd.H) ? 1.f : -1.f;
+            C0[k] = C1[k] = C2[k] = 0.f; last[k] = 0; nb[k] = 0;
+            fpx[k] = (float)px;
+            fpy[k] = (float)py;
         }
-        const uint64_t km = __ballot(qm != 0u);
-        const uint32_t mine = popc_below(km);
-        if (qm != 0u) {
-            s_g[w][mine] = g;
-            s_c[w][mine] = c;
-            s_b[w][mine] = bl;
-            s_p[w][mine] = ((idx - start + 1u) << 4) | qm;
-        }
-        wave_sync();
-        const int cnt = (int)__popcll(km);
-        uint64_t hit = 0ull;     // staged records this lane blended (bit j)
-        for (int j = 0; j < cnt; ++j) {
-            // quadrants with a live pixel (wave-uniform)
-            uint32_t qlive = 0u;
+        const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+        for (uint32_t b = start; b < end; b += 64) {
+            if (__ballot((T[0] > 0.f) | (T[1] > 0.f) | (T[2] > 0.f) | (T[3] > 0.f)) == 0ull) break;
+            const uint32_t idx = b + lane;
+            uint32_t qm = 0u;
+            float4 g, c;
+            float bl = 0.f;
+            if (idx < end) {
+                const int64_t r = inst_rec[idx];
+                g = rec[kRecF4 * r + 0];
+                c = rec[kRecF4 * r + 1];
+                bl = rec[kRecF4 * r + 2].x;
+                qm = quadrant_mask(g, c, bx0, by0, bxm, bym);
+            }
+            const uint64_t km = __ballot(qm != 0u);
+            const uint32_t mine = popc_below(km);
+            if (qm != 0u) {
+                s_g[w][mine] = g;
+                s_c[w][mine] = c;
+                s_b[w][mine] = bl;
+                s_p[w][mine] = ((idx - start + 1u) << 4) | qm;
+            }
+            wave_sync();
+            const int cnt = (int)__popcll(km);
+            uint64_t hit = 0ull;     // staged records this lane blended (bit j)
+            for (int j = 0; j < cnt; ++j) {
+                // quadrants with a live pixel (wave-uniform)
+                uint32_t qlive = 0u;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (__ballot(T[k] > 0.f) != 0ull) qlive |= 1u << k;
-            if (qlive == 0u) break;
-            const float4 gg = s_g[w][j];
-            const float4 cc = s_c[w][j];
-            const float bb = s_b[w][j];
-            const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
-            const uint32_t pos = pq >> 4;
-            const uint32_t act = pq & qlive;
-            const uint64_t jbit = 1ull << j;
+                for (int k = 0; k < 4; ++k)
+                    if (__ballot(T[k] > 0.f) != 0ull) qlive |= 1u << k;
+                if (qlive == 0u) break;
+                const float4 gg = s_g[w][j];
+                const float4 cc = s_c[w][j];
+                const float bb = s_b[w][j];
+                const uint32_t pq = __builtin_amdgcn_readfirstlane(s_p[w][j]);
+                const uint32_t pos = pq >> 4;
+                const uint32_t act = pq & qlive;
+                const uint64_t jbit = 1ull << j;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!((act >> k) & 1u)) continue;          // wave-uniform quadrant skip
-                const float dx = fpx[k] - gg.x;
-                const float dy = fpy[k] - gg.y;
-                float G;
-                bool pcl;
-                const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
-                if (alpha < kMinAlpha) continue;
-                const float Tn = T[k] * (1.f - alpha);
-                if (Tn < kMinT) {      // finished here (or already): keep -T
-                    T[k] = -fabsf(T[k]);
-                    continue;
+                for (int k = 0; k < 4; ++k) {
+                    if (!((act >> k) & 1u)) continue;          // wave-uniform quadrant skip
+                    const float dx = fpx[k] - gg.x;
+                    const float dy = fpy[k] - gg.y;
+                    float G;
+                    bool pcl;
+                    const float alpha = blend_alpha(dx, dy, gg, cc, G, pcl);
+                    if (alpha < kMinAlpha) continue;
+                    const float Tn = T[k] * (1.f - alpha);
+                    if (Tn < kMinT) {      // finished here (or already): keep -T
+                        T[k] = -fabsf(T[k]);
+                        continue;
+                    }
+                    const float wgt = alpha * T[k];
+                    C0[k] = fmaf(wgt, cc.z, C0[k]);
+                    C1[k] = fmaf(wgt, cc.w, C1[k]);
+                    C2[k] = fmaf(wgt, bb, C2[k]);
+                    T[k] = Tn;
+                    last[k] = pos;
+                    hit |= jbit;           // this lane blended staged record j
+                    if constexpr (STATS) ++nb[k];
                 }
-                const float wgt = alpha * T[k];
-                C0[k] = fmaf(wgt, cc.z, C0[k]);
-                C1[k] = fmaf(wgt, cc.w, C1[k]);
-                C2[k] = fmaf(wgt, bb, C2[k]);
-                T[k] = Tn;
-                last[k] = pos;
-                hit |= jbit;           // this lane blended staged record j
-                if constexpr (STATS) ++nb[k];
+            }
+            const uint32_t hit_lo = wave_or_u32((uint32_t)hit), hit_hi = wave_or_u32((uint32_t)(hit >> 32));
+            const uint32_t blended = mine < 32 ? (hit_lo >> mine) & 1u : (hit_hi >> (mine - 32)) & 1u;
+            if (idx < end) qbits[idx] = (qm != 0u && blended) ? (uint8_t)qm : (uint8_t)0;
+            wave_sync();
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
+            if (px < vd.W && py < vd.H) {
+                const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
+                const float Tk = fabsf(T[k]);
+                image[3 * p + 0] = C0[k] + Tk * vd.bg[0];
+                image[3 * p + 1] = C1[k] + Tk * vd.bg[1];
+                image[3 * p + 2] = C2[k] + Tk * vd.bg[2];
+                T_final[p] = Tk;
+                n_last[p] = (int32_t)last[k];
+                if constexpr (STATS) n_blend[p] = (int32_t)nb[k];
             }
         }
-        const uint32_t hit_lo = wave_or_u32((uint32_t)hit), hit_hi = wave_or_u32((uint32_t)(hit >> 32));
-        const uint32_t blended = mine < 32 ? (hit_lo >> mine) & 1u : (hit_hi >> (mine - 32)) & 1u;
-        if (idx < end) qbits[idx] = (qm != 0u && blended) ? (uint8_t)qm : (uint8_t)0;
-        wave_sync();
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
-        if (px < vd.W && py < vd.H) {
-            const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
-            const float Tk = fabsf(T[k]);
-            image[3 * p + 0] = C0[k] + Tk * vd.bg[0];
-            image[3 * p + 1] = C1[k] + Tk * vd.bg[1];
-            image[3 * p + 2] = C2[k] + Tk * vd.bg[2];
-            T_final[p] = Tk;
-            n_last[p] = (int32_t)last[k];
-            if constexpr (STATS) n_blend[p] = (int32_t)nb[k];
-        }
-    }
+    if constexpr (PERSIST) retire_wave(cnt->q_fwd, &cnt->done_fwd, (unsigned long long)gridDim.x * WPB, lane);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -389,12 +413,27 @@ hipError_t launch_plain_keys(const uint32_t* stile, const uint32_t* sgid, const 
     return hipGetLastError();
 }
 
-hipError_t launch_blend_fwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, const uint32_t* ranges,
+
+hipError_t launch_blend_fwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, bool persist, const uint32_t* ranges,
                             const uint32_t* inst_rec, const float4* rec, uint8_t* qbits,
-                            float* image, float* T_final, int32_t* n_last, int32_t* n_blend, hipStream_t st) {
+                            float* image, float* T_final, int32_t* n_last, int32_t* n_blend, DevCounters* cnt,
+                            hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-#define CGS_BF(W, S) hipLaunchKernelGGL((k_blend_fwd<W, S>), dim3((unsigned)((n_tiles + W - 1) / W)), dim3(W * 64), \
-                                        0, st, d_desc, ranges, inst_rec, rec, qbits, image, T_final, n_last, n_blend)
+    if (persist) {
+#define CGS_BFP(S)                                                                                              \
+    do {                                                                                                        \
+        const int64_t nb = std::min<int64_t>(n_tiles, resident_blocks(reinterpret_cast<const void*>(&k_blend_fwd<1, S, true>), 64));            \
+        if (nb <= 0) return hipErrorInvalidValue;                                                               \
+        hipLaunchKernelGGL((k_blend_fwd<1, S, true>), dim3((unsigned)nb), dim3(64), 0, st, d_desc, ranges,       \
+                           inst_rec, rec, qbits, image, T_final, n_last, n_blend, cnt);                         \
+    } while (0)
+        if (n_blend) CGS_BFP(true); else CGS_BFP(false);
+#undef CGS_BFP
+        return hipGetLastError();
+    }
+#define CGS_BF(W, S) hipLaunchKernelGGL((k_blend_fwd<W, S, false>), dim3((unsigned)((n_tiles + W - 1) / W)), \
+                                        dim3(W * 64), 0, st, d_desc, ranges, inst_rec, rec, qbits, image, T_final, \
+                                        n_last, n_blend, cnt)
     if (n_blend) {
         if (wpb == 1) CGS_BF(1, true); else if (wpb == 2) CGS_BF(2, true); else CGS_BF(4, true);
     } else {

@@ -7,6 +7,8 @@
 // per-tile digit states are published tile-major ([tile][digit], 64-bit
 // words: a 2-bit state, how far back the sum reaches, the sum) for the
 // look-back.
+#include <mutex>
+
 #include "cgs_internal.h"
 
 namespace cgs {
@@ -496,6 +498,25 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
     }
     *err = hipGetLastError();
     return final_buf;
+}
+
+int64_t resident_blocks(const void* kernel, int block) {
+    struct Entry { int dev, block; const void* kernel; int64_t n; };
+    static Entry table[64];
+    static int used = 0;
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < used; ++i)
+        if (table[i].dev == dev && table[i].kernel == kernel && table[i].block == block) return table[i].n;
+    int ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || ncu <= 0)
+        return 0;
+    const int64_t n = (int64_t)ncu * (per > 0 ? per : 1);
+    if (used < 64) table[used++] = Entry{dev, block, kernel, n};
+    return n;
 }
 
 uint32_t sort_stalls() {

@@ -129,7 +129,7 @@ class Renderer:
 
     def __init__(self, scenes: Sequence[DeviceScene], cameras: Sequence[sc.Camera],
                  view_scene: Sequence[int], capacity: Optional[int] = None,
-                 waves_per_block: int = 1, tile_order: int = 0, device="cuda"):
+                 waves_per_block: int = 1, tile_order: int = 0, device="cuda", persistent: int = 0):
         self.scenes = list(scenes)
         self.cameras = list(cameras)
         self.device = torch.device(device)
@@ -141,6 +141,7 @@ class Renderer:
         self._sched = cgs.Schedule()
         self._sched.blend_waves_per_block = waves_per_block
         self._sched.tile_order = tile_order
+        self._sched.persistent = persistent
         self.n_pixels = sum(c.width * c.height for c in self.cameras)
         self.pix_off = np.concatenate([[0], np.cumsum([c.width * c.height for c in self.cameras])]).astype(np.int64)
         if capacity is None:
@@ -191,15 +192,17 @@ class Renderer:
         self._grads = (cgs.SceneGrads * ns)(*gr)
         self.set_capacity(capacity)
 
-    def set_schedule(self, waves_per_block: int, tile_order: int) -> None:
+    def set_schedule(self, waves_per_block: int, tile_order: int, persistent: int = 0) -> None:
         """Change the blend launch schedule (issue order only; results are
         bitwise unchanged)."""
         self._sched.blend_waves_per_block = int(waves_per_block)
         self._sched.tile_order = int(tile_order)
+        self._sched.persistent = int(persistent)
 
     @property
     def schedule(self):
-        return int(self._sched.blend_waves_per_block or 1), int(self._sched.tile_order)
+        return (int(self._sched.blend_waves_per_block or 1), int(self._sched.tile_order),
+                int(self._sched.persistent))
 
     def set_capacity(self, capacity: int) -> None:
         self.capacity = int(capacity)

@@ -180,25 +180,31 @@ def test_determinism():
 
 @pytest.mark.parametrize("kind", ["scenes3", "views3"])
 def test_schedule_invariance(kind):
-    """Waves per workgroup and tile order change only the issue order: every
-    output (image, T, n_last, every gradient) is bitwise the same."""
+    """Waves per workgroup, tile order and the persistent tile queue change
+    only the issue order: every output (image, T, n_last, every gradient) is
+    bitwise the same.  A persistent renderer also runs the step twice more,
+    the second time with two backwards after one forward, which needs each
+    launch to leave its tile queue reset for the next."""
     wl = small_workload(kind)
     g = torch.from_numpy(np.random.default_rng(6).standard_normal((sum(c.width * c.height for c in wl.cameras), 3))
                          .astype(np.float32) * 1e-5).cuda()
     ref = None
-    for wpb, order in ((1, 0), (2, 1), (4, 2), (1, 2), (2, 2)):
-        say(f"[schedule] {kind} waves_per_block={wpb} tile_order={order}")
-        r = gpu_renderer(wl, waves_per_block=wpb, tile_order=order)
-        r.forward()
-        _, gcb = r.backward(g)
-        torch.cuda.synchronize()
-        out = [r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()]
-        out += [x.cpu().numpy() for x in gcb] + [x.cpu().numpy() for x in r.grad_means]
-        if ref is None:
-            ref = out
-            continue
-        for a, b in zip(ref, out):
-            np.testing.assert_array_equal(a, b)
+    for wpb, order, pers in ((1, 0, 0), (2, 1, 0), (4, 2, 0), (1, 2, 0), (2, 2, 0), (1, 0, 1), (1, 2, 1)):
+        say(f"[schedule] {kind} waves_per_block={wpb} tile_order={order} persistent={pers}")
+        r = gpu_renderer(wl, waves_per_block=wpb, tile_order=order, persistent=pers)
+        for rep in range(3 if pers else 1):
+            r.forward()
+            if rep == 2:
+                r.backward(g)
+            _, gcb = r.backward(g)
+            torch.cuda.synchronize()
+            out = [r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()]
+            out += [x.cpu().numpy() for x in gcb] + [x.cpu().numpy() for x in r.grad_means]
+            if ref is None:
+                ref = out
+                continue
+            for a, b in zip(ref, out):
+                np.testing.assert_array_equal(a, b)
 
 
 def _bin_inputs(seed, n, tx, ty, V, ties=True):
