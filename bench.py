@@ -278,7 +278,7 @@ def pair_counts(form: Form):
     return e_eval, e_blend, walked
 
 
-def cpu_baseline(wl: sc.Workload, target_s: float):
+def cpu_baseline(wl: sc.Workload, target_s: float, full_frames=("uniform4k_128px",)):
     """The FP64 oracle on a bounded sample of the same workload: forward, L1
     gradient and backward of randomly chosen 16x16 tiles of view 0."""
     import oracle
@@ -324,7 +324,7 @@ def cpu_baseline(wl: sc.Workload, target_s: float):
     model, affinity, nproc = host_cpu()
     return {"value": npix / dt / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "cpu": model, "affinity": affinity, "nproc": nproc, "forward_value": npix / dt_fwd / 1e6,
-            "full_frame": [cpu_full_frame("uniform4k_128px")],
+            "full_frame": [cpu_full_frame(n) for n in full_frames],
             "sample": f"{ntiles} random 16x16 tiles ({npix} px) of view 0 of {wl.name}: FP64 forward, "
                       f"L1 gradient and backward incl. codebook reduction, {dt:.1f} s"}, last
 
@@ -368,14 +368,17 @@ def cpu_full_frame(name: str):
     wl = sc.make_workload(name)
     s, cam = wl.scenes[int(wl.view_scene[0])], wl.cameras[0]
     P = cam.width * cam.height
+    log(f"[bench] oracle full frame of {name}: forward")
     t0 = time.perf_counter()
     o = oracle.render_view(s, cam)
     t_fwd = time.perf_counter() - t0
+    log(f"[bench] oracle full frame of {name}: forward {t_fwd:.1f} s, now L1 gradient and backward")
     tgt = wl.targets[0].reshape(-1, 3).astype(np.float64)
     g = np.sign(o["color"] - tgt) / (3.0 * P)
     o2 = oracle.render_view(s, cam, grad_color=g)
     oracle.codebook_grad_reduce(o2["grad_rows"], s.idx, s.k)
     t_all = time.perf_counter() - t0
+    log(f"[bench] oracle full frame of {name}: forward + backward {t_all:.1f} s")
     return {"workload": name, "pixels": P, "forward": P / t_fwd / 1e6, "forward_backward": P / t_all / 1e6,
             "unit": "Mpixel/s"}
 
@@ -571,6 +574,9 @@ def main():
                     help="comma list of: fp32_plain, 1m, uncompressed, uneven16, graph; or none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-full-frame", default="uniform4k_128px",
+                    help="comma list of workloads whose first view the oracle renders in full "
+                         "(clusters200k_800px adds about two minutes)")
     ap.add_argument("--schedule", default="auto",
                     help="blend schedule 'W,O' (waves per workgroup, tile order) or 'auto' to time the candidates")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -624,7 +630,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s) and the oracle check of its sample")
-        cpu, sample = cpu_baseline(wl, args.cpu_seconds)
+        cpu, sample = cpu_baseline(wl, args.cpu_seconds,
+                                   tuple(x for x in args.cpu_full_frame.split(",") if x))
         extra_info["oracle_parity"] = oracle_parity(head, sample)
         del sample
     if "graph" in extras:
