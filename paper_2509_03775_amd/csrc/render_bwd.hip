@@ -66,7 +66,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
         const int tx = (int)(lt % vd.tiles_x), ty = (int)(lt / vd.tiles_x);
         const int x0 = tx * kTile, y0 = ty * kTile;
 
-        float T[4], dC0[4], dC1[4], dC2[4], bh0[4], bh1[4], bh2[4], fpx[4], fpy[4];
+        // Bh[k]: dL/dC . (colour composited behind the current position,
+        // normalised to unit transmittance), starting from the background --
+        // dL/dC is fixed per pixel, so one scalar replaces the three channels
+        float T[4], dC0[4], dC1[4], dC2[4], Bh[4], fpx[4], fpy[4];
         uint32_t last[4];
         uint32_t maxlast = 0;
 #pragma unroll
@@ -74,7 +77,6 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             const int px = x0 + 8 * (k & 1) + (lane & 7), py = y0 + 8 * (k >> 1) + (lane >> 3);
             fpx[k] = (float)px;
             fpy[k] = (float)py;
-            bh0[k] = vd.bg[0]; bh1[k] = vd.bg[1]; bh2[k] = vd.bg[2];
             if (px < vd.W && py < vd.H) {
                 const int64_t p = vd.pix_off + (int64_t)py * vd.W + px;
                 T[k] = T_final[p];
@@ -85,6 +87,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
             } else {
                 T[k] = 1.f; last[k] = 0; dC0[k] = dC1[k] = dC2[k] = 0.f;
             }
+            Bh[k] = fmaf(dC0[k], vd.bg[0], fmaf(dC1[k], vd.bg[1], dC2[k] * vd.bg[2]));
             maxlast = last[k] > maxlast ? last[k] : maxlast;
         }
         maxlast = wave_max_u32(maxlast);
@@ -156,17 +159,17 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
                     // Branch-free for the lanes of the quadrant: pairs the forward
                     // did not blend get alpha 0 and zero gradients, which leaves T
                     // and the background sum unchanged.
+                    // (rcp(1) = 1 exactly, so an unused pair leaves T as it is)
                     const float am = use ? alpha : 0.f;
-                    const float Tb = use ? T[k] * __builtin_amdgcn_rcpf(1.f - alpha) : T[k];
+                    const float Tb = T[k] * __builtin_amdgcn_rcpf(1.f - am);
                     const float wgt = am * Tb;
                     a_r = fmaf(wgt, dC0[k], a_r);
                     a_g = fmaf(wgt, dC1[k], a_g);
                     a_bl = fmaf(wgt, dC2[k], a_bl);
-                    const float e0 = cc.z - bh0[k], e1 = cc.w - bh1[k], e2 = bb - bh2[k];
-                    const float dal = Tb * fmaf(dC0[k], e0, fmaf(dC1[k], e1, dC2[k] * e2));
-                    bh0[k] = fmaf(am, e0, bh0[k]);
-                    bh1[k] = fmaf(am, e1, bh1[k]);
-                    bh2[k] = fmaf(am, e2, bh2[k]);
+                    // dL/dalpha = T_before (dL/dC . c - Bh); Bh <- Bh + alpha (dL/dC . c - Bh)
+                    const float e = fmaf(dC0[k], cc.z, fmaf(dC1[k], cc.w, dC2[k] * bb)) - Bh[k];
+                    const float dal = Tb * e;
+                    Bh[k] = fmaf(am, e, Bh[k]);
                     T[k] = Tb;
                     const bool open = use && (alpha < kMaxAlpha);      // alpha not saturated at 0.99
                     const float dao = open ? dal : 0.f;
