@@ -24,6 +24,9 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
     const int64_t q = wv - sd.wave_off;            // the wave's 64-Gaussian chunk of its scene
     const int64_t g = q * kWave + lane;
     const bool inb = g < sd.n;                     // lanes past the scene's end write nothing
+    const int64_t nvalid = sd.n - q * kWave < kWave ? sd.n - q * kWave : kWave;   // the wave's records per view
+    __shared__ float4 s_rec[4][kRecF4 * kWave];
+    const int w = (int)(threadIdx.x >> 6);
 
     GaussParams gp;
     const bool valid = inb && load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
@@ -44,33 +47,41 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         const uint32_t nt = keep ? (uint32_t)((vp.tx1 - vp.tx0) * (vp.ty1 - vp.ty0)) : 0u;
         const uint32_t incl = wave_incl_sum_u32(nt, lane);
         if (lane == 63) chunk_tot[vd.rec_wave_off + q] = incl;
-        if (!inb) continue;
-        if (!keep) {
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = make_float4(0.f, 0.f, 0.f, __uint_as_float(incl - nt));
+        if (inb && !keep) {
             depth_key[r] = kCulledKey;
             tile_rect[r] = make_uint2(0u, 0u);
             ntiles[r] = 0u;
             if (desc->pack_rect) prect[r] = 0u;
-            rec[kRecF4 * r + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[kRecF4 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[kRecF4 * r + 2] = make_float4(0.f, 0.f, 0.f, __uint_as_float(incl - nt));
-            rec[kRecF4 * r + 3] = make_float4(0.f, 0.f, 0.f, 0.f);
-            continue;
+        } else if (inb) {
+            float A, B, C;
+            conic_of(vp.a, vp.b, vp.c, A, B, C);
+            float col[3];
+            sh_colour<SHD>(vd, gp, col, nullptr);
+            depth_key[r] = __float_as_uint(vp.zc);
+            const uint32_t rlo = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16);
+            const uint32_t rhi = (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16);
+            tile_rect[r] = make_uint2(rlo, rhi);
+            ntiles[r] = nt;
+            if (desc->pack_rect)
+                prect[r] = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 8) | ((uint32_t)vp.tx1 << 16) |
+                           ((uint32_t)vp.ty1 << 24);
+            r0 = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
+            r1 = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
+            r2 = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), __uint_as_float(incl - nt));
         }
-        float A, B, C;
-        conic_of(vp.a, vp.b, vp.c, A, B, C);
-        float col[3];
-        sh_colour<SHD>(vd, gp, col, nullptr);
-        depth_key[r] = __float_as_uint(vp.zc);
-        const uint32_t rlo = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16);
-        const uint32_t rhi = (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16);
-        tile_rect[r] = make_uint2(rlo, rhi);
-        ntiles[r] = nt;
-        if (desc->pack_rect)
-            prect[r] = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 8) | ((uint32_t)vp.tx1 << 16) | ((uint32_t)vp.ty1 << 24);
-        rec[kRecF4 * r + 0] = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
-        rec[kRecF4 * r + 1] = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
-        rec[kRecF4 * r + 2] = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), __uint_as_float(incl - nt));
-        rec[kRecF4 * r + 3] = make_float4(0.f, 0.f, 0.f, 0.f);   // whole 64-byte lines are written
+        // The wave's records are one contiguous 4 KB block: staged in LDS and
+        // written 1 KB per store instruction (whole lines), padding included.
+        s_rec[w][kRecF4 * lane + 0] = r0;
+        s_rec[w][kRecF4 * lane + 1] = r1;
+        s_rec[w][kRecF4 * lane + 2] = r2;
+        s_rec[w][kRecF4 * lane + 3] = make_float4(0.f, 0.f, 0.f, 0.f);
+        wave_sync();
+        float4* dst = rec + kRecF4 * (vd.rec_off + q * kWave);
+#pragma unroll
+        for (int t = 0; t < kRecF4; ++t)
+            if (t * kWave + lane < kRecF4 * nvalid) dst[t * kWave + lane] = s_rec[w][t * kWave + lane];
+        wave_sync();
         (void)NCO;
     }
 }
