@@ -657,32 +657,34 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
                                                const uint32_t* __restrict__ rec_flag,
                                                float* __restrict__ gtheta, uint32_t* __restrict__ isl_flag) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
+    constexpr int RW = 8 + 3 * NCO;                      // the row width of the batch's SH degree
+    constexpr int kHalf = 32;                            // rows staged per round
+    // Per wave: half of its gradient rows at a time, written out as whole
+    // lines (a lane's own 16-byte stores would touch a line per lane).
+    // Staging the record gradients the same way costs 20 registers and a
+    // wave per SIMD, more than it saves.
+    __shared__ __align__(16) float s_stage[4][kHalf * RW];
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
     const int s = find_scene_by_wave(desc, wv);
     const SceneDesc& sd = desc->scenes[s];
-    const int64_t g = (wv - sd.wave_off) * kWave + (threadIdx.x & 63);
-    if (g >= sd.n) return;
-    const int64_t gg = sd.g_off + g;
-    const int RW = desc->row_width;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = wv - sd.wave_off;
+    const int64_t g = q * kWave + lane;
+    const bool inb = g < sd.n;                  // every lane stays: the staging is wave-wide
+    const int nrows = (int)(sd.n - q * kWave < kWave ? sd.n - q * kWave : kWave);
+    float* stg = s_stage[w];
 
     GaussParams gp;
-    float* out = gtheta + gg * RW;
-    if (!load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0)) {
-        for (int i = 0; i < RW; ++i) out[i] = 0.f;
-        if (sd.g_means) { sd.g_means[3 * g] = 0.f; sd.g_means[3 * g + 1] = 0.f; sd.g_means[3 * g + 2] = 0.f; }
-        if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = 0.f;
-        if (desc->sgld) {
-            const float zero3[3] = {0.f, 0.f, 0.f};
-            sgld_gaussian(desc, sd, s, g, zero3, 0.f);
-        }
-        return;
-    }
+    const bool valid = inb && load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
     GaussShape sh;
-    gaussian_shape(gp, sh);
-    const float opac = 1.0f / (1.0f + __expf(-gp.logit));
+    float opac = 0.f;
     ShRegs<DT, SHD> shc;
-    shc.load(sd, g, gp, desc->vec_rows != 0);
+    if (valid) {
+        gaussian_shape(gp, sh);
+        opac = 1.0f / (1.0f + __expf(-gp.logit));
+        shc.load(sd, g, gp, desc->vec_rows != 0);
+    }
 
     float dmu[3] = {0.f, 0.f, 0.f};
     float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
@@ -691,19 +693,20 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
     for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
     float dop = 0.f;
     // dL/d(record) of the next view is loaded while this view's math runs
-    float dn[9];
-    auto load_rec = [&](int vi, float* out9) {
+    // (no load for records with a zero sum).
+    float pre[9];
+    auto fetch_rec = [&](int vi) {
         const ViewDesc& v = desc->views[desc->view_list[sd.vfirst + vi]];
-        const int64_t fw = 2 * (v.rec_wave_off + (g >> 6)) + ((g >> 5) & 1);
+        const int64_t fw = 2 * (v.rec_wave_off + q);
+        const uint64_t m = (uint64_t)rec_flag[fw] | ((uint64_t)rec_flag[fw + 1] << 32);
+        const float* src = rec_grad + 9 * (v.rec_off + g);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out9[i] = 0.f;
-        if ((rec_flag[fw] >> (g & 31)) & 1u) {      // no load for records with a zero sum
-            const float* src = rec_grad + 9 * (v.rec_off + g);
+        for (int i = 0; i < 9; ++i) pre[i] = 0.f;
+        if ((m >> lane) & 1ull)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) out9[i] = src[i];
-        }
+            for (int i = 0; i < 9; ++i) pre[i] = src[i];
     };
-    if (sd.vcount > 0) load_rec(0, dn);
+    if (sd.vcount > 0) fetch_rec(0);
 
     bool isl = false;
     for (int vi = 0; vi < sd.vcount; ++vi) {
@@ -711,12 +714,12 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         const ViewDesc& vd = desc->views[v];
         float d[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = dn[i];
-        if (vi + 1 < sd.vcount) load_rec(vi + 1, dn);
+        for (int i = 0; i < 9; ++i) d[i] = pre[i];
+        if (vi + 1 < sd.vcount) fetch_rec(vi + 1);
         bool nz = false;
 #pragma unroll
         for (int i = 0; i < 9; ++i) nz |= d[i] != 0.f;
-        if (!nz) continue;
+        if (!nz || !valid) continue;
         ViewProj p;
         if (!project_view(vd, gp.mean, sh, p)) continue;
         float A, B, C;
@@ -733,19 +736,68 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
             chain_colour<DT, SHD>(vd, gp, shc, d, dk, nullptr);
         }
     }
-    // the shape again (bitwise the same) rather than R, M held across the loop
+    float dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dlogit = 0.f;
+    if (valid) {
+        // the shape again (bitwise the same) rather than R, M held across the loop
 #pragma unroll
-    for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(gp.ls[i]));
+        for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(gp.ls[i]));
 #pragma unroll
-    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(gp.q[i]));
-    gaussian_shape(gp, sh);
-    float ds[3], dq[4];
-    chain_shape<float>(dSig, sh, ds, dq);
-    const float dlogit = dop * opac * (1.f - opac);
-    const float dls[3] = {ds[0] * sh.s[0], ds[1] * sh.s[1], ds[2] * sh.s[2]};
-    store_gaussian_grad<SHD>(sd, out, g, dls, dq, dlogit, dk, dmu);
-    if (isl) atomicOr(&isl_flag[2 * wv + ((threadIdx.x & 63) >> 5)], 1u << (threadIdx.x & 31));
-    else if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmu, dlogit);
+        for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(gp.q[i]));
+        gaussian_shape(gp, sh);
+        float ds[3];
+        chain_shape<float>(dSig, sh, ds, dq);
+        dlogit = dop * opac * (1.f - opac);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dls[i] = ds[i] * sh.s[i];
+    }
+    if (inb) {
+        if (sd.g_means) {
+            sd.g_means[3 * g + 0] = dmu[0];
+            sd.g_means[3 * g + 1] = dmu[1];
+            sd.g_means[3 * g + 2] = dmu[2];
+        }
+        if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
+    }
+    // rows [sd.g_off + 64 q, + nrows) are contiguous: two rounds of 32
+    float* rows = gtheta + (sd.g_off + q * kWave) * RW;
+#pragma unroll
+    for (int h = 0; h < kWave / kHalf; ++h) {
+        const int nr = nrows - h * kHalf < kHalf ? nrows - h * kHalf : kHalf;
+        if (nr <= 0) break;
+        if (lane >= h * kHalf && lane < h * kHalf + nr) {
+            float* o = stg + (lane - h * kHalf) * RW;
+            o[0] = dls[0]; o[1] = dls[1]; o[2] = dls[2];
+            o[3] = dq[0]; o[4] = dq[1]; o[5] = dq[2]; o[6] = dq[3];
+            o[7] = dlogit;
+#pragma unroll
+            for (int i = 0; i < 3 * NCO; ++i) o[8 + i] = dk[i];
+        }
+        wave_sync();
+        float* dst = rows + (int64_t)h * kHalf * RW;
+        if constexpr (RW % 4 == 0) {      // 16-byte aligned rows: one float4 per lane per store
+            const int n4 = nr * (RW / 4);
+            const float4* s4 = reinterpret_cast<const float4*>(stg);
+#pragma unroll
+            for (int it = 0; it < (kHalf * RW / 4 + kWave - 1) / kWave; ++it) {
+                const int t = it * kWave + lane;
+                if (t < n4) reinterpret_cast<float4*>(dst)[t] = s4[t];
+                asm volatile("" ::: "memory");   // one float4 in flight: no registers held for the copy
+            }
+        } else {
+            const int n1 = nr * RW;
+#pragma unroll
+            for (int it = 0; it < (kHalf * RW + kWave - 1) / kWave; ++it) {
+                const int t = it * kWave + lane;
+                if (t < n1) dst[t] = stg[t];
+                asm volatile("" ::: "memory");
+            }
+        }
+        wave_sync();
+    }
+    if (inb) {
+        if (isl) atomicOr(&isl_flag[2 * wv + (lane >> 5)], 1u << (lane & 31));
+        else if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmu, dlogit);
+    }
 }
 
 // The chain rule of the Gaussians k_chain marked, in FP64 from the conic on:
