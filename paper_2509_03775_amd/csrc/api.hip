@@ -28,9 +28,12 @@ hipError_t launch_blend_fwd(const BatchDesc*, int64_t, int, bool, const uint32_t
 hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, bool, const uint32_t*, const uint32_t*, const float4*,
                             const uint8_t*, const uint32_t*, const uint32_t*, const float*, const float*,
                             const int32_t*, float*, uint2*, DevCounters*, hipStream_t);
-hipError_t launch_chain(const BatchDesc*, int, int, int64_t, int64_t, const float*, const uint32_t*, const uint32_t*,
-                        const uint2*, const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*, float*,
-                        uint32_t*, hipStream_t);
+hipError_t launch_slot_sum(const BatchDesc*, int64_t, const float*, const uint32_t*, const uint32_t*, const uint2*,
+                           const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*, hipStream_t);
+hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const uint32_t*, float*, uint32_t*,
+                        const uint32_t*, const uint32_t*, const uint32_t*, float*, hipStream_t);
+hipError_t launch_merge_rows(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const float*, const float*,
+                             const uint32_t*, int, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
@@ -56,7 +59,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
     size_t radix_ws, scan_bsum, scan_bsum2;
-    size_t chunk_tot, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, psort_key[2], psort_val[2], row_start;
+    size_t chunk_tot, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, rpart, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t scan_blocks_max;
 };
@@ -263,6 +266,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.rec_flag = take(8 * (size_t)d.n_rec_waves + 8);
     p.isl_flag = take(8 * (size_t)d.n_gauss_waves + 8);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
+    p.rpart = take(4 * (size_t)d.row_width * 2 * (size_t)d.n_gauss_waves);    // head and tail partial per wavefront
     for (int i = 0; i < 2; ++i) { p.psort_key[i] = take(4 * (size_t)G); p.psort_val[i] = take(4 * (size_t)G); }
     p.row_start = take(8 * (size_t)(h->rows_total + 1));
     p.total = o;
@@ -609,22 +613,35 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
                              grad_image, T_final, n_last, ginst, at<uint2>(ws, p.tile_cut), cnt, st));
     CGS_TRY(mark(h, 5, st));
     float* gth = at<float>(ws, p.gtheta);
-    CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.chunk_base),
-                         at<uint32_t>(ws, p.ntiles), at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key),
-                         at<uint2>(ws, p.tile_cut), cnt, at<float>(ws, p.rec_grad), at<uint32_t>(ws, p.rec_flag),
-                         gth, at<uint32_t>(ws, p.isl_flag), st));
-    CGS_TRY(mark(h, 6, st));
-    const int nparts = single ? 1 : 2;
-    for (int part_i = 0; part_i < nparts; ++part_i) {
-        const int64_t rows = part_i == 0 ? h.d.sr_rows_total : h.d.sh_rows_total;
-        int c0, D;
-        if (single) { c0 = 0; D = h.d.row_width; }
-        else if (part_i == 0) { c0 = 0; D = h.opacity_mode ? 8 : 7; }
-        else { c0 = 8; D = h.d.row_width - 8; }
+    float* rgrad = at<float>(ws, p.rec_grad);
+    uint32_t* rflag = at<uint32_t>(ws, p.rec_flag);
+    uint32_t* islf = at<uint32_t>(ws, p.isl_flag);
+    CGS_TRY(launch_slot_sum(dd, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.chunk_base), at<uint32_t>(ws, p.ntiles),
+                            at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key), at<uint2>(ws, p.tile_cut), cnt,
+                            rgrad, rflag, st));
+    if (single) {
+        // Single codebook: the chain rule walks the Gaussians in row order and
+        // reduces the rows itself (the row sort must be done first).
         int pb = pb0;
         if (side) CGS_TRY(guard.join());
-        else CGS_TRY(sort_rows(part_i, rows, st, &pb));
-        CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
+        else CGS_TRY(sort_rows(0, h.d.sr_rows_total, st, &pb));
+        CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, rgrad, rflag, gth, islf,
+                             pk[pb], pv[pb], rr, at<float>(ws, p.rpart), st));
+        CGS_TRY(mark(h, 6, st));
+        CGS_TRY(launch_merge_rows(dd, h.d.sr_rows_total, pv[pb], rr, at<float>(ws, p.rpart), gth, islf,
+                                  h.d.row_width, st));
+    } else {
+        CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, rgrad, rflag, gth, islf,
+                             nullptr, nullptr, nullptr, nullptr, st));
+        CGS_TRY(mark(h, 6, st));
+        for (int part_i = 0; part_i < 2; ++part_i) {
+            const int64_t rows = part_i == 0 ? h.d.sr_rows_total : h.d.sh_rows_total;
+            const int c0 = part_i == 0 ? 0 : 8;
+            const int D = part_i == 0 ? (h.opacity_mode ? 8 : 7) : h.d.row_width - 8;
+            int pb = 0;
+            CGS_TRY(sort_rows(part_i, rows, st, &pb));
+            CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
+        }
     }
     CGS_TRY(mark(h, 7, st));
     return CGS_OK;

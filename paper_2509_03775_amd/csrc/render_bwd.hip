@@ -645,36 +645,41 @@ __device__ inline void store_gaussian_grad(const SceneDesc& sd, float* out, int6
     if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
 }
 
-// One thread per Gaussian: recompute the projection of every view of its
-// scene, pull dL/d(record) back to dL/dmean and dL/d(row values), and write
-// the per-Gaussian row gradient [dls 3, dq 4, dlogit 1, dsh 3 NCO].  A
-// Gaussian whose footprint took the FP64 conic in some view (near-degenerate,
-// very elongated) is marked in isl_flag (a bit per Gaussian, two words per
-// wavefront, zeroed before the launch): k_chain_fp64 redoes its chain rule in
-// FP64 and overwrites what this kernel wrote, and applies its SGLD update.
-template <int DT, int SHD>
-__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ rec_grad,
-                                               const uint32_t* __restrict__ rec_flag,
-                                               float* __restrict__ gtheta, uint32_t* __restrict__ isl_flag) {
-    constexpr int NCO = (SHD + 1) * (SHD + 1);
-    constexpr int RW = 8 + 3 * NCO;                      // the row width of the batch's SH degree
-    constexpr int kHalf = 32;                            // rows staged per round
-    // Per wave: half of its gradient rows at a time, written out as whole
-    // lines (a lane's own 16-byte stores would touch a line per lane).
-    // Staging the record gradients the same way costs 20 registers and a
-    // wave per SIMD, more than it saves.
-    __shared__ __align__(16) float s_stage[4][kHalf * RW];
-    const int64_t wv = wave_id(4);
-    if (wv >= desc->n_gauss_waves) return;
-    const int s = find_scene_by_wave(desc, wv);
-    const SceneDesc& sd = desc->scenes[s];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t q = wv - sd.wave_off;
-    const int64_t g = q * kWave + lane;
-    const bool inb = g < sd.n;                  // every lane stays: the staging is wave-wide
-    const int nrows = (int)(sd.n - q * kWave < kWave ? sd.n - q * kWave : kWave);
-    float* stg = s_stage[w];
+// The codebook gradient row a global row index lands in.
+struct RowOut {
+    float* ptr;
+    int64_t stride;
+    int32_t col0;
+};
 
+__device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, int64_t* local, int* scene) {
+    int lo = 0, hi = desc->n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t off = part == 0 ? desc->scenes[mid].sr_row_off : desc->scenes[mid].sh_row_off;
+        if (off <= row) lo = mid; else hi = mid - 1;
+    }
+    const SceneDesc& sd = desc->scenes[lo];
+    *scene = lo;
+    if (part == 0) {
+        *local = row - sd.sr_row_off;
+        return RowOut{sd.g_sr, sd.g_sr_stride, sd.g_sr_col0};
+    }
+    *local = row - sd.sh_row_off;
+    return RowOut{sd.g_sh, sd.g_sh_stride, sd.g_sh_col0};
+}
+
+// The chain rule of one Gaussian (one lane): recompute the projection of
+// every view of its scene, pull dL/d(record) back to dL/dmean and to the row
+// gradient row = [dls 3, dq 4, dlogit 1, dsh 3 NCO].  Returns whether the
+// footprint took the FP64 conic in some view (near-degenerate, very
+// elongated): such a Gaussian's chain rule is redone in FP64 by
+// k_chain_fp64.  Lanes with !inb or an invalid row get zeros.
+template <int DT, int SHD>
+__device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const SceneDesc& sd, int64_t g, bool inb,
+                                      const float* __restrict__ rec_grad, const uint32_t* __restrict__ rec_flag,
+                                      float* row, float (&dmu)[3]) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
     GaussParams gp;
     const bool valid = inb && load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
     GaussShape sh;
@@ -685,24 +690,24 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         opac = 1.0f / (1.0f + __expf(-gp.logit));
         shc.load(sd, g, gp, desc->vec_rows != 0);
     }
-
-    float dmu[3] = {0.f, 0.f, 0.f};
+    dmu[0] = dmu[1] = dmu[2] = 0.f;
     float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-    float dk[48];
+    float* dk = row + 8;
 #pragma unroll
     for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
     float dop = 0.f;
     // dL/d(record) of the next view is loaded while this view's math runs
-    // (no load for records with a zero sum).
+    // (no load for records with a zero sum: one flag bit per record, two
+    // words per wavefront of the view's records)
     float pre[9];
     auto fetch_rec = [&](int vi) {
         const ViewDesc& v = desc->views[desc->view_list[sd.vfirst + vi]];
-        const int64_t fw = 2 * (v.rec_wave_off + q);
-        const uint64_t m = (uint64_t)rec_flag[fw] | ((uint64_t)rec_flag[fw + 1] << 32);
+        uint32_t fw = 0u;
+        if (inb) fw = rec_flag[2 * (v.rec_wave_off + (g >> 6)) + ((g >> 5) & 1)];
         const float* src = rec_grad + 9 * (v.rec_off + g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) pre[i] = 0.f;
-        if ((m >> lane) & 1ull)
+        if ((fw >> (g & 31)) & 1u)
 #pragma unroll
             for (int i = 0; i < 9; ++i) pre[i] = src[i];
     };
@@ -736,7 +741,8 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
             chain_colour<DT, SHD>(vd, gp, shc, d, dk, nullptr);
         }
     }
-    float dls[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dlogit = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) row[i] = 0.f;
     if (valid) {
         // the shape again (bitwise the same) rather than R, M held across the loop
 #pragma unroll
@@ -744,20 +750,65 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
 #pragma unroll
         for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(gp.q[i]));
         gaussian_shape(gp, sh);
-        float ds[3];
+        float ds[3], dq[4];
         chain_shape<float>(dSig, sh, ds, dq);
-        dlogit = dop * opac * (1.f - opac);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) dls[i] = ds[i] * sh.s[i];
+        for (int i = 0; i < 3; ++i) row[i] = ds[i] * sh.s[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) row[3 + i] = dq[i];
+        row[7] = dop * opac * (1.f - opac);
     }
-    if (inb) {
-        if (sd.g_means) {
-            sd.g_means[3 * g + 0] = dmu[0];
-            sd.g_means[3 * g + 1] = dmu[1];
-            sd.g_means[3 * g + 2] = dmu[2];
-        }
-        if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
+    return isl;
+}
+
+// The per-Gaussian outputs beside the row: dL/dmean, dL/dlogit of a
+// per-Gaussian opacity, and the island mark (a bit per Gaussian, two words
+// per wavefront of the scene, plus one word that says some bit is set) or
+// the SGLD update of the Gaussian's own parameters.
+__device__ inline void gaussian_epilogue(const BatchDesc* __restrict__ desc, const SceneDesc& sd, int s, int64_t g,
+                                         const float* dmu, float dlogit, bool isl, uint32_t* __restrict__ isl_flag) {
+    if (sd.g_means) {
+        sd.g_means[3 * g + 0] = dmu[0];
+        sd.g_means[3 * g + 1] = dmu[1];
+        sd.g_means[3 * g + 2] = dmu[2];
     }
+    if (sd.opacity_mode == 0 && sd.g_opacity) sd.g_opacity[g] = dlogit;
+    if (isl) {
+        atomicOr(&isl_flag[2 * (sd.wave_off + (g >> 6)) + ((g >> 5) & 1)], 1u << (g & 31));
+        atomicOr(&isl_flag[2 * desc->n_gauss_waves], 1u);
+    } else if (desc->sgld) {
+        sgld_gaussian(desc, sd, s, g, dmu, dlogit);
+    }
+}
+
+// One thread per Gaussian, in Gaussian order: the chain rule, and the
+// per-Gaussian row gradient written to gtheta (for the reduction by rows that
+// follows).  Island Gaussians' rows are overwritten by k_chain_fp64.
+template <int DT, int SHD>
+__global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ desc, const float* __restrict__ rec_grad,
+                                               const uint32_t* __restrict__ rec_flag,
+                                               float* __restrict__ gtheta, uint32_t* __restrict__ isl_flag) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    constexpr int RW = 8 + 3 * NCO;                      // the row width of the batch's SH degree
+    constexpr int kHalf = 32;                            // rows staged per round
+    // Per wave: half of its gradient rows at a time, written out as whole
+    // lines (a lane's own 16-byte stores would touch a line per lane).
+    // Staging the record gradients the same way costs 20 registers and a
+    // wave per SIMD, more than it saves.
+    __shared__ __align__(16) float s_stage[4][kHalf * RW];
+    const int64_t wv = wave_id(4);
+    if (wv >= desc->n_gauss_waves) return;
+    const int s = find_scene_by_wave(desc, wv);
+    const SceneDesc& sd = desc->scenes[s];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = wv - sd.wave_off;
+    const int64_t g = q * kWave + lane;
+    const bool inb = g < sd.n;                  // every lane stays: the staging is wave-wide
+    const int nrows = (int)(sd.n - q * kWave < kWave ? sd.n - q * kWave : kWave);
+    float* stg = s_stage[w];
+
+    float row[RW], dmu[3];
+    const bool isl = chain_gaussian<DT, SHD>(desc, sd, g, inb, rec_grad, rec_flag, row, dmu);
     // rows [sd.g_off + 64 q, + nrows) are contiguous: two rounds of 32
     float* rows = gtheta + (sd.g_off + q * kWave) * RW;
 #pragma unroll
@@ -766,11 +817,8 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         if (nr <= 0) break;
         if (lane >= h * kHalf && lane < h * kHalf + nr) {
             float* o = stg + (lane - h * kHalf) * RW;
-            o[0] = dls[0]; o[1] = dls[1]; o[2] = dls[2];
-            o[3] = dq[0]; o[4] = dq[1]; o[5] = dq[2]; o[6] = dq[3];
-            o[7] = dlogit;
 #pragma unroll
-            for (int i = 0; i < 3 * NCO; ++i) o[8 + i] = dk[i];
+            for (int i = 0; i < RW; ++i) o[i] = row[i];
         }
         wave_sync();
         float* dst = rows + (int64_t)h * kHalf * RW;
@@ -794,9 +842,147 @@ __global__ __launch_bounds__(256) void k_chain(const BatchDesc* __restrict__ des
         }
         wave_sync();
     }
-    if (inb) {
-        if (isl) atomicOr(&isl_flag[2 * wv + (lane >> 5)], 1u << (lane & 31));
-        else if (desc->sgld) sgld_gaussian(desc, sd, s, g, dmu, dlogit);
+    if (inb) gaussian_epilogue(desc, sd, s, g, dmu, row[7], isl, isl_flag);
+}
+
+// Single-codebook layout: the chain rule fused with the reduction by rows.
+// The Gaussians sorted by (row, Gaussian) keep each scene in its own range
+// of positions (a row key never leaves its scene's rows), so wavefront
+// (scene s, q) takes positions g_off + [64 q, 64 q + 64) of that order: its
+// lanes hold a few runs of equal rows.  The rows are staged in LDS and lane c
+// sums column c of each run in position order.  A run holding all of its
+// row's Gaussians is the row's gradient, written to the codebook gradient
+// (with the row's SGLD update); otherwise it is the head (starting at lane 0)
+// or tail partial of the row in this wavefront, kept in rpart[2 wv] or
+// rpart[2 wv + 1] for k_merge_rows.  Island Gaussians add zero here;
+// k_merge_rows adds their FP64 rows.
+template <int DT, int SHD>
+__global__ __launch_bounds__(256) void k_chain_rows(const BatchDesc* __restrict__ desc,
+                                                    const float* __restrict__ rec_grad,
+                                                    const uint32_t* __restrict__ rec_flag,
+                                                    const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sval,
+                                                    const uint32_t* __restrict__ row_range, float* __restrict__ rpart,
+                                                    uint32_t* __restrict__ isl_flag) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    constexpr int RW = 8 + 3 * NCO;
+    constexpr int kHalf = 32;
+    __shared__ __align__(16) float s_stage[4][kHalf * RW];
+    const int64_t wv = wave_id(4);
+    if (wv >= desc->n_gauss_waves) return;
+    const int s = find_scene_by_wave(desc, wv);
+    const SceneDesc& sd = desc->scenes[s];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = wv - sd.wave_off;
+    const int64_t p0 = sd.g_off + q * kWave;                  // the wavefront's first sorted position
+    const int nlive = (int)(sd.n - q * kWave < kWave ? sd.n - q * kWave : kWave);
+    const bool live = lane < nlive;
+    const uint32_t key = live ? skey[p0 + lane] : 0xffffffffu;
+    const int64_t g = live ? (int64_t)sval[p0 + lane] - sd.g_off : 0;
+
+    float row[RW], dmu[3];
+    const bool isl = chain_gaussian<DT, SHD>(desc, sd, g, live, rec_grad, rec_flag, row, dmu);
+    if (live) gaussian_epilogue(desc, sd, s, g, dmu, row[7], isl, isl_flag);
+
+    const int64_t n_rows = desc->sr_rows_total;
+    const uint64_t islm = __ballot(isl);
+    float* stg = s_stage[w];
+    float acc = 0.f;
+    uint32_t cur = __builtin_amdgcn_readfirstlane(key);
+    int seg0 = 0;
+    auto flush = [&](uint32_t kr, int a, int b) {
+        if ((int64_t)kr >= n_rows) return;
+        const uint32_t rs = row_range[2 * (int64_t)kr], re = row_range[2 * (int64_t)kr + 1];
+        const bool whole = (int64_t)rs >= p0 + a && (int64_t)re <= p0 + b;
+        if (whole) {
+            const uint64_t span = (b - a < 64 ? (1ull << (b - a)) - 1ull : ~0ull) << a;
+            int64_t lr;
+            int sc;
+            const RowOut o = row_out(desc, 0, kr, &lr, &sc);
+            if (lane < RW) {
+                o.ptr[lr * o.stride + o.col0 + lane] = acc;
+                if (desc->sgld && (islm & span) == 0ull) sgld_row(desc, sc, lr, lane, acc);
+            }
+        } else if (lane < RW) {
+            rpart[(2 * wv + (a == 0 ? 0 : 1)) * RW + lane] = acc;
+        }
+    };
+#pragma unroll
+    for (int h = 0; h < kWave / kHalf; ++h) {
+        const int r0 = h * kHalf;
+        if (r0 >= nlive) break;
+        const int nr = nlive - r0 < kHalf ? nlive - r0 : kHalf;
+        if (lane >= r0 && lane < r0 + nr) {
+            float* o = stg + (lane - r0) * RW;
+#pragma unroll
+            for (int i = 0; i < RW; ++i) o[i] = isl ? 0.f : row[i];
+        }
+        wave_sync();
+        for (int rr = 0; rr < nr; ++rr) {
+            const int r = r0 + rr;
+            const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, r);
+            if (k != cur) {
+                flush(cur, seg0, r);
+                cur = k;
+                seg0 = r;
+                acc = 0.f;
+            }
+            if (lane < RW) acc += stg[rr * RW + lane];
+        }
+        wave_sync();
+    }
+    flush(cur, seg0, nlive);
+}
+
+// The rows k_chain_rows left partial: a row spanning several wavefronts
+// (head or tail partial of each, summed in wavefront order) or holding
+// island Gaussians (their FP64 rows, written to gtheta by k_chain_fp64, added
+// in position order).  One wavefront per row, lanes over columns.
+__global__ __launch_bounds__(256) void k_merge_rows(const BatchDesc* __restrict__ desc,
+                                                    const uint32_t* __restrict__ sval,
+                                                    const uint32_t* __restrict__ row_range,
+                                                    const float* __restrict__ rpart, const float* __restrict__ gtheta,
+                                                    const uint32_t* __restrict__ isl_flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = wave_id(4);
+    if (r >= desc->sr_rows_total) return;
+    const int RW = desc->row_width;
+    const int64_t rs = row_range[2 * r], re = row_range[2 * r + 1];
+    if (rs == re) return;                                   // k_reduce_empty
+    int64_t lr;
+    int sc;
+    const RowOut o = row_out(desc, 0, r, &lr, &sc);
+    // the row's positions lie in its scene's range: wavefronts of that scene
+    const SceneDesc& sd = desc->scenes[sc];
+    const int64_t w0 = sd.wave_off + ((rs - sd.g_off) >> 6), w1 = sd.wave_off + ((re - 1 - sd.g_off) >> 6);
+    auto island = [&](uint32_t gid) -> bool {
+        const SceneDesc& sd = desc->scenes[find_scene(desc, gid)];
+        const int64_t g = (int64_t)gid - sd.g_off;
+        return (isl_flag[2 * (sd.wave_off + (g >> 6)) + ((g >> 5) & 1)] >> (g & 31)) & 1u;
+    };
+    bool has_isl = false;
+    if (isl_flag[2 * desc->n_gauss_waves] != 0u)
+        for (int64_t pb = rs; pb < re; pb += 64)
+            has_isl |= __ballot(pb + lane < re && island(sval[pb + lane])) != 0ull;
+    if (w0 == w1 && !has_isl) return;                       // written whole by k_chain_rows
+    float* out = o.ptr + lr * o.stride + o.col0;
+    float acc = 0.f;
+    if (lane < RW) {
+        if (w0 == w1) {
+            acc = out[lane];                                // the run's sum, islands left out
+        } else {
+            const bool head = ((rs - sd.g_off) & 63) == 0;    // the row starts a wavefront
+            acc = rpart[(2 * w0 + (head ? 0 : 1)) * RW + lane];
+            for (int64_t wq = w0 + 1; wq <= w1; ++wq) acc += rpart[2 * wq * RW + lane];
+        }
+    }
+    if (has_isl)
+        for (int64_t pp = rs; pp < re; ++pp) {
+            const uint32_t gid = sval[pp];
+            if (island(gid) && lane < RW) acc += gtheta[(int64_t)gid * RW + lane];
+        }
+    if (lane < RW) {
+        out[lane] = acc;
+        if (desc->sgld) sgld_row(desc, sc, lr, lane, acc);
     }
 }
 
@@ -885,30 +1071,13 @@ __global__ __launch_bounds__(256) void k_row_keys(const BatchDesc* __restrict__ 
     const int s = find_scene(desc, gg);
     const SceneDesc& sd = desc->scenes[s];
     const int64_t g = gg - sd.g_off;
-    key[gg] = part == 0 ? (uint32_t)(sd.sr_row_off + sd.idx_sr[g]) : (uint32_t)(sd.sh_row_off + sd.idx_sh[g]);
-}
-
-struct RowOut {
-    float* ptr;
-    int64_t stride;
-    int32_t col0;
-};
-
-__device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, int64_t* local, int* scene) {
-    int lo = 0, hi = desc->n_scenes - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int64_t off = part == 0 ? desc->scenes[mid].sr_row_off : desc->scenes[mid].sh_row_off;
-        if (off <= row) lo = mid; else hi = mid - 1;
-    }
-    const SceneDesc& sd = desc->scenes[lo];
-    *scene = lo;
-    if (part == 0) {
-        *local = row - sd.sr_row_off;
-        return RowOut{sd.g_sr, sd.g_sr_stride, sd.g_sr_col0};
-    }
-    *local = row - sd.sh_row_off;
-    return RowOut{sd.g_sh, sd.g_sh_stride, sd.g_sh_col0};
+    // an index outside the codebook (the Gaussian is invalid, its row
+    // gradient zero) is clamped into the scene's rows, so every scene keeps
+    // its own range of the sorted order
+    const int64_t k = part == 0 ? sd.idx_sr[g] : sd.idx_sh[g];
+    const int64_t rows = part == 0 ? sd.sr_rows : sd.sh_rows;
+    const int64_t kc = k < 0 ? 0 : (k >= rows ? rows - 1 : k);
+    key[gg] = (uint32_t)((part == 0 ? sd.sr_row_off : sd.sh_row_off) + kc);
 }
 
 // One wavefront per chunk of kReduceChunk consecutive positions of the
@@ -1083,21 +1252,34 @@ hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, b
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, int64_t n_rec_waves,
-                        const float* ginst, const uint32_t* eo, const uint32_t* nt, const uint2* tr, const uint32_t* dk,
-                        const uint2* cut, const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, float* gtheta,
-                        uint32_t* isl_flag, hipStream_t st) {
+hipError_t launch_slot_sum(const BatchDesc* d_desc, int64_t n_rec_waves, const float* ginst, const uint32_t* eo,
+                           const uint32_t* nt, const uint2* tr, const uint32_t* dk, const uint2* cut,
+                           const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, hipStream_t st) {
     if (n_rec_waves > 0)
         hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
                            nt, tr, dk, cut, cnt, rec_grad, rec_flag);
+    return hipGetLastError();
+}
+
+// The chain rule in Gaussian order (rows to gtheta), or fused with the
+// reduction by rows when skey is given (rows sorted by the single codebook's
+// index; partials to rpart), then the FP64 redo of island Gaussians.
+hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves,
+                        const float* rec_grad, const uint32_t* rec_flag, float* gtheta, uint32_t* isl_flag,
+                        const uint32_t* skey, const uint32_t* sval, const uint32_t* row_range, float* rpart,
+                        hipStream_t st) {
     if (n_gauss_waves <= 0) return hipGetLastError();
-    hipError_t e = fill_u32(isl_flag, 0u, (size_t)(2 * n_gauss_waves), st);
+    hipError_t e = fill_u32(isl_flag, 0u, (size_t)(2 * n_gauss_waves + 1), st);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
     dim3 grid64((unsigned)((2 * n_gauss_waves + 255) / 256));
 #define CGS_CH(DT, SHD)                                                                                     \
     do {                                                                                                    \
-        hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta, isl_flag); \
+        if (skey)                                                                                           \
+            hipLaunchKernelGGL((k_chain_rows<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, rec_flag, skey,  \
+                               sval, row_range, rpart, isl_flag);                                           \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_chain<DT, SHD>), grid, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta, isl_flag); \
         hipLaunchKernelGGL((k_chain_fp64<DT, SHD>), grid64, blk, 0, st, d_desc, rec_grad, rec_flag, gtheta,      \
                            isl_flag);                                                                       \
     } while (0)
@@ -1109,6 +1291,18 @@ hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_g
                        case 2: CGS_CH(CGS_BF16, 2); break; default: CGS_CH(CGS_BF16, 3); break; }
     }
 #undef CGS_CH
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_rows(const BatchDesc* d_desc, int64_t n_rows, const uint32_t* sval, const uint32_t* row_range,
+                             const float* rpart, const float* gtheta, const uint32_t* isl_flag, int D,
+                             hipStream_t st) {
+    if (n_rows > 0)
+        hipLaunchKernelGGL(k_merge_rows, dim3((unsigned)((n_rows + 3) / 4)), dim3(256), 0, st, d_desc, sval,
+                           row_range, rpart, gtheta, isl_flag);
+    if (n_rows * D > 0)
+        hipLaunchKernelGGL(k_reduce_empty, dim3((unsigned)((n_rows * D + 255) / 256)), dim3(256), 0, st, d_desc, 0, 0,
+                           D, 0, n_rows, row_range);
     return hipGetLastError();
 }
 
