@@ -514,3 +514,50 @@ def test_needle_gaussians_fp64_island():
            row_rel_l2_max=max(e[1] for e in needle_errs), mean_rel_l2_max=max(e[2] for e in needle_errs),
            grad_err_over_bound=worst, background=bg_err)
     say(f"  needle gradients: worst error / bound {worst:.2f}")
+
+
+def test_out_of_range_indices_are_absent():
+    """A Gaussian whose codebook index lies outside its codebook (negative or
+    >= K) is invalid: nothing renders it and its gradients are zero.  A
+    two-scene batch holding 40 such Gaussians per scene must render and
+    differentiate as the oracle's batch without them; the single-codebook
+    backward, which walks Gaussians sorted by row, keeps each of them in its
+    own scene's rows (the other scene's rows are untouched)."""
+    rng = np.random.default_rng(91)
+    ss = [sc.make_scene(rng, n, k, 3, sc.screen_matched_mu(64), clusters=True) for n, k in ((3000, 64), (2000, 100))]
+    bad, keep = [], []
+    for s in ss:
+        b = np.sort(rng.choice(s.n, 40, replace=False))
+        s.idx[b[:20]] = (-1 - rng.integers(0, 5, 20)).astype(np.int32)
+        s.idx[b[20:]] = (s.k + rng.integers(0, 5, 20)).astype(np.int32)
+        bad.append(b)
+        keep.append(np.setdiff1d(np.arange(s.n), b))
+    cams = [sc.pinhole(64, 48, (0.0, 0.0, -3.0)), sc.pinhole(64, 64, (0.3, 0.0, -3.0))]
+    tg = [rng.uniform(0, 1, (c.height, c.width, 3)).astype(np.float32) for c in cams]
+    vs = np.array([0, 1], np.int32)
+    wl = sc.Workload("oob_idx", ss, cams, vs, tg, False)
+    ref = sc.Workload("oob_idx_ref", [sc.Scene(s.means[k], s.idx[k], s.cb, s.sh_degree) for s, k in zip(ss, keep)],
+                      cams, vs, tg, False)
+    say("[out-of-range indices] 2 scenes, 40 invalid Gaussians each")
+    r = gpu_renderer(wl)
+    r.forward()
+    torch.cuda.synchronize()
+    img, T, nl = r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()
+    pix = [full_pixels(c) for c in cams]
+    base = oracle_render(ref, pix)
+    for v, cam in enumerate(cams):
+        a, b = r.pix_off[v], r.pix_off[v + 1]
+        ec, et, mism, namb = compare_view(img[a:b], T[a:b], nl[a:b], cam, pix[v], base[v])
+        say(f"  view {v}: colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}")
+        assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
+    gcols, gfull = oracle_grad_image(ref, pix, base)
+    ogm, ogcb = oracle_scene_grads(ref, oracle_render(ref, pix, gcols))
+    gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
+    torch.cuda.synchronize()
+    for i in range(len(ss)):
+        m = gm[i].cpu().numpy()
+        assert np.all(m[bad[i]] == 0.0)
+        errs = grad_errors(m[keep[i]], gcb[i].cpu().numpy(), ogm[i], ogcb[i])
+        say(f"  scene {i}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        for k, e in errs.items():
+            assert e <= GRAD_TOL, (k, e)
