@@ -14,7 +14,7 @@ namespace cgs {
 
 // launchers defined in the other translation units
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*, uint32_t*,
-                             uint32_t*, hipStream_t);
+                             uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
                        const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
@@ -59,7 +59,7 @@ struct WsPlan {
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
     size_t radix_ws, scan_bsum, scan_bsum2;
-    size_t chunk_tot, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, rpart, psort_key[2], psort_val[2], row_start;
+    size_t chunk_tot, krange, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, rpart, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t scan_blocks_max;
 };
@@ -260,6 +260,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
     p.scan_bsum2 = take(8 * (size_t)p.scan_blocks_max);
     p.chunk_tot = take(4 * (size_t)d.n_rec_waves + 4);
+    p.krange = take(8 * (size_t)d.n_rec_waves + 8);
     p.chunk_base = take(4 * (size_t)d.n_rec_waves + 4);
     p.ginst = take(4 * 9 * (size_t)cap);
     p.rec_grad = take(4 * 9 * (size_t)R);
@@ -447,7 +448,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect),
-                              at<uint32_t>(ws, p.chunk_tot), st));
+                              at<uint32_t>(ws, p.chunk_tot), at<uint32_t>(ws, p.krange), st));
     CGS_TRY(mark(h, 1, st));
     // backward gradient slots: each 64-record chunk owns a contiguous range
     // (chunks in record order); its base, needed only by the backward, is
@@ -477,7 +478,11 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
         rg.pay_buf[0] = at<uint32_t>(ws, p.pay[0]);
         rg.pay_buf[1] = at<uint32_t>(ws, p.pay[1]);
     }
-    int db = radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, sws, st, &e, &rg);
+    const int db = h.d.pack_rect
+                       ? radix_sort_depth(at<uint32_t>(ws, p.depth_key), at<uint32_t>(ws, p.krange), h.d.n_rec_waves,
+                                          dk, dv, h.d.n_rec, sws, st, &e, rg)
+                       : radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, sws,
+                                          st, &e, &rg);
     CGS_TRY(e);
     // instance offsets in depth order, capacity check, emission
     CGS_TRY(scan_u32(at<uint32_t>(ws, p.cnt_d), nullptr, h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));

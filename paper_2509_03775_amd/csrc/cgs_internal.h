@@ -321,6 +321,13 @@ size_t radix_ws_bytes(int64_t n_max);
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
                      const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
                      const SortGather* last = nullptr);
+// The records' depth sort with the packed-rectangle payload (g.pay_in,
+// g.pay_buf): 9-bit digits over the keys relative to the live depth range
+// (from krange: n_part pairs (max ~key, max key) over live keys),
+// only the passes the range needs; results in kbuf/vbuf[1], g.rect_out and
+// g.cnt_out.  Returns 1.
+int radix_sort_depth(const uint32_t* kin, const uint32_t* krange, int64_t n_part, uint32_t* kbuf[2], uint32_t* vbuf[2],
+                     int64_t n, void* ws, hipStream_t st, hipError_t* err, const SortGather& g);
 // Look-back waits of the radix passes that hit their bound on the current
 // device since the library was loaded (synchronous read; 0 expected).
 uint32_t sort_stalls();

@@ -15,7 +15,8 @@ template <int DT, int SHD>
 __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict__ desc,
                                                     float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles,
-                                                    uint32_t* __restrict__ prect, uint32_t* __restrict__ chunk_tot) {
+                                                    uint32_t* __restrict__ prect, uint32_t* __restrict__ chunk_tot,
+                                                    uint32_t* __restrict__ krange) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
@@ -69,6 +70,17 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
             r0 = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
             r1 = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
             r2 = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), __uint_as_float(incl - nt));
+        }
+        // the wave's share of the depth-key range the depth sort needs:
+        // max of ~key and of key over its kept records
+        {
+            const uint32_t kk = __float_as_uint(vp.zc);
+            const bool kept = inb && keep;
+            const uint32_t nlo = wave_max_u32(kept ? ~kk : 0u), hi = wave_max_u32(kept ? kk : 0u);
+            if (lane == 0) {
+                krange[2 * (vd.rec_wave_off + q)] = nlo;
+                krange[2 * (vd.rec_wave_off + q) + 1] = hi;
+            }
         }
         // The wave's records are one contiguous 4 KB block: staged in LDS and
         // written 1 KB per store instruction (whole lines), padding included.
@@ -379,10 +391,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 // ------------------------------------------------------------------ launchers
 hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, float4* rec,
                              uint32_t* dk, uint2* tr, uint32_t* nt, uint32_t* prect, uint32_t* chunk_tot,
-                             hipStream_t st) {
+                             uint32_t* krange, hipStream_t st) {
     if (n_gauss_waves <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot)
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot, krange)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
                        case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }

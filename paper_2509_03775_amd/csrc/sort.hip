@@ -169,12 +169,20 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_
 // ticket is taken only by a running workgroup and a workgroup publishes its
 // state before it waits, so every wait ends; the wait is still bounded (a
 // stall is counted and the pass finishes with its writes kept in bounds).
+//
+// The depth sort of the records uses 9-bit digits over keys relative to the
+// batch's depth range: k_key_range finds the least and largest live depth key,
+// a key becomes min(key, largest) - least (culled records, whose key is +inf,
+// take the largest live key: they own no instances, so their place in the
+// order is never read), and only the passes that cover the range's bits run
+// (three for a range under 2^27); the last of them writes the final buffers.
 constexpr int kOsThreads = 512;             // 8 waves
 constexpr int kOsWaves = kOsThreads / 64;
 constexpr int kOsItems = 16;                // keys per lane
 constexpr int kOsTile = kOsItems * kOsThreads;   // 8192 keys per workgroup
 constexpr int kOsHistBlocks = 512;
-constexpr int kHistCopies = 8;
+constexpr int kDepthBits = 9;               // digit width of the depth sort
+constexpr int kMaxBins = 1 << kDepthBits;
 constexpr uint64_t kStAgg = 1ull << 62;     // bits 32..61: k + 1; low 32: count of tiles (k, t]
 constexpr uint64_t kStInc = 2ull << 62;     // low 32: count of tiles [0, t]
 constexpr uint32_t kSpinLimit = 1u << 21;
@@ -195,9 +203,58 @@ __device__ inline uint64_t status_get(uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <int RB>
 __device__ inline uint32_t pass_mask(int nbits, int p) {
-    const int w = nbits - p * kRadixBits < kRadixBits ? nbits - p * kRadixBits : kRadixBits;
+    const int w = nbits - p * RB < RB ? nbits - p * RB : RB;
     return (1u << w) - 1u;
+}
+
+// The depth range: range[0] = ~(least live key), range[1] = largest live key
+// (both start at 0, both found by atomicMax).
+struct DepthRange {
+    uint32_t lo, hi;
+    bool any;
+};
+
+__device__ inline DepthRange depth_range(const uint32_t* range) {
+    DepthRange r;
+    r.lo = ~range[0];
+    r.hi = range[1];
+    r.any = r.lo <= r.hi;
+    return r;
+}
+
+__device__ inline uint32_t depth_rel(uint32_t key, const DepthRange& r) {
+    if (!r.any) return 0u;
+    return (key < r.hi ? key : r.hi) - r.lo;
+}
+
+// Passes the depth range needs (at least one).
+__device__ inline int depth_passes(const DepthRange& r) {
+    const uint32_t span = r.any ? r.hi - r.lo : 0u;
+    const int bits = span == 0u ? 1 : 32 - __clz(span);
+    return (bits + kDepthBits - 1) / kDepthBits;
+}
+
+// The depth range from per-wavefront partials (pairs: max of ~key, max of key
+// over the wavefront's live keys, written by the preprocessing).
+__global__ __launch_bounds__(256) void k_key_range(const uint2* part, int64_t n_part, uint32_t* range) {
+    uint32_t nlo = 0u, hi = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_part; i += (int64_t)gridDim.x * 256) {
+        const uint2 pr = part[i];
+        nlo = pr.x > nlo ? pr.x : nlo;
+        hi = pr.y > hi ? pr.y : hi;
+    }
+    nlo = wave_max_u32(nlo);
+    hi = wave_max_u32(hi);
+    __shared__ uint32_t s_lo[4], s_hi[4];
+    if ((threadIdx.x & 63) == 0) { s_lo[threadIdx.x >> 6] = nlo; s_hi[threadIdx.x >> 6] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) { nlo = s_lo[w] > nlo ? s_lo[w] : nlo; hi = s_hi[w] > hi ? s_hi[w] : hi; }
+        if (nlo) atomicMax(&range[0], nlo);
+        if (hi) atomicMax(&range[1], hi);
+    }
 }
 
 // Exclusive scan over the workgroup of one value per thread (kOsThreads).
@@ -214,68 +271,82 @@ __device__ inline uint32_t os_scan(uint32_t v, uint32_t* s_wave) {
 }
 
 struct SortWs {
-    uint64_t* status[2];    // [tiles][256] per pass, the two alternating
-    uint32_t* ghist;        // [4][256] digit counts of every pass
+    uint64_t* status[2];    // [tiles][bins] per pass, the two alternating
+    uint32_t* ghist;        // [4][bins] digit counts of every pass
     uint32_t* tickets;      // [4] per pass
+    uint32_t* range;        // [2] the depth sort's key range
 };
 
+// Laid out for the widest digit (the 8-bit sorts use the front of each row).
 SortWs sort_ws(void* ws, int64_t n_max) {
     const int64_t nb = std::max<int64_t>(1, (n_max + kOsTile - 1) / kOsTile);
     char* p = static_cast<char*>(ws);
     SortWs s;
-    const size_t st_bytes = align_up(8 * (size_t)kRadixBins * (size_t)nb);
+    const size_t st_bytes = align_up(8 * (size_t)kMaxBins * (size_t)nb);
     s.status[0] = reinterpret_cast<uint64_t*>(p);
     s.status[1] = reinterpret_cast<uint64_t*>(p + st_bytes);
     s.ghist = reinterpret_cast<uint32_t*>(p + 2 * st_bytes);
-    s.tickets = s.ghist + 4 * kRadixBins;
+    s.tickets = s.ghist + 4 * kMaxBins;
+    s.range = s.tickets + 4;
     return s;
 }
 
 size_t radix_ws_bytes(int64_t n_max) {
     const int64_t nb = std::max<int64_t>(1, (n_max + kOsTile - 1) / kOsTile);
-    return 2 * align_up(8 * (size_t)kRadixBins * (size_t)nb) + align_up(4 * (4 * (size_t)kRadixBins + 4));
+    return 2 * align_up(8 * (size_t)kMaxBins * (size_t)nb) + align_up(4 * (4 * (size_t)kMaxBins + 6));
 }
 
 // Digit histograms of every pass over the live keys (global atomics of each
 // workgroup's nonzero LDS bins) and a zeroed state row per live tile for the
-// first pass.  Each bin has kHistCopies LDS copies, lane l adding to copy l % kHistCopies,
+// first pass.  Each bin has LDS copies, lane l adding to copy l % copies,
 // so lanes of a wave that share a digit (the high digits of depth keys take
-// few values) collide at most 64 / kHistCopies ways.
+// few values) collide at most 64 / copies ways.  DEPTH: digits of the keys
+// relative to the depth range.
+template <int RB, bool DEPTH>
 __global__ __launch_bounds__(kOsThreads) void k_os_hist(const uint32_t* keys, int64_t n_max,
                                                         const unsigned long long* n_dev, int nbits, uint32_t* ghist,
-                                                        uint64_t* status0) {
-    __shared__ uint32_t h[4 * kRadixBins * kHistCopies];
-    for (int i = threadIdx.x; i < 4 * kRadixBins * kHistCopies; i += kOsThreads) h[i] = 0;
+                                                        uint64_t* status0, const uint32_t* range) {
+    constexpr int KB = 1 << RB;
+    constexpr int kCopies = 8 >> (RB - 8);
+    __shared__ uint32_t h[4 * KB * kCopies];
+    for (int i = threadIdx.x; i < 4 * KB * kCopies; i += kOsThreads) h[i] = 0;
     __syncthreads();
-    const uint32_t copy = threadIdx.x % kHistCopies;
+    const uint32_t copy = threadIdx.x % kCopies;
     const int64_t n = live_count(n_max, n_dev);
     const int64_t nb = (n + kOsTile - 1) / kOsTile;
-    const int passes = (nbits + kRadixBits - 1) / kRadixBits;
+    int passes = (nbits + RB - 1) / RB;
+    DepthRange dr{};
+    if constexpr (DEPTH) {
+        dr = depth_range(range);
+        passes = depth_passes(dr);          // digits above the range are all zero: not counted
+    }
     for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
-        if (threadIdx.x < kRadixBins) status0[t * kRadixBins + threadIdx.x] = 0ull;
+        if (threadIdx.x < KB) status0[t * KB + threadIdx.x] = 0ull;
         uint32_t k_[kOsItems];
 #pragma unroll
         for (int i = 0; i < kOsItems; ++i) {
             const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
             k_[i] = j < n ? keys[j] : 0u;
+            if constexpr (DEPTH) k_[i] = depth_rel(k_[i], dr);
         }
 #pragma unroll
         for (int i = 0; i < kOsItems; ++i) {
             const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
             if (j < n)
                 for (int p = 0; p < passes; ++p) {
-                    const uint32_t d = (k_[i] >> (p * kRadixBits)) & pass_mask(nbits, p);
-                    atomicAdd(&h[(p * kRadixBins + d) * kHistCopies + copy], 1u);
+                    const uint32_t d = (k_[i] >> (p * RB)) & pass_mask<RB>(nbits, p);
+                    atomicAdd(&h[(p * KB + d) * kCopies + copy], 1u);
                 }
         }
     }
     __syncthreads();
-    for (int p = 0; p < passes && threadIdx.x < kRadixBins; ++p) {
-        uint32_t c = 0;
+    for (int p = 0; p < passes; ++p)
+        for (int b = threadIdx.x; b < KB; b += kOsThreads) {
+            uint32_t c = 0;
 #pragma unroll
-        for (int q = 0; q < kHistCopies; ++q) c += h[(p * kRadixBins + threadIdx.x) * kHistCopies + q];
-        if (c) atomicAdd(&ghist[p * kRadixBins + threadIdx.x], c);
-    }
+            for (int q = 0; q < kCopies; ++q) c += h[(p * KB + b) * kCopies + q];
+            if (c) atomicAdd(&ghist[p * kMaxBins + b], c);     // rows laid out for the widest digit
+        }
 }
 
 // One pass.  Wave w of the workgroup owns keys [w * 1024, w * 1024 + 1024)
@@ -286,36 +357,66 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const uint32_t* keys, in
 // count of the digit and clears the mask.  The keys then go to LDS in
 // block-local digit order and out linearly, so each digit's run goes to
 // consecutive global addresses; the values (and a payload word, if any)
-// follow through the same LDS buffer.  Threads 0..255 own one digit each for
-// the counts and the look-back.
+// follow through the same LDS buffer.  Threads 0..bins-1 own one digit each
+// for the counts and the look-back.
 //
 // MODE 0: plain.  1 (last pass): also gathers each value's tile rectangle
 // from g.rect_in.  2: carries g.pay (pay_in -> pay_out).  3 (last pass):
 // unpacks the payload (x0 | y0 << 8 | x1 << 16 | y1 << 24) into the
-// rectangle and its tile count.
-constexpr int kPassPlain = 0, kPassGather = 1, kPassCarry = 2, kPassUnpack = 3;
+// rectangle and its tile count.  4: a pass of the depth sort (dio): exits if
+// the depth range does not need it, picks its buffers so that the last
+// pass the range needs writes the final ones, carries the payload, or
+// unpacks it as in mode 3 when it is that last pass; the first pass makes
+// the keys relative to the range.
+constexpr int kPassPlain = 0, kPassGather = 1, kPassCarry = 2, kPassUnpack = 3, kPassDepth = 4;
 
-template <int MODE>
+struct DepthIO {
+    const uint32_t* keys;       // raw depth keys
+    const uint32_t* pay;        // packed rectangles
+    uint32_t* kb[2];
+    uint32_t* vb[2];
+    uint32_t* pb[2];
+    const uint32_t* range;
+    int pass;
+};
+
+template <int MODE, int RB>
 __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in, const uint32_t* vals_in,
                                                         uint32_t* keys_out, uint32_t* vals_out, int64_t n_max,
                                                         const unsigned long long* n_dev, int shift, uint32_t mask,
                                                         const uint32_t* ghist, uint64_t* status,
                                                         uint64_t* status_next, uint32_t* ticket, SortGather g,
-                                                        const uint32_t* pay_in, uint32_t* pay_out) {
-    constexpr bool PAY = MODE == kPassCarry || MODE == kPassUnpack;
-    __shared__ uint32_t cnt[kOsWaves][kRadixBins];
+                                                        const uint32_t* pay_in, uint32_t* pay_out, DepthIO dio) {
+    constexpr int KB = 1 << RB;
+    constexpr bool PAY = MODE == kPassCarry || MODE == kPassUnpack || MODE == kPassDepth;
+    bool fin = MODE == kPassGather || MODE == kPassUnpack;    // writes the final rectangles
+    DepthRange dr{};
+    if constexpr (MODE == kPassDepth) {
+        dr = depth_range(dio.range);
+        const int L = depth_passes(dr);
+        if (dio.pass >= L) return;                            // the range is covered already
+        fin = dio.pass == L - 1;
+        const int o = (L - 1 - dio.pass) & 1 ? 0 : 1;         // the last live pass writes buffer 1
+        keys_in = dio.pass == 0 ? dio.keys : dio.kb[o ^ 1];
+        vals_in = dio.pass == 0 ? nullptr : dio.vb[o ^ 1];
+        pay_in = dio.pass == 0 ? dio.pay : dio.pb[o ^ 1];
+        keys_out = fin ? nullptr : dio.kb[o];
+        vals_out = dio.vb[o];
+        pay_out = dio.pb[o];
+        if (fin) status_next = nullptr;
+    }
+    __shared__ uint32_t cnt[kOsWaves][KB];
     // The peer masks are needed only while ranking, the staging buffer only
-    // after it (two barriers later): they share the same LDS, which keeps the
-    // workgroup at 41 KB (three per CU instead of two).
+    // after it (two barriers later): they share the same LDS.
     __shared__ __align__(16) uint32_t s_buf[kOsTile];
-    static_assert(sizeof(unsigned long long) * kOsWaves * kRadixBins <= sizeof(uint32_t) * kOsTile, "peer masks");
-    unsigned long long (*s_peer)[kRadixBins] = reinterpret_cast<unsigned long long (*)[kRadixBins]>(s_buf);
-    __shared__ uint32_t s_goff[kRadixBins];
+    static_assert(sizeof(unsigned long long) * kOsWaves * KB <= sizeof(uint32_t) * kOsTile, "peer masks");
+    unsigned long long (*s_peer)[KB] = reinterpret_cast<unsigned long long (*)[KB]>(s_buf);
+    __shared__ uint32_t s_goff[KB];
     __shared__ uint32_t s_wave[kOsWaves];
     __shared__ uint32_t s_ticket;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
-    for (int i = threadIdx.x; i < kOsWaves * kRadixBins; i += kOsThreads) {
+    for (int i = threadIdx.x; i < kOsWaves * KB; i += kOsThreads) {
         (&cnt[0][0])[i] = 0;
         (&s_peer[0][0])[i] = 0ull;
     }
@@ -324,9 +425,9 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
     const int64_t n = live_count(n_max, n_dev);
     const int64_t blk0 = b * kOsTile;
     if (blk0 >= n) return;
-    const bool dig = threadIdx.x < kRadixBins;
+    const bool dig = threadIdx.x < KB;
     const uint32_t d = dig ? threadIdx.x : 0u;
-    if (status_next && dig) status_next[b * kRadixBins + d] = 0ull;
+    if (status_next && dig) status_next[b * KB + d] = 0ull;
     const int64_t base = blk0 + (int64_t)w * (kOsItems * 64);
     uint32_t k_[kOsItems], v_[kOsItems], p_[PAY ? kOsItems : 1];
     uint32_t lp[kOsItems];
@@ -334,6 +435,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
     for (int i = 0; i < kOsItems; ++i) {
         const int64_t j = base + i * 64 + lane;
         k_[i] = j < n ? keys_in[j] : 0u;
+        if constexpr (MODE == kPassDepth)
+            if (dio.pass == 0) k_[i] = depth_rel(k_[i], dr);
     }
     const unsigned long long bit = 1ull << lane;
 #pragma unroll
@@ -360,7 +463,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
     uint32_t tot = 0, wb[kOsWaves];
 #pragma unroll
     for (int i = 0; i < kOsWaves; ++i) { wb[i] = tot; tot += dig ? cnt[i][d] : 0u; }
-    uint64_t* mine = status + b * kRadixBins + d;
+    uint64_t* mine = status + b * KB + d;
     if (dig) status_put(mine, (b == 0 ? kStInc : (kStAgg | ((uint64_t)b << 32))) | (uint64_t)tot);
 #pragma unroll
     for (int i = 0; i < kOsItems; ++i) {
@@ -384,7 +487,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
         int64_t k = b - 1;
         uint32_t spins = 0;
         for (;;) {
-            const uint64_t s = status_get(status + k * kRadixBins + d);
+            const uint64_t s = status_get(status + k * KB + d);
             const uint64_t f = s >> 62;
             if (f == 0) {
                 if (++spins >= kSpinLimit) { atomicAdd(&g_sort_stalls, 1u); break; }
@@ -442,7 +545,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
             const int q = i * kOsThreads + (int)threadIdx.x;
             if (q < m && (int64_t)pos[i] < n) {
                 const uint32_t pw = s_buf[q];
-                if constexpr (MODE == kPassCarry) {
+                if (!fin) {
                     pay_out[pos[i]] = pw;
                 } else {
                     const uint32_t x0 = pw & 0xffu, y0 = (pw >> 8) & 0xffu, x1 = (pw >> 16) & 0xffu, y1 = pw >> 24;
@@ -464,40 +567,70 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
     if (nblocks == 0 || nbits <= 0) return final_buf;
     if (passes > 4) { *err = hipErrorInvalidValue; return final_buf; }
     const SortWs s = sort_ws(ws, n_max);
-    *err = fill_u32(s.ghist, 0u, 4 * kRadixBins + 4, st);
+    *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
     if (*err != hipSuccess) return final_buf;
     const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
-    hipLaunchKernelGGL(k_os_hist, dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev, nbits, s.ghist,
-                       s.status[0]);
+    hipLaunchKernelGGL((k_os_hist<kRadixBits, false>), dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev, nbits,
+                       s.ghist, s.status[0], nullptr);
     const uint32_t* ksrc = kin;
     const uint32_t* vsrc = vin;
+    const DepthIO none{};
     for (int p = 0; p < passes; ++p) {
         const int out = p & 1;
         const bool fin = p + 1 == passes;
         SortGather g{};
         const uint32_t* pin = nullptr;
         uint32_t* pout = nullptr;
-        auto kern = k_os_pass<kPassPlain>;
+        auto kern = k_os_pass<kPassPlain, kRadixBits>;
         if (last && last->pay_in) {       // payload carried through every pass
             g = *last;
             pin = p == 0 ? last->pay_in : last->pay_buf[(p - 1) & 1];
             pout = last->pay_buf[p & 1];
-            kern = fin ? k_os_pass<kPassUnpack> : k_os_pass<kPassCarry>;
+            kern = fin ? k_os_pass<kPassUnpack, kRadixBits> : k_os_pass<kPassCarry, kRadixBits>;
         } else if (fin && last && last->rect_in) {
             g = *last;
-            kern = k_os_pass<kPassGather>;
+            kern = k_os_pass<kPassGather, kRadixBits>;
         }
         hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kOsThreads), 0, st, ksrc, vsrc,
                            fin && last && last->drop_keys ? nullptr : kbuf[out],
                            vbuf[out], n_max, n_dev, p * kRadixBits,
                            (uint32_t)((1ull << std::min(kRadixBits, nbits - p * kRadixBits)) - 1ull),
-                           s.ghist + p * kRadixBins, s.status[p & 1], p + 1 < passes ? s.status[(p + 1) & 1] : nullptr,
-                           s.tickets + p, g, pin, pout);
+                           s.ghist + p * kMaxBins, s.status[p & 1], p + 1 < passes ? s.status[(p + 1) & 1] : nullptr,
+                           s.tickets + p, g, pin, pout, none);
         ksrc = kbuf[out];
         vsrc = vbuf[out];
     }
     *err = hipGetLastError();
     return final_buf;
+}
+
+// The depth sort of the records (31-bit keys, +inf for culled records) with
+// the packed-rectangle payload: the result is in kbuf/vbuf[1] and g's
+// rectangle and count arrays whatever the number of passes the range takes.
+int radix_sort_depth(const uint32_t* kin, const uint32_t* krange, int64_t n_part, uint32_t* kbuf[2], uint32_t* vbuf[2],
+                     int64_t n, void* ws, hipStream_t st, hipError_t* err, const SortGather& g) {
+    *err = hipSuccess;
+    const int64_t nblocks = (n + kOsTile - 1) / kOsTile;
+    if (nblocks == 0) return 1;
+    const SortWs s = sort_ws(ws, n);
+    *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
+    if (*err != hipSuccess) return 1;
+    const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
+    const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_part + 255) / 256, 256));
+    hipLaunchKernelGGL(k_key_range, dim3(rb), dim3(256), 0, st, reinterpret_cast<const uint2*>(krange), n_part,
+                       s.range);
+    hipLaunchKernelGGL((k_os_hist<kDepthBits, true>), dim3(hb), dim3(kOsThreads), 0, st, kin, n, nullptr, 31,
+                       s.ghist, s.status[0], s.range);
+    constexpr int kPasses = (31 + kDepthBits - 1) / kDepthBits;
+    for (int p = 0; p < kPasses; ++p) {
+        DepthIO io{kin, g.pay_in, {kbuf[0], kbuf[1]}, {vbuf[0], vbuf[1]}, {g.pay_buf[0], g.pay_buf[1]}, s.range, p};
+        hipLaunchKernelGGL((k_os_pass<kPassDepth, kDepthBits>), dim3((unsigned)nblocks), dim3(kOsThreads), 0, st,
+                           nullptr, nullptr, nullptr, nullptr, n, nullptr, p * kDepthBits, (uint32_t)(kMaxBins - 1),
+                           s.ghist + p * kMaxBins, s.status[p & 1], p + 1 < kPasses ? s.status[(p + 1) & 1] : nullptr,
+                           s.tickets + p, g, nullptr, nullptr, io);
+    }
+    *err = hipGetLastError();
+    return 1;
 }
 
 int64_t resident_blocks(const void* kernel, int block) {
