@@ -561,3 +561,49 @@ def test_out_of_range_indices_are_absent():
         say(f"  scene {i}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
         for k, e in errs.items():
             assert e <= GRAD_TOL, (k, e)
+
+
+def _depth_range_workload(kind: str) -> sc.Workload:
+    """Scenes whose live depth keys span 0 bits (every mean on the plane
+    z = 0, camera axis-aligned at z = -3: all camera depths exactly 3.0, so
+    every key ties), about 2^18 (depths 3 to 3.05) and more than 2^27 (depths
+    0.3 to 1e5): the depth sort takes 1, 2 and 4 passes of 9 bits."""
+    rng = np.random.default_rng({"flat": 81, "shallow": 82, "deep": 83}[kind])
+    s = sc.make_scene(rng, 4000, 128, 3, sc.screen_matched_mu(96), clusters=False)
+    means = s.means.copy()
+    if kind == "flat":
+        means[:, 2] = 0.0
+    elif kind == "shallow":
+        means[:, 2] = rng.uniform(0.0, 0.05, means.shape[0]).astype(np.float32)
+    else:
+        dist = np.exp(rng.uniform(np.log(0.3), np.log(1e5), means.shape[0]))
+        means[:, 2] = (dist - 3.0).astype(np.float32)
+        means[:, 0:2] *= (dist / 3.0)[:, None].astype(np.float32)      # keep them in the frustum
+    s = sc.Scene(means, s.idx, s.cb, 3)
+    cams = [sc.pinhole(96, 72, (0.0, 0.0, -3.0))]
+    return sc.Workload("depth_" + kind, [s], cams, np.array([0], np.int32),
+                       [rng.uniform(0, 1, (72, 96, 3)).astype(np.float32)], False)
+
+
+@pytest.mark.parametrize("kind", ["flat", "shallow", "deep"])
+def test_depth_range_pass_counts(kind):
+    wl = _depth_range_workload(kind)
+    say(f"[depth range] {kind}")
+    r = gpu_renderer(wl)
+    r.forward()
+    torch.cuda.synchronize()
+    img, T, nl = r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()
+    pix = [full_pixels(c) for c in wl.cameras]
+    base = oracle_render(wl, pix)
+    ec, et, mism, namb = compare_view(img, T, nl, wl.cameras[0], pix[0], base[0])
+    say(f"  colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}")
+    assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
+    assert namb <= 0.01 * len(pix[0])
+    gcols, gfull = oracle_grad_image(wl, pix, base)
+    ogm, ogcb = oracle_scene_grads(wl, oracle_render(wl, pix, gcols))
+    gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
+    torch.cuda.synchronize()
+    errs = grad_errors(gm[0].cpu().numpy(), gcb[0].cpu().numpy(), ogm[0], ogcb[0])
+    say("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
