@@ -17,7 +17,7 @@ hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint3
                              uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
-                       const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
+                       const DevCounters*, void*, bool, uint32_t*, hipStream_t);
 hipError_t launch_plain_counts(const uint16_t*, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_emit_plain(const uint16_t*, const int32_t*, const uint32_t*, const uint32_t*, int64_t, int32_t,
                              int32_t, const DevCounters*, uint32_t*, uint32_t*, hipStream_t);
@@ -489,12 +489,24 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(launch_capacity(cnt, h.d.capacity, d_info, st));
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
     uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
+    // tile keys stored in 16 bits when the batch has at most 65536 tiles
+    const bool key16 = h.tile_bits <= 16;
     CGS_TRY(launch_emit(dd, h.d.n_rec, dv[db], at<uint32_t>(ws, p.offs), at<uint2>(ws, p.rect_d),
-                        at<uint32_t>(ws, p.cnt_d), cnt, ik[1], iv[1], st));
-    int ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
-    CGS_TRY(e);
-    if (ib != h.inst_buf) return CGS_EHIP;
-    CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
+                        at<uint32_t>(ws, p.cnt_d), cnt, ik[1], key16, iv[1], st));
+    int ib;
+    if (key16) {
+        uint16_t* ik16[2] = {reinterpret_cast<uint16_t*>(ik[0]), reinterpret_cast<uint16_t*>(ik[1])};
+        ib = radix_sort_pairs16(ik16[1], iv[1], ik16, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
+        CGS_TRY(e);
+        if (ib != h.inst_buf) return CGS_EHIP;
+        CGS_TRY(tile_ranges16(ik16[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range),
+                              st));
+    } else {
+        ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
+        CGS_TRY(e);
+        if (ib != h.inst_buf) return CGS_EHIP;
+        CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
+    }
     if (h.d.tile_order == 2) {
         uint32_t* tk[2] = {at<uint32_t>(ws, p.tperm_key[0]), at<uint32_t>(ws, p.tperm_key[1])};
         uint32_t* tv[2] = {at<uint32_t>(ws, p.tperm_val[0]), at<uint32_t>(ws, p.tperm_val[1])};

@@ -342,5 +342,11 @@ int64_t resident_blocks(const void* kernel, int block);
 
 hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                        int64_t n_tiles, uint32_t* ranges, hipStream_t st);
+// The same over 16-bit tile keys (batches of at most 65536 tiles), and the
+// radix sort of 16-bit keys with 32-bit values (plain passes only).
+hipError_t tile_ranges16(const uint16_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
+                         int64_t n_tiles, uint32_t* ranges, hipStream_t st);
+int radix_sort_pairs16(const uint16_t* kin, const uint32_t* vin, uint16_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
+                       const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err);
 
 }  // namespace cgs

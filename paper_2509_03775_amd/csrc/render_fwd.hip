@@ -124,11 +124,13 @@ __global__ void k_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info) 
 // record, carried into the next chunk), so writes are
 // coalesced and a record with many tiles does not stall its wave.  Instance
 // (record, tile) keys are the view's tile offset + the row-major tile index;
-// tiles of a record follow row-major order.
+// tiles of a record follow row-major order.  KT: the key's storage type
+// (16 bits when the batch has at most 65536 tiles).
+template <typename KT>
 __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc, const uint32_t* __restrict__ sorted_rec,
                                               const uint32_t* __restrict__ offs, const uint2* __restrict__ rect_d,
                                               const uint32_t* __restrict__ cnt_d, const DevCounters* __restrict__ cnt,
-                                              uint32_t* __restrict__ inst_key, uint32_t* __restrict__ inst_val) {
+                                              KT* __restrict__ inst_key, uint32_t* __restrict__ inst_val) {
     __shared__ uint32_t s_rel[4][64], s_w[4][64], s_base[4][64], s_tx[4][64], s_r[4][64], s_mark[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t j0 = ((int64_t)blockIdx.x * 4 + w) * 64;
@@ -182,7 +184,7 @@ __global__ __launch_bounds__(256) void k_emit(const BatchDesc* __restrict__ desc
             uint32_t row = (uint32_t)((float)local * __builtin_amdgcn_rcpf((float)wq));
             if (row * wq > local) --row;
             if ((row + 1) * wq <= local) ++row;
-            inst_key[o0 + i] = s_base[w][lo] + row * s_tx[w][lo] + (local - row * wq);
+            inst_key[o0 + i] = (KT)(s_base[w][lo] + row * s_tx[w][lo] + (local - row * wq));
             inst_val[o0 + i] = s_r[w][lo];
         }
         wave_sync();
@@ -412,12 +414,16 @@ hipError_t launch_capacity(DevCounters* cnt, int64_t capacity, int64_t* d_info, 
 }
 
 hipError_t launch_emit(const BatchDesc* d_desc, int64_t n_rec, const uint32_t* sorted_rec, const uint32_t* offs,
-                       const uint2* rect_d, const uint32_t* cnt_d, const DevCounters* cnt, uint32_t* ik, uint32_t* iv,
-                       hipStream_t st) {
+                       const uint2* rect_d, const uint32_t* cnt_d, const DevCounters* cnt, void* ik, bool key16,
+                       uint32_t* iv, hipStream_t st) {
     if (n_rec <= 0) return hipSuccess;
     const int64_t waves = (n_rec + 63) / 64;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, d_desc, sorted_rec, offs, rect_d,
-                       cnt_d, cnt, ik, iv);
+    if (key16)
+        hipLaunchKernelGGL(k_emit<uint16_t>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, d_desc, sorted_rec,
+                           offs, rect_d, cnt_d, cnt, static_cast<uint16_t*>(ik), iv);
+    else
+        hipLaunchKernelGGL(k_emit<uint32_t>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, d_desc, sorted_rec,
+                           offs, rect_d, cnt_d, cnt, static_cast<uint32_t*>(ik), iv);
     return hipGetLastError();
 }
 

@@ -302,8 +302,8 @@ size_t radix_ws_bytes(int64_t n_max) {
 // so lanes of a wave that share a digit (the high digits of depth keys take
 // few values) collide at most 64 / copies ways.  DEPTH: digits of the keys
 // relative to the depth range.
-template <int RB, bool DEPTH>
-__global__ __launch_bounds__(kOsThreads) void k_os_hist(const uint32_t* keys, int64_t n_max,
+template <int RB, bool DEPTH, typename KT = uint32_t>
+__global__ __launch_bounds__(kOsThreads) void k_os_hist(const KT* keys, int64_t n_max,
                                                         const unsigned long long* n_dev, int nbits, uint32_t* ghist,
                                                         uint64_t* status0, const uint32_t* range) {
     constexpr int KB = 1 << RB;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const uint32_t* keys, in
 #pragma unroll
         for (int i = 0; i < kOsItems; ++i) {
             const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
-            k_[i] = j < n ? keys[j] : 0u;
+            k_[i] = j < n ? (uint32_t)keys[j] : 0u;
             if constexpr (DEPTH) k_[i] = depth_rel(k_[i], dr);
         }
 #pragma unroll
@@ -380,9 +380,9 @@ struct DepthIO {
     int pass;
 };
 
-template <int MODE, int RB>
-__global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in, const uint32_t* vals_in,
-                                                        uint32_t* keys_out, uint32_t* vals_out, int64_t n_max,
+template <int MODE, int RB, typename KT = uint32_t>
+__global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const uint32_t* vals_in,
+                                                        KT* keys_out, uint32_t* vals_out, int64_t n_max,
                                                         const unsigned long long* n_dev, int shift, uint32_t mask,
                                                         const uint32_t* ghist, uint64_t* status,
                                                         uint64_t* status_next, uint32_t* ticket, SortGather g,
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
 #pragma unroll
     for (int i = 0; i < kOsItems; ++i) {
         const int64_t j = base + i * 64 + lane;
-        k_[i] = j < n ? keys_in[j] : 0u;
+        k_[i] = j < n ? (uint32_t)keys_in[j] : 0u;
         if constexpr (MODE == kPassDepth)
             if (dio.pass == 0) k_[i] = depth_rel(k_[i], dr);
     }
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
         if (q < m) {
             const uint32_t key = s_buf[q];
             pos[i] = s_goff[(key >> shift) & mask] + (uint32_t)q;
-            if (keys_out && (int64_t)pos[i] < n) keys_out[pos[i]] = key;
+            if (keys_out && (int64_t)pos[i] < n) keys_out[pos[i]] = (KT)key;
         }
     }
     __syncthreads();
@@ -557,9 +557,10 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const uint32_t* keys_in,
     }
 }
 
-int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
-                     const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
-                     const SortGather* last) {
+template <typename KT>
+int radix_sort_impl(const KT* kin, const uint32_t* vin, KT* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
+                    const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
+                    const SortGather* last) {
     *err = hipSuccess;
     const int passes = (nbits + kRadixBits - 1) / kRadixBits;
     const int final_buf = passes > 0 ? (passes - 1) & 1 : 0;
@@ -570,9 +571,9 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
     *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
     if (*err != hipSuccess) return final_buf;
     const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
-    hipLaunchKernelGGL((k_os_hist<kRadixBits, false>), dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev, nbits,
-                       s.ghist, s.status[0], nullptr);
-    const uint32_t* ksrc = kin;
+    hipLaunchKernelGGL((k_os_hist<kRadixBits, false, KT>), dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev,
+                       nbits, s.ghist, s.status[0], nullptr);
+    const KT* ksrc = kin;
     const uint32_t* vsrc = vin;
     const DepthIO none{};
     for (int p = 0; p < passes; ++p) {
@@ -581,15 +582,17 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
         SortGather g{};
         const uint32_t* pin = nullptr;
         uint32_t* pout = nullptr;
-        auto kern = k_os_pass<kPassPlain, kRadixBits>;
-        if (last && last->pay_in) {       // payload carried through every pass
-            g = *last;
-            pin = p == 0 ? last->pay_in : last->pay_buf[(p - 1) & 1];
-            pout = last->pay_buf[p & 1];
-            kern = fin ? k_os_pass<kPassUnpack, kRadixBits> : k_os_pass<kPassCarry, kRadixBits>;
-        } else if (fin && last && last->rect_in) {
-            g = *last;
-            kern = k_os_pass<kPassGather, kRadixBits>;
+        auto kern = k_os_pass<kPassPlain, kRadixBits, KT>;
+        if constexpr (sizeof(KT) == 4) {
+            if (last && last->pay_in) {       // payload carried through every pass
+                g = *last;
+                pin = p == 0 ? last->pay_in : last->pay_buf[(p - 1) & 1];
+                pout = last->pay_buf[p & 1];
+                kern = fin ? k_os_pass<kPassUnpack, kRadixBits> : k_os_pass<kPassCarry, kRadixBits>;
+            } else if (fin && last && last->rect_in) {
+                g = *last;
+                kern = k_os_pass<kPassGather, kRadixBits>;
+            }
         }
         hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(kOsThreads), 0, st, ksrc, vsrc,
                            fin && last && last->drop_keys ? nullptr : kbuf[out],
@@ -602,6 +605,18 @@ int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2]
     }
     *err = hipGetLastError();
     return final_buf;
+}
+
+int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
+                     const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
+                     const SortGather* last) {
+    return radix_sort_impl<uint32_t>(kin, vin, kbuf, vbuf, n_max, n_dev, nbits, ws, st, err, last);
+}
+
+int radix_sort_pairs16(const uint16_t* kin, const uint32_t* vin, uint16_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
+                       const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err) {
+    if (nbits > 16) { *err = hipErrorInvalidValue; return 0; }
+    return radix_sort_impl<uint16_t>(kin, vin, kbuf, vbuf, n_max, n_dev, nbits, ws, st, err, nullptr);
 }
 
 // The depth sort of the records (31-bit keys, +inf for culled records) with
@@ -624,7 +639,7 @@ int radix_sort_depth(const uint32_t* kin, const uint32_t* krange, int64_t n_part
     constexpr int kPasses = (31 + kDepthBits - 1) / kDepthBits;
     for (int p = 0; p < kPasses; ++p) {
         DepthIO io{kin, g.pay_in, {kbuf[0], kbuf[1]}, {vbuf[0], vbuf[1]}, {g.pay_buf[0], g.pay_buf[1]}, s.range, p};
-        hipLaunchKernelGGL((k_os_pass<kPassDepth, kDepthBits>), dim3((unsigned)nblocks), dim3(kOsThreads), 0, st,
+        hipLaunchKernelGGL((k_os_pass<kPassDepth, kDepthBits, uint32_t>), dim3((unsigned)nblocks), dim3(kOsThreads), 0, st,
                            nullptr, nullptr, nullptr, nullptr, n, nullptr, p * kDepthBits, (uint32_t)(kMaxBins - 1),
                            s.ghist + p * kMaxBins, s.status[p & 1], p + 1 < kPasses ? s.status[(p + 1) & 1] : nullptr,
                            s.tickets + p, g, nullptr, nullptr, io);
@@ -661,7 +676,8 @@ uint32_t sort_stalls() {
 
 // ----------------------------------------------------------- tile ranges
 // ranges[t] = [lower_bound(t), lower_bound(t+1)) over the sorted tile keys.
-__global__ void k_tile_ranges(const uint32_t* sorted, const unsigned long long* n_dev, int64_t n_max,
+template <typename KT>
+__global__ void k_tile_ranges(const KT* sorted, const unsigned long long* n_dev, int64_t n_max,
                               int64_t n_tiles, uint32_t* ranges) {
     // thread t finds lower_bound(t), the start of tile t and the end of
     // tile t - 1 (thread n_tiles finds the end of the last tile)
@@ -704,7 +720,15 @@ hipError_t tile_len_keys(const uint32_t* ranges, int64_t n_tiles, uint32_t* key,
 hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                        int64_t n_tiles, uint32_t* ranges, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_tile_ranges<uint32_t>, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, st,
+                       sorted_tile, n_dev, n_max, n_tiles, ranges);
+    return hipGetLastError();
+}
+
+hipError_t tile_ranges16(const uint16_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
+                         int64_t n_tiles, uint32_t* ranges, hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_ranges<uint16_t>, dim3((unsigned)((n_tiles + 1 + 255) / 256)), dim3(256), 0, st,
                        sorted_tile, n_dev, n_max, n_tiles, ranges);
     return hipGetLastError();
 }

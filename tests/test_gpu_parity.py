@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_2509_03775_amd import cgs, render, scenes as sc
 from harness import (BLOCKS, GRAD_TOL, IMAGE_TOL, compare_view, full_pixels, grad_error_stats, grad_errors,
-                     oracle_grad_image, oracle_render, oracle_scene_grads, record, rel_l2, say)
+                     oracle_grad_image, oracle_render, oracle_scene_grads, random_tiles, record, rel_l2, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -599,6 +599,38 @@ def test_depth_range_pass_counts(kind):
     say(f"  colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}")
     assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
     assert namb <= 0.01 * len(pix[0])
+    gcols, gfull = oracle_grad_image(wl, pix, base)
+    ogm, ogcb = oracle_scene_grads(wl, oracle_render(wl, pix, gcols))
+    gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
+    torch.cuda.synchronize()
+    errs = grad_errors(gm[0].cpu().numpy(), gcb[0].cpu().numpy(), ogm[0], ogcb[0])
+    say("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, e in errs.items():
+        assert e <= GRAD_TOL, (k, e)
+
+
+def test_more_than_65536_tiles():
+    """A batch of five 2400 x 1600 views (75 000 tiles, fewer than 256 per
+    side): instance tile keys need 17 bits, so binning keeps 32-bit keys
+    (batches of at most 65536 tiles store them in 16 bits).  Forward and
+    backward against the oracle on 24 random tiles per view."""
+    rng = np.random.default_rng(95)
+    s = sc.make_scene(rng, 6000, 256, 1, sc.screen_matched_mu(2400), clusters=True)
+    cams = [sc.pinhole(2400, 1600, (3.0 * np.sin(a), 0.3, -3.0 * np.cos(a))) for a in (0.0, 1.2, 2.4, 3.6, 4.8)]
+    tg = [rng.uniform(0, 1, (c.height, c.width, 3)).astype(np.float32) for c in cams]
+    wl = sc.Workload("tiles75k", [s], cams, np.zeros(5, np.int32), tg, False)
+    say("[more than 65536 tiles] 5 x 2400 x 1600")
+    r = gpu_renderer(wl)
+    r.forward()
+    torch.cuda.synchronize()
+    img, T, nl = r.image.cpu().numpy(), r.T_final.cpu().numpy(), r.n_last.cpu().numpy()
+    pix = [random_tiles(c, 24, 950 + v) for v, c in enumerate(cams)]
+    base = oracle_render(wl, pix)
+    for v, cam in enumerate(cams):
+        a, b = r.pix_off[v], r.pix_off[v + 1]
+        ec, et, mism, namb = compare_view(img[a:b], T[a:b], nl[a:b], cam, pix[v], base[v])
+        say(f"  view {v}: colour err {ec:.2e} T err {et:.2e} n_last mismatches {mism} ambiguous {namb}")
+        assert ec <= IMAGE_TOL and et <= IMAGE_TOL and mism == 0
     gcols, gfull = oracle_grad_image(wl, pix, base)
     ogm, ogcb = oracle_scene_grads(wl, oracle_render(wl, pix, gcols))
     gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
