@@ -250,12 +250,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // Wave-cooperative: a wavefront owns 64 consecutive records, whose slots are
 // one contiguous range.  The lanes walk that range 64 slots at a time, one
 // slot each (its record by a max-scan of per-record start marks),
-// so a record covering many tiles does not hold up the other 63; then each
-// lane adds its own record's slots of the chunk from LDS in slot order --
-// the same order, and so the same bits, as a sequential sum per record.
-// Zeros read in place of a slot not reached (global, never written: a
-// selection between it and a slot stays in the global address space).
-__device__ float kZeroSlot[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+// so a record covering many tiles does not hold up the other 63; only the
+// slots the walk reached are loaded, and each lane adds its own record's
+// reached slots of the chunk from LDS in slot order -- the order, and so the
+// bits, of a sequential sum per record (an unreached slot would add +0).
 
 __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ desc, const float* __restrict__ ginst,
                                                   const uint32_t* __restrict__ chunk_base,
@@ -308,7 +306,7 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
             mk = mk > carry ? mk : carry;
             carry = (uint32_t)__builtin_amdgcn_readlane((int)mk, 63);
             const uint32_t k = c0 + (uint32_t)lane;
-            float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            bool reached = false;
             if (k < total) {
                 // the last record of the wave whose slots start at or before k
                 const int lo = (int)mk - 1;
@@ -320,19 +318,27 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                 const uint32_t org = s_org[w][lo];
                 const uint2 ct = cutv[(int64_t)((org >> 16) + row) * vd.tiles_x + (org & 0xffffu) + (e - row * wq)];
                 const uint32_t kk = s_key[w][lo];
-                const bool reached = kk < ct.x || (kk == ct.x && rec0 + (uint32_t)lo < ct.y);
-                const float* src = reached ? ginst + 9 * ((int64_t)s_so[w][lo] + e) : kZeroSlot;
+                reached = kk < ct.x || (kk == ct.x && rec0 + (uint32_t)lo < ct.y);
+                if (reached) {
+                    const float* src = ginst + 9 * ((int64_t)s_so[w][lo] + e);
 #pragma unroll
-                for (int q = 0; q < 9; ++q) v[q] = src[q];
+                    for (int q = 0; q < 9; ++q) s_v[w][q][lane] = src[q];
+                }
             }
-#pragma unroll
-            for (int q = 0; q < 9; ++q) s_v[w][q][lane] = v[q];
+            const uint64_t rm = __ballot(reached);
             wave_sync();
-            const uint32_t a = start > c0 ? start : c0;
-            const uint32_t b = my_end < c0 + 64u ? my_end : c0 + 64u;
-            for (uint32_t j = a; j < b; ++j)
+            // this lane's record's reached slots of the chunk, in slot order
+            // (an unreached slot would add +0, which changes no nonzero sum)
+            const uint32_t a = start > c0 ? start - c0 : 0u;
+            const uint32_t b = my_end < c0 + 64u ? (my_end > c0 ? my_end - c0 : 0u) : 64u;
+            uint64_t mm = 0ull;
+            if (a < b) mm = rm & (b == 64u ? ~0ull : (1ull << b) - 1ull) & ~((1ull << a) - 1ull);
+            while (mm) {
+                const int j = (int)__builtin_ctzll(mm);
+                mm &= mm - 1ull;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) d[q] += s_v[w][q][j - c0];
+                for (int q = 0; q < 9; ++q) d[q] += s_v[w][q][j];
+            }
             wave_sync();
         }
     }
