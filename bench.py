@@ -59,8 +59,8 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", ("render_common.h", "cgs_internal.h")),
                   "k_blend_fwd": ("render_fwd.hip", ("render_common.h", "cgs_internal.h"))}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2, 0)): {"sources": "4622d2f2b2242d0f", "read": 2256381807, "write": 729645792},
-    ("k_blend_fwd", HEADLINE, (1, 2, 0)): {"sources": "64955dcb0cfe4f6e", "read": 1554720417, "write": 234926296},
+    ("k_blend_bwd", HEADLINE, (1, 2, 0)): {"sources": "80913f9ecd457dd1", "read": 2255229748, "write": 729730720},
+    ("k_blend_fwd", HEADLINE, (1, 2, 0)): {"sources": "8420eaf0a0559613", "read": 1552417757, "write": 235175272},
 }
 
 
@@ -418,19 +418,41 @@ def combined_roofline(stages_ms: dict, sb: dict, e_eval: int, step_ms: float) ->
     return {"roof_ms": t_roof, "step_ms": step_ms, "frac": t_roof / step_ms, "stages": per}
 
 
+def depth_sort_passes(wl: sc.Workload) -> int:
+    """Passes of 9-bit digits the records' depth sort takes: its keys are the
+    bit patterns of the FP32 camera depths in front of the near plane, sorted
+    relative to the least of them (host estimate; the device decides)."""
+    lo, hi = None, None
+    for v, cam in enumerate(wl.cameras):
+        m = wl.scenes[int(wl.view_scene[v])].means
+        z = (m @ cam.Rt[2, :3].astype(np.float32) + np.float32(cam.Rt[2, 3])).astype(np.float32)
+        z = z[z > np.float32(0.2)]
+        if z.size == 0:
+            continue
+        k = z.view(np.uint32)
+        lo = int(k.min()) if lo is None else min(lo, int(k.min()))
+        hi = int(k.max()) if hi is None else max(hi, int(k.max()))
+    bits = max(1, (hi - lo).bit_length()) if lo is not None else 1
+    return (bits + 8) // 9
+
+
 def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     """Algorithmic HBM bytes of one step, per stage: what the method must
-    read and write once (codebook rows counted once per unique row; radix
-    passes at 16 B per item: key+value in and out, plus one 4 B key read per
-    sort for the digit counts of all its passes).  Binning: the depth sort
-    (its last pass writes no keys but gathers each record's 8 B rectangle
-    and writes it with its 4 B count), the offsets scan (8 B per record),
-    the emission (20 B in per record, 8 B out per instance), the slot-offset
-    scan (8 B per record) and the tile sort.  The blends read only the walked instances W (positions before
-    the tile's termination): a 4 B record id plus the record's 36 B of blend
-    data each; the backward adds the record's tile rectangle and slot offset
-    (12 B) and writes a 36 B gradient slot; the chain rule reads those slots
-    back."""
+    read and write once (codebook rows counted once per unique row; a radix
+    pass reads and writes each item once, plus one key read per sort for the
+    digit counts of all its passes).  Binning: the depth sort (key, record
+    and packed rectangle, 12 B per record each way per pass, as many 9-bit
+    passes as the live depth range needs), the offsets scan (8 B per record),
+    the emission (20 B in per record, tile key + record out per instance,
+    the key in 2 B when the batch has at most 65536 tiles), the slot-offset
+    scan and the tile sort.  The blends read only the walked instances W
+    (positions before the tile's termination): a 4 B record id plus the
+    record's 36 B of blend data each; the backward adds the record's tile
+    rectangle and slot offset (12 B) and writes a 36 B gradient slot.  The
+    chain rule reads those slots back, the Gaussians in row order (8 B of
+    sorted row and id each) and writes dL/dmean, each wavefront's two partial
+    rows and the codebook gradient; the reduction stage is the row sort and
+    the merge of the partial rows."""
     N = sum(s.n for s in wl.scenes)
     Rrec = sum(wl.scenes[int(v)].n for v in wl.view_scene)
     K = sum(s.k for s in wl.scenes)
@@ -440,15 +462,18 @@ def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     M = n_inst
     tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in wl.cameras)
     tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
+    key_b = 2 if tiles <= 65536 else 4
     row_passes = (max(1, (K - 1).bit_length()) + 7) // 8
+    partials = 2 * ((N + 63) // 64) * 4 * RW
     out = {
         "preprocess": N * 16 + K * RW * b + Rrec * 52,
-        "binning": (4 * 16 + 20 + 8 + 20 + 8) * Rrec + (8 + 4 + tile_passes * 16) * M,
+        "binning": (depth_sort_passes(wl) * 24 + 4 + 8 + 20 + 8) * Rrec
+        + ((key_b + 4) + key_b + tile_passes * 2 * (key_b + 4)) * M,
         "blend_fwd": walked * 40 + P * 20,
         "loss": P * 36,
         "blend_bwd": walked * (40 + 12 + 36) + P * 24 + tiles * 8,
-        "chain": N * 16 + K * RW * b + Rrec * 20 + walked * 36 + tiles * 8 + N * (12 + 4 * RW),
-        "codebook_reduce": N * 8 + row_passes * 16 * N + 4 * N + N * 4 * RW + K * 4 * RW,
+        "chain": N * 16 + K * RW * b + Rrec * 20 + walked * 36 + tiles * 8 + N * 8 + N * 12 + partials + K * 4 * RW,
+        "codebook_reduce": N * 8 + row_passes * 16 * N + 4 * N + partials + K * 8,
     }
     out["total"] = sum(out.values())
     return out
