@@ -312,9 +312,11 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                 const int lo = (int)mk - 1;
                 const uint32_t e = k - s_start[w][lo];
                 const uint32_t wq = s_w[w][lo];
+                // e / wq: the quotient is a row of the rectangle (< 2^16), so
+                // the FP32 estimate is off by less than 1/64: one step each way
                 uint32_t row = (uint32_t)((float)e * __builtin_amdgcn_rcpf((float)wq));
-                while (row * wq > e) --row;
-                while ((row + 1) * wq <= e) ++row;
+                row -= row * wq > e ? 1u : 0u;
+                row += (row + 1) * wq <= e ? 1u : 0u;
                 const uint32_t org = s_org[w][lo];
                 const uint2 ct = cutv[(int64_t)((org >> 16) + row) * vd.tiles_x + (org & 0xffffu) + (e - row * wq)];
                 const uint32_t kk = s_key[w][lo];
@@ -418,7 +420,7 @@ template <int DT, int SHD>
 struct ShRegs {
     static constexpr int N = 3 * (SHD + 1) * (SHD + 1);
     float v[N];
-    __device__ void load(const SceneDesc&, int64_t, const GaussParams& gp, bool) {
+    __device__ void load(const SceneDesc&, int64_t, const GaussParams& gp, bool, int64_t = -1) {
 #pragma unroll
         for (int i = 0; i < N; ++i) v[i] = gp.sh[i];
     }
@@ -430,8 +432,9 @@ template <int SHD>
 struct ShRegs<CGS_BF16, SHD> {
     static constexpr int N = 3 * (SHD + 1) * (SHD + 1);
     uint32_t w[(N + 1) / 2];
-    __device__ void load(const SceneDesc& sd, int64_t g, const GaussParams&, bool vec) {
-        const uint16_t* row = static_cast<const uint16_t*>(sd.sh) + sd.idx_sh[g] * sd.sh_stride + sd.sh_col0;
+    __device__ void load(const SceneDesc& sd, int64_t g, const GaussParams&, bool vec, int64_t known = -1) {
+        const uint16_t* row = static_cast<const uint16_t*>(sd.sh) + (known >= 0 ? known : (int64_t)sd.idx_sh[g]) * sd.sh_stride +
+                              sd.sh_col0;
         if constexpr (N % 8 == 0) {
             if (vec) {      // host-checked: 16-byte aligned rows
                 const uint4* r4 = reinterpret_cast<const uint4*>(row);
@@ -684,17 +687,18 @@ __device__ inline RowOut row_out(const BatchDesc* desc, int part, int64_t row, i
 template <int DT, int SHD>
 __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const SceneDesc& sd, int64_t g, bool inb,
                                       const float* __restrict__ rec_grad, const uint32_t* __restrict__ rec_flag,
-                                      float* row, float (&dmu)[3]) {
+                                      float* row, float (&dmu)[3], int64_t known_row = -1) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     GaussParams gp;
-    const bool valid = inb && load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0);
+    const bool valid = inb && (known_row >= 0 ? load_gaussian_row<DT, SHD>(sd, g, known_row, gp, desc->vec_rows != 0)
+                                              : load_gaussian<DT, SHD>(sd, g, gp, desc->vec_rows != 0));
     GaussShape sh;
     float opac = 0.f;
     ShRegs<DT, SHD> shc;
     if (valid) {
         gaussian_shape(gp, sh);
         opac = 1.0f / (1.0f + __expf(-gp.logit));
-        shc.load(sd, g, gp, desc->vec_rows != 0);
+        shc.load(sd, g, gp, desc->vec_rows != 0, known_row);
     }
     dmu[0] = dmu[1] = dmu[2] = 0.f;
     float dSig[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
@@ -886,7 +890,9 @@ __global__ __launch_bounds__(256) void k_chain_rows(const BatchDesc* __restrict_
     const int64_t g = live ? (int64_t)sval[p0 + lane] - sd.g_off : 0;
 
     float row[RW], dmu[3];
-    const bool isl = chain_gaussian<DT, SHD>(desc, sd, g, live, rec_grad, rec_flag, row, dmu);
+    // the row is the sort key (a valid Gaussian's index; clamped otherwise)
+    const int64_t known = live ? (int64_t)key - sd.sr_row_off : 0;
+    const bool isl = chain_gaussian<DT, SHD>(desc, sd, g, live, rec_grad, rec_flag, row, dmu, known);
     if (live) gaussian_epilogue(desc, sd, s, g, dmu, row[7], isl, isl_flag);
 
     const int64_t n_rows = desc->sr_rows_total;

@@ -131,6 +131,39 @@ __device__ inline bool load_gaussian(const SceneDesc& sd, int64_t g, GaussParams
     return true;
 }
 
+// The same for a Gaussian whose codebook row is already known (single
+// codebook, row in range): the row loads do not wait for the index load;
+// the Gaussian is valid iff its index equals that row.
+template <int DT, int SHD>
+__device__ inline bool load_gaussian_row(const SceneDesc& sd, int64_t g, int64_t row, GaussParams& gp, bool vec) {
+    constexpr int NCO = (SHD + 1) * (SHD + 1);
+    const bool ok = sd.idx_sr[g] == row && sd.idx_sh[g] == row;
+    gp.mean[0] = sd.means[3 * g + 0];
+    gp.mean[1] = sd.means[3 * g + 1];
+    gp.mean[2] = sd.means[3 * g + 2];
+    const int64_t bsr = row * sd.sr_stride + sd.sr_col0;
+    const int64_t bsh = row * sd.sh_stride + sd.sh_col0;
+    if constexpr (SHD == 3) {
+        if (vec) {
+            float sr[8];
+            load_vec<DT, 8>(sd.sr, bsr, sr);
+            gp.ls[0] = sr[0]; gp.ls[1] = sr[1]; gp.ls[2] = sr[2];
+            gp.q[0] = sr[3]; gp.q[1] = sr[4]; gp.q[2] = sr[5]; gp.q[3] = sr[6];
+            gp.logit = sr[7];
+            load_vec<DT, 48>(sd.sh, bsh, gp.sh);
+            return ok;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gp.ls[i] = load_cb<DT>(sd.sr, bsr + i);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gp.q[i] = load_cb<DT>(sd.sr, bsr + 3 + i);
+    gp.logit = sd.opacity_mode ? load_cb<DT>(sd.sr, bsr + 7) : sd.opacity[g];
+#pragma unroll
+    for (int i = 0; i < 3 * NCO; ++i) gp.sh[i] = load_cb<DT>(sd.sh, bsh + i);
+    return ok;
+}
+
 // View-independent shape: scale, unit quaternion, R(q), M = R S, Sigma = M M^T.
 struct GaussShape {
     float s[3];
