@@ -23,13 +23,14 @@ def _stream_ptr(stream=None) -> int:
 class DeviceScene:
     """One scene's state on the GPU in the fused single-codebook layout:
     means float32 [N,3], idx int32 [N], codebook [K, 8 + 3(d+1)^2] in float32
-    or bfloat16 (row: log-scale 3, quaternion 4, opacity logit 1, SH)."""
+    or bfloat16 (row: log-scale 3, quaternion 4, opacity logit 1, SH).  The
+    codebook may be a row-strided view (rows padded for alignment)."""
 
     def __init__(self, means: torch.Tensor, idx: torch.Tensor, cb: torch.Tensor, sh_degree: int):
         assert means.dtype == torch.float32 and means.is_contiguous() and means.dim() == 2 and means.shape[1] == 3
         assert idx.dtype == torch.int32 and idx.is_contiguous() and idx.shape[0] == means.shape[0]
-        assert cb.dtype in (torch.float32, torch.bfloat16) and cb.is_contiguous()
-        assert cb.shape[1] == sc.row_width(sh_degree)
+        assert cb.dtype in (torch.float32, torch.bfloat16) and cb.dim() == 2 and cb.stride(1) == 1
+        assert cb.shape[1] == sc.row_width(sh_degree) and cb.stride(0) >= cb.shape[1]
         self.means, self.idx, self.cb, self.sh_degree = means, idx, cb, sh_degree
 
     @classmethod
@@ -42,7 +43,13 @@ class DeviceScene:
             cb = torch.from_numpy(bits.view(np.int16)).to(device).view(torch.bfloat16)
         else:
             cb = torch.from_numpy(np.ascontiguousarray(s.cb)).to(device)
-        return cls(means, idx, cb.contiguous(), s.sh_degree)
+        # rows padded to whole 128-byte lines: a Gaussian's row gather then
+        # touches one or two lines, never a line shared with the next row
+        k, r = cb.shape
+        line = 128 // cb.element_size()
+        store = torch.zeros((k, (r + line - 1) // line * line), dtype=cb.dtype, device=device)
+        store[:, :r] = cb
+        return cls(means, idx, store[:, :r], s.sh_degree)
 
     @property
     def n(self) -> int:
@@ -65,8 +72,8 @@ class DeviceScene:
         d.means = self.means.data_ptr()
         d.idx_sr = self.idx.data_ptr()
         d.idx_sh = self.idx.data_ptr()
-        d.sr = cgs.CbView(self.cb.data_ptr(), dt, self.r, self.k, 0, 0)
-        d.sh = cgs.CbView(self.cb.data_ptr(), dt, self.r, self.k, 8, 0)
+        d.sr = cgs.CbView(self.cb.data_ptr(), dt, self.cb.stride(0), self.k, 0, 0)
+        d.sh = cgs.CbView(self.cb.data_ptr(), dt, self.cb.stride(0), self.k, 8, 0)
         d.opacity_logit = None
         return d
 
@@ -323,10 +330,10 @@ def sgld_params(scene, master_sr: Optional[torch.Tensor] = None,
         p.sh, p.sh_stride, p.sh_col0 = sh.data_ptr(), int(sh.shape[1]), 0
     else:
         cb = scene.cb if scene.cb.dtype == torch.float32 else master_sr
-        assert cb is not None and cb.dtype == torch.float32 and cb.shape == scene.cb.shape
+        assert cb is not None and cb.dtype == torch.float32 and cb.shape == scene.cb.shape and cb.stride(1) == 1
         p.opacity_logit = None
-        p.sr, p.sr_stride, p.sr_col0 = cb.data_ptr(), int(cb.shape[1]), 0
-        p.sh, p.sh_stride, p.sh_col0 = cb.data_ptr(), int(cb.shape[1]), 8
+        p.sr, p.sr_stride, p.sr_col0 = cb.data_ptr(), int(cb.stride(0)), 0
+        p.sh, p.sh_stride, p.sh_col0 = cb.data_ptr(), int(cb.stride(0)), 8
     return p
 
 
