@@ -10,6 +10,7 @@
 #include <mutex>
 
 #include "cgs_internal.h"
+#include "wave_scan.h"
 
 namespace cgs {
 
@@ -142,6 +143,9 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_down(const uint32_t* in, co
     }
 }
 
+hipError_t scan_onepass(const uint32_t* in, int64_t n, uint32_t* out, unsigned long long* total,
+                        unsigned long long* bsum, hipStream_t st);
+
 hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out,
                     unsigned long long* total, unsigned long long* bsum, hipStream_t st) {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
@@ -149,6 +153,7 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_
         if (total) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bsum, (int64_t)0, total);
         return hipGetLastError();
     }
+    if (!perm) return scan_onepass(in, n, out, total, bsum, st);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kSortBlock), 0, st, in, perm, n, bsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bsum, nb, total);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kSortBlock), 0, st, in, perm, n, bsum, out);
@@ -268,6 +273,115 @@ __device__ inline uint32_t os_scan(uint32_t v, uint32_t* s_wave) {
         if (i < w) before += s_wave[i];
     __syncthreads();
     return before + inc - v;
+}
+
+// Single-pass exclusive scan (decoupled look-back, Merrill & Garland 2016):
+// a 512-thread workgroup takes a ticket (its tile of 8192 consecutive items,
+// in start order), sums its items, publishes its total, and wave 0 looks
+// back over 64 earlier tiles' states at a time until one holds an inclusive
+// prefix; each wave reads and writes its 1024 items 64 at a time (DPP wave
+// scans with a running carry).  st[0] is the
+// ticket counter and st[1 + t] tile t's state (2-bit flag, 62-bit sum), all
+// zero on entry.  Offsets are u32 (they wrap only past 2^32 instances, which
+// the capacity check rejects on the exact 64-bit total).
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanItems * kOsThreads;
+constexpr uint64_t kStVal = (1ull << 62) - 1ull;
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d, 64);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, 64);
+        v += ((unsigned long long)hi << 32) | lo;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kOsThreads) void k_scan_1p(const uint32_t* in, int64_t n, uint32_t* out,
+                                                        unsigned long long* total, unsigned long long* st) {
+    __shared__ uint32_t s_wave[kOsWaves];
+    __shared__ unsigned long long s_wsum[kOsWaves];
+    __shared__ unsigned long long s_excl;
+    __shared__ uint32_t s_ticket;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_ticket = (uint32_t)atomicAdd(&st[0], 1ull);
+    __syncthreads();
+    const int64_t b = s_ticket;
+    // wave w owns items [1024 w, 1024 w + 1024) of the tile, read 64 at a time
+    const int64_t wbase = b * kScanTile + (int64_t)w * (kScanItems * 64);
+    uint32_t v[kScanItems], inc[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t j = wbase + i * 64 + lane;
+        v[i] = j < n ? in[j] : 0u;
+    }
+    uint32_t carry = 0;
+    unsigned long long wtot = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const uint32_t x = wave_incl_sum_u32(v[i], lane);
+        inc[i] = carry + x;
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+        carry += t;
+        wtot += t;
+    }
+    if (lane == 0) { s_wave[w] = carry; s_wsum[w] = wtot; }
+    __syncthreads();
+    uint32_t woff = 0;
+#pragma unroll
+    for (int i = 0; i < kOsWaves; ++i)
+        if (i < w) woff += s_wave[i];
+    if (w == 0) {
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int i = 0; i < kOsWaves; ++i) tot += s_wsum[i];
+        uint64_t* const sts = reinterpret_cast<uint64_t*>(st + 1);   // tile states
+        uint64_t* mine = sts + b;
+        if (lane == 0) status_put(mine, (b == 0 ? kStInc : kStAgg) | tot);
+        unsigned long long excl = 0;
+        int64_t k = b - 1;
+        uint32_t spins = 0;
+        while (k >= 0) {
+            const int64_t kk = k - lane;              // lane 0: the nearest earlier tile
+            const uint64_t sk = kk >= 0 ? status_get(sts + kk) : kStInc;
+            const uint64_t f = sk >> 62;
+            const uint64_t incm = __ballot(f == 2), pending = __ballot(f == 0);
+            const int first = incm ? (int)__builtin_ctzll(incm) : 64;
+            const uint64_t need = first < 63 ? (2ull << first) - 1ull : ~0ull;
+            if (pending & need) {
+                if (++spins >= kSpinLimit) {
+                    if (lane == 0) atomicAdd(&g_sort_stalls, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            excl += wave_sum_u64(lane <= first ? (sk & kStVal) : 0ull);
+            if (first < 64) break;
+            k -= 64;
+        }
+        if (lane == 0) {
+            if (b > 0) status_put(mine, kStInc | (excl + tot));
+            s_excl = excl;
+            if ((b + 1) * kScanTile >= n && total) *total = excl + tot;
+        }
+    }
+    __syncthreads();
+    const uint32_t base = (uint32_t)s_excl + woff;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t j = wbase + i * 64 + lane;
+        if (j < n) out[j] = base + inc[i] - v[i];
+    }
+}
+
+hipError_t scan_onepass(const uint32_t* in, int64_t n, uint32_t* out, unsigned long long* total,
+                        unsigned long long* bsum, hipStream_t st) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipError_t e = fill_u32(bsum, 0u, 2 * (size_t)(nb + 1), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_1p, dim3((unsigned)nb), dim3(kOsThreads), 0, st, in, n, out, total, bsum);
+    return hipGetLastError();
 }
 
 struct SortWs {
