@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     const uint32_t key = depth_key[r];
     const uint32_t ntr = ntiles[r];
     const uint32_t nt = valid && cnt->n_inst_ok != 0ull ? ntr : 0u;
-    const uint32_t incl = wave_incl_scan(nt, lane);
+    const uint32_t incl = wave_incl_sum_u32(nt, lane);
     const uint32_t start = incl - nt;
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     const uint32_t so = chunk_base[wv] + start;     // the chunk's slots are contiguous
@@ -320,7 +320,8 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                 const uint32_t org = s_org[w][lo];
                 const uint2 ct = cutv[(int64_t)((org >> 16) + row) * vd.tiles_x + (org & 0xffffu) + (e - row * wq)];
                 const uint32_t kk = s_key[w][lo];
-                reached = kk < ct.x || (kk == ct.x && rec0 + (uint32_t)lo < ct.y);
+                // both words of the cut in one load (no short-circuit on ct.x)
+                reached = (kk < ct.x) | ((kk == ct.x) & (rec0 + (uint32_t)lo < ct.y));
                 if (reached) {
                     const float* src = ginst + 9 * ((int64_t)s_so[w][lo] + e);
 #pragma unroll
