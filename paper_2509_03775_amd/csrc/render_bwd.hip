@@ -985,7 +985,18 @@ __global__ __launch_bounds__(256) void k_merge_rows(const BatchDesc* __restrict_
         } else {
             const bool head = ((rs - sd.g_off) & 63) == 0;    // the row starts a wavefront
             acc = rpart[(2 * w0 + (head ? 0 : 1)) * RW + lane];
-            for (int64_t wq = w0 + 1; wq <= w1; ++wq) acc += rpart[2 * wq * RW + lane];
+            // the head partials of the later wavefronts, eight loads in
+            // flight, added in wavefront order (a row of a small codebook can
+            // span thousands of wavefronts)
+            int64_t wq = w0 + 1;
+            for (; wq + 8 <= w1 + 1; wq += 8) {
+                float a[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) a[t] = rpart[2 * (wq + t) * RW + lane];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) acc += a[t];
+            }
+            for (; wq <= w1; ++wq) acc += rpart[2 * wq * RW + lane];
         }
     }
     if (has_isl)

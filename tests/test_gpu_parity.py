@@ -639,3 +639,28 @@ def test_more_than_65536_tiles():
     say("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, e in errs.items():
         assert e <= GRAD_TOL, (k, e)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_tiny_codebook_rows_span_many_wavefronts(k):
+    """20 000 Gaussians sharing 1 or 2 codebook rows: in the fused chain rule
+    and reduction each row spans hundreds of wavefronts of the row-sorted
+    order, so its gradient is the merge of as many partial rows."""
+    rng = np.random.default_rng(97 + k)
+    s = sc.make_scene(rng, 20000, k, 3, sc.screen_matched_mu(160), clusters=True)
+    cams = [sc.pinhole(160, 120, (0.2, -0.1, -3.0))]
+    wl = sc.Workload(f"k{k}", [s], cams, np.array([0], np.int32),
+                     [rng.uniform(0, 1, (120, 160, 3)).astype(np.float32)], False)
+    say(f"[tiny codebook] K = {k}, N = 20000")
+    r = gpu_renderer(wl)
+    pix = [full_pixels(c) for c in cams]
+    base = oracle_render(wl, pix)
+    gcols, gfull = oracle_grad_image(wl, pix, base)
+    ogm, ogcb = oracle_scene_grads(wl, oracle_render(wl, pix, gcols))
+    r.forward()
+    gm, gcb = r.backward(torch.from_numpy(gfull).cuda())
+    torch.cuda.synchronize()
+    errs = grad_errors(gm[0].cpu().numpy(), gcb[0].cpu().numpy(), ogm[0], ogcb[0])
+    say("  " + " ".join(f"{kk}={v:.2e}" for kk, v in errs.items()))
+    for kk, e in errs.items():
+        assert e <= GRAD_TOL, (kk, e)
