@@ -216,6 +216,16 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         for (int v = 0; v < b->n_views; ++v)
             if (b->view_scene[v] == s) d.view_list[nv++] = v;
         d.scenes[s].vcount = nv - d.scenes[s].vfirst;
+        for (int k = d.scenes[s].vfirst; k < nv; ++k) d.views[d.view_list[k]].scene_vi = k - d.scenes[s].vfirst;
+    }
+    {   // Gaussian-major flag offsets (the same total as the view-major record wavefronts)
+        int64_t fw = 0;
+        for (int s = 0; s < b->n_scenes; ++s) {
+            SceneDesc& sd = d.scenes[s];
+            sd.flag_wave_off = fw;
+            fw += (sd.n + kWave - 1) / kWave * sd.vcount;
+        }
+        if (fw != d.n_rec_waves) return CGS_EINVAL;
     }
     const cgs_schedule* sch = b->schedule;
     h->wpb = (sch && (sch->blend_waves_per_block == 2 || sch->blend_waves_per_block == 4)) ? sch->blend_waves_per_block

@@ -29,7 +29,7 @@ constexpr int kRecF4 = 4;
 // ---------------------------------------------------------------- descriptors
 struct ViewDesc {
     int32_t W, H, tiles_x, tiles_y;
-    int32_t scene, pad0;
+    int32_t scene, scene_vi;   // the scene, and this view's place among the scene's views
     int64_t tile_off, pix_off, rec_off;
     int64_t rec_wave_off;   // wavefronts before this view when records are split view-aligned
     float fx, fy, cx, cy;
@@ -41,6 +41,11 @@ struct ViewDesc {
 struct SceneDesc {
     int64_t n, g_off;
     int64_t wave_off;       // wavefronts before this scene when Gaussians are split scene-aligned
+    // The nonzero flags of the records' gradients (two words per record
+    // wavefront) are stored Gaussian-major within a scene: wavefront q of the
+    // scene's vi-th view at flag_wave_off + q*vcount + vi, so the flags of one
+    // Gaussian's views share a line.
+    int64_t flag_wave_off;
     int64_t sr_rows, sh_rows, sr_row_off, sh_row_off;
     const float* means;
     const int32_t* idx_sr;

@@ -350,8 +350,10 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     for (int k = 0; k < 9; ++k) nz |= d[k] != 0.f;
     const uint64_t m = __ballot(nz);
     if (lane == 0) {
-        rec_flag[2 * wv] = (uint32_t)m;
-        rec_flag[2 * wv + 1] = (uint32_t)(m >> 32);
+        const SceneDesc& sd = desc->scenes[vd.scene];
+        const int64_t fw = sd.flag_wave_off + (wv - vd.rec_wave_off) * sd.vcount + vd.scene_vi;
+        rec_flag[2 * fw] = (uint32_t)m;
+        rec_flag[2 * fw + 1] = (uint32_t)(m >> 32);
     }
     if (nz) {
         float* out = rec_grad + 9 * r;
@@ -709,12 +711,14 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
     float dop = 0.f;
     // dL/d(record) of the next view is loaded while this view's math runs
     // (no load for records with a zero sum: one flag bit per record, two
-    // words per wavefront of the view's records)
+    // words per record wavefront, the words of one Gaussian's views side by
+    // side so that they share a line)
     float pre[9];
+    const uint32_t* flags = rec_flag + 2 * (sd.flag_wave_off + (g >> 6) * sd.vcount) + ((g >> 5) & 1);
     auto fetch_rec = [&](int vi) {
         const ViewDesc& v = desc->views[desc->view_list[sd.vfirst + vi]];
         uint32_t fw = 0u;
-        if (inb) fw = rec_flag[2 * (v.rec_wave_off + (g >> 6)) + ((g >> 5) & 1)];
+        if (inb) fw = flags[2 * vi];
         const float* src = rec_grad + 9 * (v.rec_off + g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) pre[i] = 0.f;
@@ -1049,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_chain_fp64(const BatchDesc* __restrict_
         float dop = 0.f;
         for (int vi = 0; vi < sd.vcount; ++vi) {
             const ViewDesc& vd = desc->views[desc->view_list[sd.vfirst + vi]];
-            const int64_t fw = 2 * (vd.rec_wave_off + (g >> 6)) + ((g >> 5) & 1);
+            const int64_t fw = 2 * (sd.flag_wave_off + (g >> 6) * sd.vcount + vi) + ((g >> 5) & 1);
             if (!((rec_flag[fw] >> (g & 31)) & 1u)) continue;
             float d[9];
             const float* src = rec_grad + 9 * (vd.rec_off + g);

@@ -30,7 +30,7 @@ def small_workload(kind: str) -> sc.Workload:
     if kind == "uniform4k_128px":
         return sc.make_workload("uniform4k_128px")
     rng = np.random.default_rng({"clusters20k_d3": 71, "clusters20k_d3_bf16": 72, "views3": 73,
-                                 "scenes3": 74, "ragged_d1": 75, "wide258": 76, "degenerate": 77}[kind])
+                                 "scenes3": 74, "ragged_d1": 75, "wide258": 76, "degenerate": 77, "mixed_views": 78}[kind])
     if kind in ("clusters20k_d3", "clusters20k_d3_bf16"):
         bf = kind.endswith("bf16")
         s = sc.make_scene(rng, 20000, 512, 3, sc.screen_matched_mu(200), clusters=True, bf16=bf)
@@ -48,6 +48,15 @@ def small_workload(kind: str) -> sc.Workload:
         cams = [sc.pinhole(64, 48, (0.0, 0.0, -3.0)), sc.pinhole(40, 72, (0.5, 0.0, -3.0)),
                 sc.pinhole(64, 64, (0.0, 0.5, -3.0))]
         return sc.Workload(kind, ss, cams, np.array([2, 0, 1], np.int32),
+                           [rng.uniform(0, 1, (c.height, c.width, 3)).astype(np.float32) for c in cams], False)
+    if kind == "mixed_views":
+        # scenes with 2, 3, 0 and 1 views, the views interleaved across the
+        # scenes, and a last scene of 130 Gaussians (a ragged last wavefront)
+        ss = [sc.make_scene(rng, n, k, 2, sc.screen_matched_mu(64), clusters=True) for n, k in
+              ((2500, 64), (4000, 200), (900, 100), (130, 16))]
+        cams = [sc.pinhole(64, 48, (3.0 * np.sin(a), 0.1, -3.0 * np.cos(a))) for a in (0.0, 0.7, 1.4, 2.1, 2.8)]
+        cams.append(sc.pinhole(72, 40, (0.2, -0.2, -3.0)))
+        return sc.Workload(kind, ss, cams, np.array([1, 0, 1, 3, 1, 0], np.int32),
                            [rng.uniform(0, 1, (c.height, c.width, 3)).astype(np.float32) for c in cams], False)
     if kind == "ragged_d1":
         s = sc.make_scene(rng, 3000, 100, 1, -3.2, clusters=False)
@@ -89,8 +98,8 @@ def gpu_renderer(wl: sc.Workload, **kw) -> render.Renderer:
     return r
 
 
-SMALL = ["uniform4k_128px", "clusters20k_d3", "clusters20k_d3_bf16", "views3", "scenes3", "ragged_d1", "wide258",
-         "degenerate"]
+SMALL = ["uniform4k_128px", "clusters20k_d3", "clusters20k_d3_bf16", "views3", "scenes3", "mixed_views", "ragged_d1",
+         "wide258", "degenerate"]
 
 
 @pytest.mark.parametrize("kind", SMALL)
@@ -178,7 +187,7 @@ def test_determinism():
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
 
 
-@pytest.mark.parametrize("kind", ["scenes3", "views3"])
+@pytest.mark.parametrize("kind", ["scenes3", "views3", "mixed_views"])
 def test_schedule_invariance(kind):
     """Waves per workgroup, tile order and the persistent tile queue change
     only the issue order: every output (image, T, n_last, every gradient) is
