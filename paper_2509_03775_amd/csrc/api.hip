@@ -198,6 +198,12 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
         vd.rec_wave_off = rwaves;
         rwaves += (b->scenes[s].n + kWave - 1) / kWave;
         vd.fx = c.fx; vd.fy = c.fy; vd.cx = c.cx; vd.cy = c.cy;
+        {   // each step rounded to FP32, the device's order
+            const volatile float hx = 0.5f * (float)c.width, hy = 0.5f * (float)c.height;
+            const volatile float qx = hx / c.fx, qy = hy / c.fy;
+            vd.limx = kClampFov * qx;
+            vd.limy = kClampFov * qy;
+        }
         memcpy(vd.Rt, c.Rt, sizeof(vd.Rt));
         memcpy(vd.campos, c.campos, sizeof(vd.campos));
         memcpy(vd.bg, c.bg, sizeof(vd.bg));

@@ -19,6 +19,7 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kReduceChunk = 64;        // sorted positions owned by one reduction wavefront
 constexpr int kMaxRowWidth = 8 + 48;    // ls3 q4 logit1 + degree-3 SH
 constexpr uint32_t kCulledKey = 0x7f800000u;   // +inf bits: sorts after every depth
+constexpr float kClampFov = 1.3f;       // Jacobian clamp, in half-fields of view
 // One blend record per (view, Gaussian): 64 B, i.e. four float4 at rec[4r]:
 //   [0] (u, v, -A/2 log2e, -B log2e)   [1] (-C/2 log2e, opacity, red, green)
 //   [2] (blue, tile rect lo, tile rect hi, first gradient slot within the
@@ -33,6 +34,9 @@ struct ViewDesc {
     int64_t tile_off, pix_off, rec_off;
     int64_t rec_wave_off;   // wavefronts before this view when records are split view-aligned
     float fx, fy, cx, cy;
+    // Jacobian clamp limits of the tangents, kClampFov * (W/2) / fx and the
+    // same in y, in FP32 as the skeleton takes them (set by the host)
+    float limx, limy;
     float Rt[12];
     float campos[3];
     float bg[3];

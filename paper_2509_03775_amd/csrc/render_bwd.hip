@@ -244,8 +244,9 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // tile slots, in row-major tile order, over the tiles whose backward walk
 // reached the record -- (depth key, record) ordered before the tile's cut.
 // Written as 9 floats per record, only for records with a nonzero sum; a bit
-// per record (two words per wavefront, records of one view per wavefront)
-// says which, so records no walk reached cost neither a write nor a read.
+// per record (two words per wavefront of 64 records of one view, the words of
+// a scene's views for the same 64 Gaussians side by side) says which, so
+// records no walk reached cost neither a write nor a read.
 //
 // Wave-cooperative: a wavefront owns 64 consecutive records, whose slots are
 // one contiguous range.  The lanes walk that range 64 slots at a time, one
@@ -463,10 +464,106 @@ struct ShRegs<CGS_BF16, SHD> {
     }
 };
 
-// fma in the arithmetic of the chain rule: FP32 for every Gaussian, FP64 for
-// the near-degenerate ones (below).
+// fma and reciprocal in the arithmetic of the chain rule: FP32 for every
+// Gaussian (the hardware reciprocal, 1 ulp), FP64 for the near-degenerate
+// ones (below).
 __device__ inline float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fma_r(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_r(double x) { return 1.0 / x; }
+
+// The shape, projection and conic the FP32 chain rule differentiates: the
+// forward's formulas with the hardware exp and reciprocals in place of the
+// skeleton's exp and IEEE divisions.  The skeleton's bits decide integers in
+// the forward (culling, depth keys, tile rectangles) and stay bitwise there;
+// the chain rule needs the derivatives at the same point, which a few ulp do
+// not move.  No cull test beyond the near plane (the same test as the
+// forward's, on the same camera point): a record with a nonzero gradient was
+// kept by the forward.
+__device__ inline void chain_shape_of(const GaussParams& gp, GaussShape& o) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o.s[i] = __expf(fminf(80.f, fmaxf(-80.f, gp.ls[i])));
+    float w = gp.q[0], x = gp.q[1], y = gp.q[2], z = gp.q[3];
+    const float n2 = w * w + x * x + y * y + z * z;
+    if (n2 > 0.0f) {
+        const float len = __builtin_sqrtf(n2);     // a normal number for any n2 > 0
+        const float il = __builtin_amdgcn_rcpf(len);
+        o.qlen = len;
+        w *= il; x *= il; y *= il; z *= il;
+    } else {
+        o.qlen = 0.0f;
+        w = 1.0f; x = 0.0f; y = 0.0f; z = 0.0f;
+    }
+    o.qn[0] = w; o.qn[1] = x; o.qn[2] = y; o.qn[3] = z;
+    o.R[0][0] = 1.0f - 2.0f * (y * y + z * z);
+    o.R[0][1] = 2.0f * (x * y - w * z);
+    o.R[0][2] = 2.0f * (x * z + w * y);
+    o.R[1][0] = 2.0f * (x * y + w * z);
+    o.R[1][1] = 1.0f - 2.0f * (x * x + z * z);
+    o.R[1][2] = 2.0f * (y * z - w * x);
+    o.R[2][0] = 2.0f * (x * z - w * y);
+    o.R[2][1] = 2.0f * (y * z + w * x);
+    o.R[2][2] = 1.0f - 2.0f * (x * x + y * y);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o.M[i][j] = o.R[i][j] * o.s[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            o.S[i][j] = o.M[i][0] * o.M[j][0] + o.M[i][1] * o.M[j][1] + o.M[i][2] * o.M[j][2];
+            o.S[j][i] = o.S[i][j];
+        }
+}
+
+__device__ inline bool project_chain(const ViewDesc& vd, const float* mu, const GaussShape& sh, ViewProj& p) {
+    float xc, yc, zc;
+    camera_point(vd, mu, xc, yc, zc);
+    p.xc = xc; p.yc = yc; p.zc = zc;
+    if (!(zc > kNear)) return false;
+    const float iz = __builtin_amdgcn_rcpf(zc);
+    const float tx = xc * iz, ty = yc * iz;
+    const float txc = fminf(vd.limx, fmaxf(-vd.limx, tx));
+    const float tyc = fminf(vd.limy, fmaxf(-vd.limy, ty));
+    p.tx = tx; p.ty = ty; p.txc = txc; p.tyc = tyc;
+    p.clx = !(tx >= -vd.limx && tx <= vd.limx);
+    p.cly = !(ty >= -vd.limy && ty <= vd.limy);
+    p.j00 = vd.fx * iz;
+    p.j02 = -(vd.fx * txc) * iz;
+    p.j11 = vd.fy * iz;
+    p.j12 = -(vd.fy * tyc) * iz;
+    const float* Rt = vd.Rt;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        p.T[0][j] = p.j00 * Rt[0 + j] + p.j02 * Rt[8 + j];
+        p.T[1][j] = p.j11 * Rt[4 + j] + p.j12 * Rt[8 + j];
+    }
+    float U[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) U[a][j] = p.T[a][0] * sh.S[0][j] + p.T[a][1] * sh.S[1][j] + p.T[a][2] * sh.S[2][j];
+    p.a = U[0][0] * p.T[0][0] + U[0][1] * p.T[0][1] + U[0][2] * p.T[0][2] + kBlur;
+    p.c = U[1][0] * p.T[1][0] + U[1][1] * p.T[1][1] + U[1][2] * p.T[1][2] + kBlur;
+    p.b = U[0][0] * p.T[1][0] + U[0][1] * p.T[1][1] + U[0][2] * p.T[1][2];
+    return true;
+}
+
+// The conic with the forward's island test (FP64 when the FP32 determinant
+// has lost its leading digits; those Gaussians are redone by k_chain_fp64).
+__device__ inline bool conic_chain(float a, float b, float c, float& A, float& B, float& C) {
+    const float det = a * c - b * b;
+    if (det > 0x1p-10f * (a * c)) {
+        const float id = __builtin_amdgcn_rcpf(det);
+        A = c * id; B = -b * id; C = a * id;
+        return false;
+    }
+    const double da = a, db = b, dc = c;
+    const double id = 1.0 / (da * dc - db * db);
+    A = (float)(dc * id); B = (float)(-db * id); C = (float)(da * id);
+    return true;
+}
 
 // One view's projected-parameter gradient d = dL/d(u, v, -A/2, -B, -C/2,
 // opacity, r, g, b) pulled back through the conic (A, B, C) = Sigma2D^-1,
@@ -510,7 +607,7 @@ __device__ inline void chain_geometry(const ViewDesc& vd, const ViewProj& p, con
     const Real dJ02 = dT[0][0] * Wm[8] + dT[0][1] * Wm[9] + dT[0][2] * Wm[10];
     const Real dJ11 = dT[1][0] * Wm[4] + dT[1][1] * Wm[5] + dT[1][2] * Wm[6];
     const Real dJ12 = dT[1][0] * Wm[8] + dT[1][1] * Wm[9] + dT[1][2] * Wm[10];
-    const Real iz = Real(1.f) / Real(p.zc), iz2 = iz * iz;
+    const Real iz = rcp_r(Real(p.zc)), iz2 = iz * iz;
     // camera-space gradient
     Real gx = Real(d[0]) * vd.fx * iz;
     Real gy = Real(d[1]) * vd.fy * iz;
@@ -618,7 +715,7 @@ __device__ inline void chain_shape(const Real (&dSig)[3][3], const GaussShape& s
     dq[0] = dq[1] = dq[2] = dq[3] = Real(0.f);
     if (sh.qlen > 0.f) {
         const Real proj = dqw * w + dqx * x + dqy * y + dqz * z;
-        const Real il = Real(1.f) / Real(sh.qlen);
+        const Real il = rcp_r(Real(sh.qlen));
         dq[0] = (dqw - w * proj) * il;
         dq[1] = (dqx - x * proj) * il;
         dq[2] = (dqy - y * proj) * il;
@@ -699,8 +796,8 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
     float opac = 0.f;
     ShRegs<DT, SHD> shc;
     if (valid) {
-        gaussian_shape(gp, sh);
-        opac = 1.0f / (1.0f + __expf(-gp.logit));
+        chain_shape_of(gp, sh);
+        opac = __builtin_amdgcn_rcpf(1.0f + __expf(-gp.logit));
         shc.load(sd, g, gp, desc->vec_rows != 0, known_row);
     }
     dmu[0] = dmu[1] = dmu[2] = 0.f;
@@ -741,9 +838,9 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
         for (int i = 0; i < 9; ++i) nz |= d[i] != 0.f;
         if (!nz || !valid) continue;
         ViewProj p;
-        if (!project_view(vd, gp.mean, sh, p)) continue;
+        if (!project_chain(vd, gp.mean, sh, p)) continue;
         float A, B, C;
-        isl |= conic_of(p.a, p.b, p.c, A, B, C);
+        isl |= conic_chain(p.a, p.b, p.c, A, B, C);
         dop += d[5];
         chain_geometry<float>(vd, p, sh, A, B, C, d, dSig, dmu);
         if constexpr (SHD >= 1) {
@@ -764,7 +861,7 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
         for (int i = 0; i < 3; ++i) asm volatile("" : "+v"(gp.ls[i]));
 #pragma unroll
         for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(gp.q[i]));
-        gaussian_shape(gp, sh);
+        chain_shape_of(gp, sh);
         float ds[3], dq[4];
         chain_shape<float>(dSig, sh, ds, dq);
 #pragma unroll

@@ -21,7 +21,6 @@ constexpr float kMaxAlpha = 0.99f;           // alpha saturates here
 constexpr float kMinT = 1e-4f;               // stop before T would drop below this
 constexpr float kNear = 0.2f;                // near-plane cull
 constexpr float kBlur = 0.3f;                // low-pass added to Sigma2D
-constexpr float kClampFov = 1.3f;            // Jacobian clamp, in half-fields of view
 
 // Real orthonormal spherical harmonics with the Condon-Shortley phase, as
 // polynomials in the unit direction (x, y, z); index j = l*l + l + m.
@@ -234,17 +233,24 @@ struct ViewProj {
 
 // Camera point, cull, Jacobian, Sigma2D and the tile rectangle.  Returns false
 // when the Gaussian is culled (behind the near plane or off the image).
+// The camera point W mu + t, in the skeleton's order of operations.
+__device__ inline void camera_point(const ViewDesc& vd, const float* mu, float& xc, float& yc, float& zc) {
+#pragma clang fp contract(off)
+    const float* Rt = vd.Rt;
+    xc = Rt[0] * mu[0]; xc = xc + Rt[1] * mu[1]; xc = xc + Rt[2] * mu[2]; xc = xc + Rt[3];
+    yc = Rt[4] * mu[0]; yc = yc + Rt[5] * mu[1]; yc = yc + Rt[6] * mu[2]; yc = yc + Rt[7];
+    zc = Rt[8] * mu[0]; zc = zc + Rt[9] * mu[1]; zc = zc + Rt[10] * mu[2]; zc = zc + Rt[11];
+}
+
 __device__ inline bool project_view(const ViewDesc& vd, const float* mu, const GaussShape& sh, ViewProj& p) {
 #pragma clang fp contract(off)
     const float* Rt = vd.Rt;
-    float xc = Rt[0] * mu[0]; xc = xc + Rt[1] * mu[1]; xc = xc + Rt[2] * mu[2]; xc = xc + Rt[3];
-    float yc = Rt[4] * mu[0]; yc = yc + Rt[5] * mu[1]; yc = yc + Rt[6] * mu[2]; yc = yc + Rt[7];
-    float zc = Rt[8] * mu[0]; zc = zc + Rt[9] * mu[1]; zc = zc + Rt[10] * mu[2]; zc = zc + Rt[11];
+    float xc, yc, zc;
+    camera_point(vd, mu, xc, yc, zc);
     p.xc = xc; p.yc = yc; p.zc = zc;
     if (!(zc > kNear)) return false;
     const float tx = xc / zc, ty = yc / zc;
-    const float limx = kClampFov * ((0.5f * (float)vd.W) / vd.fx);
-    const float limy = kClampFov * ((0.5f * (float)vd.H) / vd.fy);
+    const float limx = vd.limx, limy = vd.limy;
     const float txc = fminf(limx, fmaxf(-limx, tx));
     const float tyc = fminf(limy, fmaxf(-limy, ty));
     p.tx = tx; p.ty = ty; p.txc = txc; p.tyc = tyc;
