@@ -14,7 +14,7 @@ namespace cgs {
 
 // launchers defined in the other translation units
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*, uint32_t*,
-                             uint32_t*, uint32_t*, hipStream_t);
+                             uint32_t*, uint32_t*, uint32_t*, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
                        const DevCounters*, void*, bool, uint32_t*, hipStream_t);
@@ -280,7 +280,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     p.chunk_base = take(4 * (size_t)d.n_rec_waves + 4);
     p.ginst = take(4 * 9 * (size_t)cap);
     p.rec_grad = take(4 * 9 * (size_t)R);
-    p.rec_flag = take(8 * (size_t)d.n_rec_waves + 8);
+    p.rec_flag = take(32 * (size_t)d.n_rec_waves + 32);
     p.isl_flag = take(8 * (size_t)d.n_gauss_waves + 8);
     p.gtheta = take(4 * (size_t)d.row_width * (size_t)G);
     p.rpart = take(4 * (size_t)d.row_width * 2 * (size_t)d.n_gauss_waves);    // head and tail partial per wavefront
@@ -464,7 +464,7 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(upload_desc(h, ws, st));
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect),
-                              at<uint32_t>(ws, p.chunk_tot), at<uint32_t>(ws, p.krange), st));
+                              at<uint32_t>(ws, p.chunk_tot), at<uint32_t>(ws, p.krange), at<uint32_t>(ws, p.rec_flag), st));
     CGS_TRY(mark(h, 1, st));
     // backward gradient slots: each 64-record chunk owns a contiguous range
     // (chunks in record order); its base, needed only by the backward, is

@@ -244,9 +244,12 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_bwd(const BatchDesc* __restr
 // tile slots, in row-major tile order, over the tiles whose backward walk
 // reached the record -- (depth key, record) ordered before the tile's cut.
 // Written as 9 floats per record, only for records with a nonzero sum; a bit
-// per record (two words per wavefront of 64 records of one view, the words of
-// a scene's views for the same 64 Gaussians side by side) says which, so
-// records no walk reached cost neither a write nor a read.
+// per record says which, so records no walk reached cost neither a write nor
+// a read.  The bits of wavefront f (64 records of one view; a scene's views of
+// the same 64 Gaussians side by side, f = flag_wave_off + q vcount + vi) are
+// words 8 f and 8 f + 4, next to the forward's colour-clamp bits of the same
+// records (words 8 f + 4 h + 1..3), so the chain rule reads all four of a
+// record's flags with one 16-byte load.
 //
 // Wave-cooperative: a wavefront owns 64 consecutive records, whose slots are
 // one contiguous range.  The lanes walk that range 64 slots at a time, one
@@ -353,8 +356,8 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     if (lane == 0) {
         const SceneDesc& sd = desc->scenes[vd.scene];
         const int64_t fw = sd.flag_wave_off + (wv - vd.rec_wave_off) * sd.vcount + vd.scene_vi;
-        rec_flag[2 * fw] = (uint32_t)m;
-        rec_flag[2 * fw + 1] = (uint32_t)(m >> 32);
+        rec_flag[8 * fw] = (uint32_t)m;
+        rec_flag[8 * fw + 4] = (uint32_t)(m >> 32);
     }
     if (nz) {
         float* out = rec_grad + 9 * r;
@@ -632,11 +635,13 @@ __device__ inline void chain_geometry(const ViewDesc& vd, const ViewProj& p, con
 }
 
 // One view's colour gradient: c = max(0, sum Y k + 1/2) with Y of the unit
-// direction camera -> mean.  Accumulates dL/dk into dk and, for SH degree >= 1,
-// writes the direction's contribution to dL/dmean into gdir.
+// direction camera -> mean; bit ch of cm says the forward's channel ch was
+// above the clamp (its value, not recomputed here).  Accumulates dL/dk into
+// dk and, for SH degree >= 1, writes the direction's contribution to dL/dmean
+// into gdir.
 template <int DT, int SHD>
 __device__ inline void chain_colour(const ViewDesc& vd, const GaussParams& gp, ShRegs<DT, SHD>& shc, const float* d,
-                                    float* dk, float* gdir) {
+                                    uint32_t cm, float* dk, float* gdir) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
         shc.pin();
         float ex = gp.mean[0] - vd.campos[0], ey = gp.mean[1] - vd.campos[1], ez = gp.mean[2] - vd.campos[2];
@@ -646,12 +651,7 @@ __device__ inline void chain_colour(const ViewDesc& vd, const GaussParams& gp, S
         sh_basis<SHD>(x, y, z, Y);
         float dcol[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.5f;
-#pragma unroll
-            for (int j = 0; j < NCO; ++j) acc = fmaf(Y[j], shc[3 * j + ch], acc);
-            dcol[ch] = acc > 0.f ? d[6 + ch] : 0.f;
-        }
+        for (int ch = 0; ch < 3; ++ch) dcol[ch] = ((cm >> ch) & 1u) ? d[6 + ch] : 0.f;
 #pragma unroll
         for (int j = 0; j < NCO; ++j)
 #pragma unroll
@@ -807,19 +807,22 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
     for (int i = 0; i < 3 * NCO; ++i) dk[i] = 0.f;
     float dop = 0.f;
     // dL/d(record) of the next view is loaded while this view's math runs
-    // (no load for records with a zero sum: one flag bit per record, two
-    // words per record wavefront, the words of one Gaussian's views side by
-    // side so that they share a line)
+    // (no load for records with a zero sum).  The record's flags -- nonzero
+    // sum, and the three colour channels the forward did not clamp -- come in
+    // one 16-byte load; a Gaussian's views share a line.
     float pre[9];
-    const uint32_t* flags = rec_flag + 2 * (sd.flag_wave_off + (g >> 6) * sd.vcount) + ((g >> 5) & 1);
+    uint32_t pre_cm = 0u;
+    const uint32_t* flags = rec_flag + 8 * (sd.flag_wave_off + (g >> 6) * sd.vcount) + 4 * ((g >> 5) & 1);
     auto fetch_rec = [&](int vi) {
         const ViewDesc& v = desc->views[desc->view_list[sd.vfirst + vi]];
-        uint32_t fw = 0u;
-        if (inb) fw = flags[2 * vi];
+        uint4 fw = make_uint4(0u, 0u, 0u, 0u);
+        if (inb) fw = *reinterpret_cast<const uint4*>(flags + 8 * vi);
+        const uint32_t b = (uint32_t)g & 31u;
+        pre_cm = ((fw.y >> b) & 1u) | (((fw.z >> b) & 1u) << 1) | (((fw.w >> b) & 1u) << 2);
         const float* src = rec_grad + 9 * (v.rec_off + g);
 #pragma unroll
         for (int i = 0; i < 9; ++i) pre[i] = 0.f;
-        if ((fw >> (g & 31)) & 1u)
+        if ((fw.x >> b) & 1u)
 #pragma unroll
             for (int i = 0; i < 9; ++i) pre[i] = src[i];
     };
@@ -832,6 +835,7 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
         float d[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[i] = pre[i];
+        const uint32_t cm = pre_cm;
         if (vi + 1 < sd.vcount) fetch_rec(vi + 1);
         bool nz = false;
 #pragma unroll
@@ -845,12 +849,12 @@ __device__ inline bool chain_gaussian(const BatchDesc* __restrict__ desc, const 
         chain_geometry<float>(vd, p, sh, A, B, C, d, dSig, dmu);
         if constexpr (SHD >= 1) {
             float gdir[3];
-            chain_colour<DT, SHD>(vd, gp, shc, d, dk, gdir);
+            chain_colour<DT, SHD>(vd, gp, shc, d, cm, dk, gdir);
             dmu[0] += gdir[0];
             dmu[1] += gdir[1];
             dmu[2] += gdir[2];
         } else {
-            chain_colour<DT, SHD>(vd, gp, shc, d, dk, nullptr);
+            chain_colour<DT, SHD>(vd, gp, shc, d, cm, dk, nullptr);
         }
     }
 #pragma unroll
@@ -1150,8 +1154,11 @@ __global__ __launch_bounds__(256) void k_chain_fp64(const BatchDesc* __restrict_
         float dop = 0.f;
         for (int vi = 0; vi < sd.vcount; ++vi) {
             const ViewDesc& vd = desc->views[desc->view_list[sd.vfirst + vi]];
-            const int64_t fw = 2 * (sd.flag_wave_off + (g >> 6) * sd.vcount + vi) + ((g >> 5) & 1);
-            if (!((rec_flag[fw] >> (g & 31)) & 1u)) continue;
+            const uint4 fw = *reinterpret_cast<const uint4*>(rec_flag + 8 * (sd.flag_wave_off + (g >> 6) * sd.vcount + vi) +
+                                                             4 * ((g >> 5) & 1));
+            const uint32_t b = (uint32_t)g & 31u;
+            if (!((fw.x >> b) & 1u)) continue;
+            const uint32_t cm = ((fw.y >> b) & 1u) | (((fw.z >> b) & 1u) << 1) | (((fw.w >> b) & 1u) << 2);
             float d[9];
             const float* src = rec_grad + 9 * (vd.rec_off + g);
 #pragma unroll
@@ -1168,12 +1175,12 @@ __global__ __launch_bounds__(256) void k_chain_fp64(const BatchDesc* __restrict_
             chain_geometry<double>(vd, p, sh, A, B, C, d, dSig, dmu);
             if constexpr (SHD >= 1) {
                 float gdir[3];
-                chain_colour<DT, SHD>(vd, gp, shc, d, dk, gdir);
+                chain_colour<DT, SHD>(vd, gp, shc, d, cm, dk, gdir);
                 dmu[0] += gdir[0];
                 dmu[1] += gdir[1];
                 dmu[2] += gdir[2];
             } else {
-                chain_colour<DT, SHD>(vd, gp, shc, d, dk, nullptr);
+                chain_colour<DT, SHD>(vd, gp, shc, d, cm, dk, nullptr);
             }
         }
         double ds[3], dq[4];

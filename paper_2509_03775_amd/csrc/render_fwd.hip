@@ -16,7 +16,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
                                                     float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles,
                                                     uint32_t* __restrict__ prect, uint32_t* __restrict__ chunk_tot,
-                                                    uint32_t* __restrict__ krange) {
+                                                    uint32_t* __restrict__ krange, uint32_t* __restrict__ rec_flag) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
@@ -80,6 +80,19 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
             if (lane == 0) {
                 krange[2 * (vd.rec_wave_off + q)] = nlo;
                 krange[2 * (vd.rec_wave_off + q) + 1] = hi;
+            }
+        }
+        // Which colour channels the forward left above its clamp at zero
+        // (dL/d(SH) passes through those only): a bit per record and channel,
+        // two words each per wavefront, beside the words the backward sets
+        // for records with a nonzero gradient -- words 8 f + 4 h + (1, 2, 3)
+        // for wavefront f of the scene's Gaussian-major order and half h.
+        {
+            const uint64_t m0 = __ballot(r1.z > 0.f), m1 = __ballot(r1.w > 0.f), m2 = __ballot(r2.x > 0.f);
+            if (lane < 6) {
+                const int h = lane >= 3 ? 1 : 0, ch = lane - 3 * h;
+                const uint64_t m = ch == 0 ? m0 : (ch == 1 ? m1 : m2);
+                rec_flag[8 * (sd.flag_wave_off + q * sd.vcount + vi) + 4 * h + 1 + ch] = (uint32_t)(m >> (32 * h));
             }
         }
         // The wave's records are one contiguous 4 KB block: staged in LDS and
@@ -393,10 +406,10 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 // ------------------------------------------------------------------ launchers
 hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, float4* rec,
                              uint32_t* dk, uint2* tr, uint32_t* nt, uint32_t* prect, uint32_t* chunk_tot,
-                             uint32_t* krange, hipStream_t st) {
+                             uint32_t* krange, uint32_t* rec_flag, hipStream_t st) {
     if (n_gauss_waves <= 0) return hipSuccess;
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot, krange)
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot, krange, rec_flag)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
                        case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }
