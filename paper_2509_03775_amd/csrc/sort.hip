@@ -184,7 +184,11 @@ hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_
 constexpr int kOsThreads = 512;             // 8 waves
 constexpr int kOsWaves = kOsThreads / 64;
 constexpr int kOsItems = 16;                // keys per lane
-constexpr int kOsTile = kOsItems * kOsThreads;   // 8192 keys per workgroup
+constexpr int kOsTile = kOsItems * kOsThreads;   // 8192 keys per workgroup (the smallest tile: workspaces are sized by it)
+// 16-bit keys take 20 per lane: a digit's run in a 10240-key tile is about
+// 80 bytes of keys instead of 64, fewer partial-line writes per pass
+template <typename KT>
+constexpr int os_items() { return sizeof(KT) == 2 ? 20 : kOsItems; }
 constexpr int kOsHistBlocks = 512;
 constexpr int kDepthBits = 9;               // digit width of the depth sort
 constexpr int kMaxBins = 1 << kDepthBits;
@@ -416,18 +420,19 @@ size_t radix_ws_bytes(int64_t n_max) {
 // so lanes of a wave that share a digit (the high digits of depth keys take
 // few values) collide at most 64 / copies ways.  DEPTH: digits of the keys
 // relative to the depth range.
-template <int RB, bool DEPTH, typename KT = uint32_t>
+template <int RB, bool DEPTH, typename KT = uint32_t, int IT = kOsItems>
 __global__ __launch_bounds__(kOsThreads) void k_os_hist(const KT* keys, int64_t n_max,
                                                         const unsigned long long* n_dev, int nbits, uint32_t* ghist,
                                                         uint64_t* status0, const uint32_t* range) {
     constexpr int KB = 1 << RB;
+    constexpr int TILE = IT * kOsThreads;
     constexpr int kCopies = 8 >> (RB - 8);
     __shared__ uint32_t h[4 * KB * kCopies];
     for (int i = threadIdx.x; i < 4 * KB * kCopies; i += kOsThreads) h[i] = 0;
     __syncthreads();
     const uint32_t copy = threadIdx.x % kCopies;
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t nb = (n + kOsTile - 1) / kOsTile;
+    const int64_t nb = (n + TILE - 1) / TILE;
     int passes = (nbits + RB - 1) / RB;
     DepthRange dr{};
     if constexpr (DEPTH) {
@@ -436,16 +441,16 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const KT* keys, int64_t 
     }
     for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
         if (threadIdx.x < KB) status0[t * KB + threadIdx.x] = 0ull;
-        uint32_t k_[kOsItems];
+        uint32_t k_[IT];
 #pragma unroll
-        for (int i = 0; i < kOsItems; ++i) {
-            const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
+        for (int i = 0; i < IT; ++i) {
+            const int64_t j = t * TILE + (int64_t)i * kOsThreads + threadIdx.x;
             k_[i] = j < n ? (uint32_t)keys[j] : 0u;
             if constexpr (DEPTH) k_[i] = depth_rel(k_[i], dr);
         }
 #pragma unroll
-        for (int i = 0; i < kOsItems; ++i) {
-            const int64_t j = t * kOsTile + (int64_t)i * kOsThreads + threadIdx.x;
+        for (int i = 0; i < IT; ++i) {
+            const int64_t j = t * TILE + (int64_t)i * kOsThreads + threadIdx.x;
             if (j < n)
                 for (int p = 0; p < passes; ++p) {
                     const uint32_t d = (k_[i] >> (p * RB)) & pass_mask<RB>(nbits, p);
@@ -463,8 +468,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_hist(const KT* keys, int64_t 
         }
 }
 
-// One pass.  Wave w of the workgroup owns keys [w * 1024, w * 1024 + 1024)
-// of the tile and walks them 64 at a time; ranks are computed in that item
+// One pass.  Wave w of the workgroup owns keys [64 IT w, 64 IT (w + 1)) of
+// the tile (IT keys per lane) and walks them 64 at a time; ranks are computed in that item
 // order (wave, step, lane), which keeps the sort stable: for each step the
 // lanes OR their bit into an LDS mask per (wave, digit), read it back (the
 // lanes sharing their digit), and the lowest of them advances the wave's
@@ -494,7 +499,7 @@ struct DepthIO {
     int pass;
 };
 
-template <int MODE, int RB, typename KT = uint32_t>
+template <int MODE, int RB, typename KT = uint32_t, int IT = kOsItems>
 __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const uint32_t* vals_in,
                                                         KT* keys_out, uint32_t* vals_out, int64_t n_max,
                                                         const unsigned long long* n_dev, int shift, uint32_t mask,
@@ -502,6 +507,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
                                                         uint64_t* status_next, uint32_t* ticket, SortGather g,
                                                         const uint32_t* pay_in, uint32_t* pay_out, DepthIO dio) {
     constexpr int KB = 1 << RB;
+    constexpr int TILE = IT * kOsThreads;
     constexpr bool PAY = MODE == kPassCarry || MODE == kPassUnpack || MODE == kPassDepth;
     bool fin = MODE == kPassGather || MODE == kPassUnpack;    // writes the final rectangles
     DepthRange dr{};
@@ -522,8 +528,8 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     __shared__ uint32_t cnt[kOsWaves][KB];
     // The peer masks are needed only while ranking, the staging buffer only
     // after it (two barriers later): they share the same LDS.
-    __shared__ __align__(16) uint32_t s_buf[kOsTile];
-    static_assert(sizeof(unsigned long long) * kOsWaves * KB <= sizeof(uint32_t) * kOsTile, "peer masks");
+    __shared__ __align__(16) uint32_t s_buf[TILE];
+    static_assert(sizeof(unsigned long long) * kOsWaves * KB <= sizeof(uint32_t) * TILE, "peer masks");
     unsigned long long (*s_peer)[KB] = reinterpret_cast<unsigned long long (*)[KB]>(s_buf);
     __shared__ uint32_t s_goff[KB];
     __shared__ uint32_t s_wave[kOsWaves];
@@ -537,16 +543,16 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     __syncthreads();
     const int64_t b = s_ticket;
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t blk0 = b * kOsTile;
+    const int64_t blk0 = b * TILE;
     if (blk0 >= n) return;
     const bool dig = threadIdx.x < KB;
     const uint32_t d = dig ? threadIdx.x : 0u;
     if (status_next && dig) status_next[b * KB + d] = 0ull;
-    const int64_t base = blk0 + (int64_t)w * (kOsItems * 64);
-    uint32_t k_[kOsItems], v_[kOsItems], p_[PAY ? kOsItems : 1];
-    uint32_t lp[kOsItems];
+    const int64_t base = blk0 + (int64_t)w * (IT * 64);
+    uint32_t k_[IT], v_[IT], p_[PAY ? IT : 1];
+    uint32_t lp[IT];
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const int64_t j = base + i * 64 + lane;
         k_[i] = j < n ? (uint32_t)keys_in[j] : 0u;
         if constexpr (MODE == kPassDepth)
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     }
     const unsigned long long bit = 1ull << lane;
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const bool live = base + i * 64 + lane < n;
         const uint32_t dd = (k_[i] >> shift) & mask;
         lp[i] = 0xffffffffu;
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     uint64_t* mine = status + b * KB + d;
     if (dig) status_put(mine, (b == 0 ? kStInc : (kStAgg | ((uint64_t)b << 32))) | (uint64_t)tot);
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const int64_t j = base + i * 64 + lane;
         v_[i] = j < n ? (vals_in ? vals_in[j] : (uint32_t)j) : 0u;
         if constexpr (PAY) p_[i] = j < n ? pay_in[j] : 0u;
@@ -591,7 +597,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
         for (int i = 0; i < kOsWaves; ++i) cnt[i][d] = dstart + wb[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i)
+    for (int i = 0; i < IT; ++i)
         if (lp[i] != 0xffffffffu) {
             lp[i] += cnt[w][(k_[i] >> shift) & mask];
             s_buf[lp[i]] = k_[i];
@@ -617,10 +623,10 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     }
     if (dig) s_goff[d] = gstart + excl - dstart;
     __syncthreads();
-    const int m = (int)(n - blk0 < kOsTile ? n - blk0 : kOsTile);
-    uint32_t pos[kOsItems];
+    const int m = (int)(n - blk0 < TILE ? n - blk0 : TILE);
+    uint32_t pos[IT];
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const int q = i * kOsThreads + (int)threadIdx.x;
         pos[i] = 0xffffffffu;
         if (q < m) {
@@ -631,11 +637,11 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i)
+    for (int i = 0; i < IT; ++i)
         if (lp[i] != 0xffffffffu) s_buf[lp[i]] = v_[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kOsItems; ++i) {
+    for (int i = 0; i < IT; ++i) {
         const int q = i * kOsThreads + (int)threadIdx.x;
         if (q < m && (int64_t)pos[i] < n) {
             const uint32_t v = s_buf[q];
@@ -651,11 +657,11 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
     if constexpr (PAY) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kOsItems; ++i)
+        for (int i = 0; i < IT; ++i)
             if (lp[i] != 0xffffffffu) s_buf[lp[i]] = p_[i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kOsItems; ++i) {
+        for (int i = 0; i < IT; ++i) {
             const int q = i * kOsThreads + (int)threadIdx.x;
             if (q < m && (int64_t)pos[i] < n) {
                 const uint32_t pw = s_buf[q];
@@ -676,16 +682,18 @@ int radix_sort_impl(const KT* kin, const uint32_t* vin, KT* kbuf[2], uint32_t* v
                     const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
                     const SortGather* last) {
     *err = hipSuccess;
+    constexpr int IT = os_items<KT>();
+    constexpr int64_t TILE = IT * kOsThreads;
     const int passes = (nbits + kRadixBits - 1) / kRadixBits;
     const int final_buf = passes > 0 ? (passes - 1) & 1 : 0;
-    const int64_t nblocks = (n_max + kOsTile - 1) / kOsTile;
+    const int64_t nblocks = (n_max + TILE - 1) / TILE;
     if (nblocks == 0 || nbits <= 0) return final_buf;
     if (passes > 4) { *err = hipErrorInvalidValue; return final_buf; }
     const SortWs s = sort_ws(ws, n_max);
     *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
     if (*err != hipSuccess) return final_buf;
     const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
-    hipLaunchKernelGGL((k_os_hist<kRadixBits, false, KT>), dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev,
+    hipLaunchKernelGGL((k_os_hist<kRadixBits, false, KT, IT>), dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev,
                        nbits, s.ghist, s.status[0], nullptr);
     const KT* ksrc = kin;
     const uint32_t* vsrc = vin;
@@ -696,7 +704,7 @@ int radix_sort_impl(const KT* kin, const uint32_t* vin, KT* kbuf[2], uint32_t* v
         SortGather g{};
         const uint32_t* pin = nullptr;
         uint32_t* pout = nullptr;
-        auto kern = k_os_pass<kPassPlain, kRadixBits, KT>;
+        auto kern = k_os_pass<kPassPlain, kRadixBits, KT, IT>;
         if constexpr (sizeof(KT) == 4) {
             if (last && last->pay_in) {       // payload carried through every pass
                 g = *last;
