@@ -29,7 +29,8 @@ hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, bool, const uint32_t
                             const uint8_t*, const uint32_t*, const uint32_t*, const float*, const float*,
                             const int32_t*, float*, uint2*, DevCounters*, hipStream_t);
 hipError_t launch_slot_sum(const BatchDesc*, int64_t, const float*, const uint32_t*, const uint32_t*, const uint2*,
-                           const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*, hipStream_t);
+                           const uint32_t*, const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*,
+                           hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const uint32_t*, float*, uint32_t*,
                         const uint32_t*, const uint32_t*, const uint32_t*, float*, hipStream_t);
 hipError_t launch_merge_rows(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const float*, const float*,
@@ -650,7 +651,8 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     uint32_t* rflag = at<uint32_t>(ws, p.rec_flag);
     uint32_t* islf = at<uint32_t>(ws, p.isl_flag);
     CGS_TRY(launch_slot_sum(dd, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.chunk_base), at<uint32_t>(ws, p.ntiles),
-                            at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.depth_key), at<uint2>(ws, p.tile_cut), cnt,
+                            at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.prect), at<uint32_t>(ws, p.depth_key),
+                            at<uint2>(ws, p.tile_cut), cnt,
                             rgrad, rflag, st));
     if (single) {
         // Single codebook: the chain rule walks the Gaussians in row order and

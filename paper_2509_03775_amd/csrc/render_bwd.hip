@@ -263,6 +263,7 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                                                   const uint32_t* __restrict__ chunk_base,
                                                   const uint32_t* __restrict__ ntiles,
                                                   const uint2* __restrict__ tile_rect,
+                                                  const uint32_t* __restrict__ prect,
                                                   const uint32_t* __restrict__ depth_key,
                                                   const uint2* __restrict__ tile_cut,
                                                   const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad,
@@ -276,12 +277,23 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
     const int64_t i0 = (wv - vd.rec_wave_off) * kWave;
     const int64_t i = i0 + lane;
     const bool valid = i < desc->scenes[vd.scene].n;
-    // the record's four words are loaded together (lanes past the end read
-    // the wave's first record and own no slots)
+    // the record's words are loaded together (lanes past the end read the
+    // wave's first record and own no slots); with every view below 256 tiles
+    // per side the rectangle is one packed word (x0 | y0 << 8 | x1 << 16 |
+    // y1 << 24, zero when culled) and the tile count follows from it
     const int64_t r = vd.rec_off + (valid ? i : i0);
-    const uint2 tr = tile_rect[r];
+    uint2 tr;
+    uint32_t ntr;
+    if (desc->pack_rect) {
+        const uint32_t pr = prect[r];
+        const uint32_t x0 = pr & 0xffu, y0 = (pr >> 8) & 0xffu, x1 = (pr >> 16) & 0xffu, y1 = pr >> 24;
+        tr = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
+        ntr = (x1 - x0) * (y1 - y0);
+    } else {
+        tr = tile_rect[r];
+        ntr = ntiles[r];
+    }
     const uint32_t key = depth_key[r];
-    const uint32_t ntr = ntiles[r];
     const uint32_t nt = valid && cnt->n_inst_ok != 0ull ? ntr : 0u;
     const uint32_t incl = wave_incl_sum_u32(nt, lane);
     const uint32_t start = incl - nt;
@@ -1385,11 +1397,11 @@ hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, b
 }
 
 hipError_t launch_slot_sum(const BatchDesc* d_desc, int64_t n_rec_waves, const float* ginst, const uint32_t* eo,
-                           const uint32_t* nt, const uint2* tr, const uint32_t* dk, const uint2* cut,
-                           const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, hipStream_t st) {
+                           const uint32_t* nt, const uint2* tr, const uint32_t* prect, const uint32_t* dk,
+                           const uint2* cut, const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, hipStream_t st) {
     if (n_rec_waves > 0)
         hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
-                           nt, tr, dk, cut, cnt, rec_grad, rec_flag);
+                           nt, tr, prect, dk, cut, cnt, rec_grad, rec_flag);
     return hipGetLastError();
 }
 
