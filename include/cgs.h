@@ -375,7 +375,10 @@ cgs_status cgs_loss_l1(const float* image, const float* target, int64_t n, float
  *   Sigma2D), L = log2(e), o (uint32 bits) the offset of the record's first
  *   backward gradient slot within its 64-record chunk; depth_key uint32 [R]
  *   (0x7f800000 when culled);
- *   tile_rect uint32[R][2] ((x0 | y0 << 16), (x1 | y1 << 16));
+ *   tile_rect uint32[R][2] ((x0 | y0 << 16), (x1 | y1 << 16)), written only
+ *   when some view of the batch is 256 tiles or more across or down (below
+ *   that the rectangle travels packed in one word); the same two words are
+ *   always words 9 and 10 of the record (zero when culled);
  * inst_rec uint32 [capacity] record of each sorted instance; tile_range
  *   uint32 [tiles][2]. */
 typedef struct {

@@ -51,9 +51,12 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = make_float4(0.f, 0.f, 0.f, __uint_as_float(incl - nt));
         if (inb && !keep) {
             depth_key[r] = kCulledKey;
-            tile_rect[r] = make_uint2(0u, 0u);
-            if (desc->pack_rect) prect[r] = 0u;     // the tile count follows from the packed rectangle
-            else ntiles[r] = 0u;
+            if (desc->pack_rect) {
+                prect[r] = 0u;      // the tile count follows from the packed rectangle
+            } else {
+                tile_rect[r] = make_uint2(0u, 0u);
+                ntiles[r] = 0u;
+            }
         } else if (inb) {
             float A, B, C;
             conic_of(vp.a, vp.b, vp.c, A, B, C);
@@ -62,12 +65,13 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
             depth_key[r] = __float_as_uint(vp.zc);
             const uint32_t rlo = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 16);
             const uint32_t rhi = (uint32_t)vp.tx1 | ((uint32_t)vp.ty1 << 16);
-            tile_rect[r] = make_uint2(rlo, rhi);
-            if (desc->pack_rect)
+            if (desc->pack_rect) {
                 prect[r] = (uint32_t)vp.tx0 | ((uint32_t)vp.ty0 << 8) | ((uint32_t)vp.tx1 << 16) |
                            ((uint32_t)vp.ty1 << 24);
-            else
+            } else {
+                tile_rect[r] = make_uint2(rlo, rhi);
                 ntiles[r] = nt;
+            }
             r0 = make_float4(vp.u, vp.v, (-0.5f * kLog2e) * A, -kLog2e * B);
             r1 = make_float4((-0.5f * kLog2e) * C, opac, col[0], col[1]);
             r2 = make_float4(col[2], __uint_as_float(rlo), __uint_as_float(rhi), __uint_as_float(incl - nt));
