@@ -449,7 +449,9 @@ def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     (positions before the tile's termination): a 4 B record id plus the
     record's 36 B of blend data each; the backward adds the record's tile
     rectangle and slot offset (12 B) and writes a 36 B gradient slot.  The
-    chain rule reads those slots back, the Gaussians in row order (8 B of
+    chain rule reads those slots back (with each record's depth key and its
+    rectangle, one packed word when every view is below 256 tiles per side,
+    else 8 B and a 4 B tile count), the Gaussians in row order (8 B of
     sorted row and id each) and writes dL/dmean, each wavefront's two partial
     rows and the codebook gradient; the reduction stage is the row sort and
     the merge of the partial rows."""
@@ -465,6 +467,8 @@ def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
     key_b = 2 if tiles <= 65536 else 4
     row_passes = (max(1, (K - 1).bit_length()) + 7) // 8
     partials = 2 * ((N + 63) // 64) * 4 * RW
+    packed = all((c.width + 15) // 16 < 256 and (c.height + 15) // 16 < 256 for c in wl.cameras)
+    rect_b = 4 if packed else 12
     out = {
         "preprocess": N * 16 + K * RW * b + Rrec * 52,
         "binning": (depth_sort_passes(wl) * 24 + 4 + 8 + 20 + 8) * Rrec
@@ -472,7 +476,7 @@ def step_bytes(wl: sc.Workload, n_inst: int, walked: int) -> dict:
         "blend_fwd": walked * 40 + P * 20,
         "loss": P * 36,
         "blend_bwd": walked * (40 + 12 + 36) + P * 24 + tiles * 8,
-        "chain": N * 16 + K * RW * b + Rrec * 20 + walked * 36 + tiles * 8 + N * 8 + N * 12 + partials + K * 4 * RW,
+        "chain": N * 16 + K * RW * b + Rrec * (8 + rect_b) + walked * 36 + tiles * 8 + N * 8 + N * 12 + partials + K * 4 * RW,
         "codebook_reduce": N * 8 + row_passes * 16 * N + 4 * N + partials + K * 8,
     }
     out["total"] = sum(out.values())

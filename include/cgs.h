@@ -369,9 +369,9 @@ cgs_status cgs_loss_l1(const float* image, const float* target, int64_t n, float
 /* Offsets (bytes from the workspace base) of the forward's intermediate
  * arrays for a batch, for inspection and tests.  Any pointer may be NULL.
  * records: R = sum over views of the view's scene size, record r of view v is
- *   Gaussian r - rec_off(v) of that scene; records float4 [R][4], 64 B each:
+ *   Gaussian r - rec_off(v) of that scene; records float4 [R][3], 48 B each:
  *   (u, v, -A/2 L, -B L), (-C/2 L, opacity, red, green), (blue, tile_rect[0]
- *   bits, tile_rect[1] bits, o), padding -- A, B, C the conic (inverse of
+ *   bits, tile_rect[1] bits, o) -- A, B, C the conic (inverse of
  *   Sigma2D), L = log2(e), o (uint32 bits) the offset of the record's first
  *   backward gradient slot within its 64-record chunk; depth_key uint32 [R]
  *   (0x7f800000 when culled);

@@ -20,12 +20,13 @@ constexpr int kReduceChunk = 64;        // sorted positions owned by one reducti
 constexpr int kMaxRowWidth = 8 + 48;    // ls3 q4 logit1 + degree-3 SH
 constexpr uint32_t kCulledKey = 0x7f800000u;   // +inf bits: sorts after every depth
 constexpr float kClampFov = 1.3f;       // Jacobian clamp, in half-fields of view
-// One blend record per (view, Gaussian): 64 B, i.e. four float4 at rec[4r]:
+// One blend record per (view, Gaussian): 48 B, i.e. three float4 at rec[3r]:
 //   [0] (u, v, -A/2 log2e, -B log2e)   [1] (-C/2 log2e, opacity, red, green)
 //   [2] (blue, tile rect lo, tile rect hi, first gradient slot within the
-//   record's 64-record chunk)   [3] unused padding
-// so the blends' gather of a record is one 64-byte segment.
-constexpr int kRecF4 = 4;
+//   record's 64-record chunk).  No padding to 64 B: the preprocess writes a
+//   quarter less, and the blends' gathers (half of them now straddling two
+//   64-byte segments) come from L2 and are not what bounds the blends.
+constexpr int kRecF4 = 3;
 
 // ---------------------------------------------------------------- descriptors
 struct ViewDesc {

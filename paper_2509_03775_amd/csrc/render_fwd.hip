@@ -100,12 +100,11 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
                 rec_flag[8 * (sd.flag_wave_off + q * sd.vcount + vi) + 4 * h + 1 + ch] = (uint32_t)(m >> (32 * h));
             }
         }
-        // The wave's records are one contiguous 4 KB block: staged in LDS and
-        // written 1 KB per store instruction (whole lines), padding included.
+        // The wave's records are one contiguous 3 KB block: staged in LDS and
+        // written 1 KB per store instruction (whole lines but at the ends).
         s_rec[w][kRecF4 * lane + 0] = r0;
         s_rec[w][kRecF4 * lane + 1] = r1;
         s_rec[w][kRecF4 * lane + 2] = r2;
-        s_rec[w][kRecF4 * lane + 3] = make_float4(0.f, 0.f, 0.f, 0.f);
         wave_sync();
         float4* dst = rec + kRecF4 * (vd.rec_off + q * kWave);
 #pragma unroll

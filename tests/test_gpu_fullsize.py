@@ -49,7 +49,7 @@ def test_skeleton_every_gaussian_bit_exact(name):
     R = lay.n_records
     ws = r.ws
     key = ws[lay.depth_key:lay.depth_key + 4 * R].view(torch.int32).cpu().numpy().view(np.uint32)
-    tr = ws[lay.records:lay.records + 64 * R].view(torch.int32).view(R, 16)[:, 9:11].contiguous().cpu().numpy().view(np.uint32)
+    tr = ws[lay.records:lay.records + 48 * R].view(torch.int32).view(R, 12)[:, 9:11].contiguous().cpu().numpy().view(np.uint32)
     off = 0
     for v, cam in enumerate(wl.cameras):
         s = wl.scenes[int(wl.view_scene[v])]
@@ -76,7 +76,7 @@ def test_binning_properties(name):
     ws = r.ws
     M = r.instances()
     key = ws[lay.depth_key:lay.depth_key + 4 * R].view(torch.int32).cpu().numpy().view(np.uint32)
-    tr = ws[lay.records:lay.records + 64 * R].view(torch.int32).view(R, 16)[:, 9:11].contiguous().cpu().numpy().view(np.uint32)
+    tr = ws[lay.records:lay.records + 48 * R].view(torch.int32).view(R, 12)[:, 9:11].contiguous().cpu().numpy().view(np.uint32)
     rec = ws[lay.inst_rec:lay.inst_rec + 4 * M].view(torch.int32).cpu().numpy().view(np.uint32)
     rng_ = ws[lay.tile_range:lay.tile_range + 8 * T].view(torch.int32).cpu().numpy().view(np.uint32).reshape(T, 2)
     x0, y0 = (tr[:, 0] & 0xFFFF).astype(np.int64), (tr[:, 0] >> 16).astype(np.int64)

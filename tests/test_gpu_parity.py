@@ -112,7 +112,7 @@ def test_skeleton_bit_exact(kind):
     ws = r.ws.cpu().numpy()
     R = lay.n_records
     key = ws[lay.depth_key:lay.depth_key + 4 * R].view(np.uint32)
-    tr = ws[lay.records:lay.records + 64 * R].view(np.uint32).reshape(R, 16)[:, 9:11]   # the record's rectangle words
+    tr = ws[lay.records:lay.records + 48 * R].view(np.uint32).reshape(R, 12)[:, 9:11]   # the record's rectangle words
     off = 0
     for v, cam in enumerate(wl.cameras):
         s = wl.scenes[int(wl.view_scene[v])]
