@@ -186,7 +186,9 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
 /* Backward of the forward render for dL/dimage = grad_image [P,3] (device).
  * Must follow cgs_render_forward on the same batch, workspace and outputs
  * (T_final, n_last as the forward wrote them; the per-pixel transmittance of
- * every blended Gaussian is recomputed from T_final by division, not stored).
+ * every blended Gaussian is recomputed from T_final by division, not stored;
+ * the codebook indices unchanged since the forward, which also ordered the
+ * Gaussians by codebook row for this call).
  * Writes, per scene, dL/dmeans and dL/dcodebook: the per-Gaussian parameter
  * gradients summed over Gaussians sharing a codebook row (the gradient of
  * S_diff needed by the update step, Sec. 4.4).  Deterministic: every sum is

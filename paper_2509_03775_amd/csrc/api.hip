@@ -59,7 +59,7 @@ struct WsPlan {
     size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
-    size_t radix_ws, scan_bsum, scan_bsum2;
+    size_t radix_ws, radix_ws_rows, scan_bsum, scan_bsum2;
     size_t chunk_tot, krange, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, rpart, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t scan_blocks_max;
@@ -273,6 +273,7 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     for (int i = 0; i < 2; ++i) { p.tperm_key[i] = take(4 * (size_t)T); p.tperm_val[i] = take(4 * (size_t)T); }
     const int64_t nmax = std::max(std::max(R, cap), std::max(G, T));   // every sort and scan below
     p.radix_ws = take(radix_ws_bytes(nmax));
+    p.radix_ws_rows = take(radix_ws_bytes(std::max<int64_t>(G, 1)));   // the row sort runs beside the forward's sorts
     p.scan_blocks_max = (int64_t)scan_bsum_count(nmax);
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
     p.scan_bsum2 = take(8 * (size_t)p.scan_blocks_max);
@@ -446,6 +447,25 @@ cgs_status cgs_workspace_layout(const cgs_batch* batch, cgs_ws_layout* out) {
     return CGS_OK;
 }
 
+// Buffer of the Gaussians' row order (psort_key/val[b]) after the forward's
+// row sort: the last of its 8-bit passes writes buffer (passes - 1) & 1.
+int row_sort_buf(const Host& h) { return (passes_for(bits_for(h.d.sr_rows_total)) - 1) & 1; }
+
+// The Gaussians sorted by codebook row (single-codebook layout: the SR and
+// SH rows are the same), and each row's range of the sorted order.
+hipError_t sort_rows(const Host& h, void* ws, const BatchDesc* dd, hipStream_t s2) {
+    const WsPlan& p = h.p;
+    uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
+    uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
+    hipError_t e = launch_row_keys(dd, 0, h.d.n_gauss, pk[1], s2);
+    if (e != hipSuccess) return e;
+    const int pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(h.d.sr_rows_total),
+                                    at<char>(ws, p.radix_ws_rows), s2, &e);
+    if (e != hipSuccess) return e;
+    if (pb != row_sort_buf(h)) return hipErrorUnknown;
+    return tile_ranges(pk[pb], nullptr, h.d.n_gauss, h.d.sr_rows_total, at<uint32_t>(ws, p.row_start), s2);
+}
+
 cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_final, int32_t* n_last, void* ws,
                               size_t ws_bytes, int64_t* d_info, void* stream) {
     static thread_local Host h;
@@ -481,6 +501,11 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     }
     CGS_TRY(scan_u32(at<uint32_t>(ws, p.chunk_tot), nullptr, h.d.n_rec_waves, at<uint32_t>(ws, p.chunk_base), nullptr,
                      at<unsigned long long>(ws, p.scan_bsum2), side ? side->s : st));
+    // Single-codebook layout: the Gaussians in codebook-row order, which the
+    // backward's fused chain rule and row reduction walk.  It depends only on
+    // the indices, so it runs beside the binning on the side stream (inline
+    // without one), with a sort workspace of its own.
+    if (h.fused) CGS_TRY(sort_rows(h, ws, dd, side ? side->s : st));
     // depth order of every record (stable: ties keep record order)
     uint32_t* dk[2] = {at<uint32_t>(ws, p.dsort_key[0]), at<uint32_t>(ws, p.dsort_key[1])};
     uint32_t* dv[2] = {at<uint32_t>(ws, p.dsort_val[0]), at<uint32_t>(ws, p.dsort_val[1])};
@@ -618,27 +643,14 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     uint32_t* pk[2] = {at<uint32_t>(ws, p.psort_key[0]), at<uint32_t>(ws, p.psort_key[1])};
     uint32_t* pv[2] = {at<uint32_t>(ws, p.psort_val[0]), at<uint32_t>(ws, p.psort_val[1])};
     uint32_t* rr = at<uint32_t>(ws, p.row_start);
-    // Single-codebook layout: the sort of Gaussians by row depends only on
-    // the indices, so it runs on the side stream beside the backward blend
-    // and the chain rule.
-    auto sort_rows = [&](int part_i, int64_t rows, hipStream_t s2, int* pb) -> hipError_t {
-        hipError_t e = launch_row_keys(dd, part_i, h.d.n_gauss, pk[1], s2);
+    // the two-codebook layout sorts the Gaussians by each codebook's rows here
+    auto sort_part = [&](int part_i, int64_t rows, int* pb) -> hipError_t {
+        hipError_t e = launch_row_keys(dd, part_i, h.d.n_gauss, pk[1], st);
         if (e != hipSuccess) return e;
-        *pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), sws, s2, &e);
+        *pb = radix_sort_pairs(pk[1], nullptr, pk, pv, h.d.n_gauss, nullptr, bits_for(rows), sws, st, &e);
         if (e != hipSuccess) return e;
-        return tile_ranges(pk[*pb], nullptr, h.d.n_gauss, rows, rr, s2);
+        return tile_ranges(pk[*pb], nullptr, h.d.n_gauss, rows, rr, st);
     };
-    Side* side = single ? side_stream(st) : nullptr;
-    std::unique_lock<std::mutex> side_lk;
-    SideGuard guard;        // declared after the lock: joins before it is released
-    int pb0 = 0;
-    if (side) {
-        side_lk = std::unique_lock<std::mutex>(side->mu);
-        CGS_TRY(side_fork(side, st));
-        guard.sd = side;
-        guard.st = st;
-        CGS_TRY(sort_rows(0, h.d.sr_rows_total, side->s, &pb0));
-    }
     float* ginst = at<float>(ws, p.ginst);
     CGS_TRY(launch_blend_bwd(dd, h.d.n_tiles, h.wpb, h.persist, at<uint32_t>(ws, p.tile_range),
                              at<uint32_t>(ws, p.inst_val[h.inst_buf]),
@@ -656,10 +668,9 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
                             rgrad, rflag, st));
     if (single) {
         // Single codebook: the chain rule walks the Gaussians in row order and
-        // reduces the rows itself (the row sort must be done first).
-        int pb = pb0;
-        if (side) CGS_TRY(guard.join());
-        else CGS_TRY(sort_rows(0, h.d.sr_rows_total, st, &pb));
+        // reduces the rows itself, in the order the forward sorted (the
+        // indices are the forward's: a backward follows its forward)
+        const int pb = row_sort_buf(h);
         CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, rgrad, rflag, gth, islf,
                              pk[pb], pv[pb], rr, at<float>(ws, p.rpart), st));
         CGS_TRY(mark(h, 6, st));
@@ -674,7 +685,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
             const int c0 = part_i == 0 ? 0 : 8;
             const int D = part_i == 0 ? (h.opacity_mode ? 8 : 7) : h.d.row_width - 8;
             int pb = 0;
-            CGS_TRY(sort_rows(part_i, rows, st, &pb));
+            CGS_TRY(sort_part(part_i, rows, &pb));
             CGS_TRY(launch_reduce(dd, part_i, gth, h.d.row_width, c0, D, 0, pk[pb], pv[pb], h.d.n_gauss, rows, rr, st));
         }
     }
