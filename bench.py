@@ -59,8 +59,8 @@ LAMBDA_SSIM = 0.2      # SSIM weight of the training-step form (Eq. 4)
 KERNEL_SOURCES = {"k_blend_bwd": ("render_bwd.hip", ("render_common.h", "cgs_internal.h")),
                   "k_blend_fwd": ("render_fwd.hip", ("render_common.h", "cgs_internal.h"))}
 MEASURED_TRAFFIC = {
-    ("k_blend_bwd", HEADLINE, (1, 2, 0)): {"sources": "80913f9ecd457dd1", "read": 2255229748, "write": 729730720},
-    ("k_blend_fwd", HEADLINE, (1, 2, 0)): {"sources": "8420eaf0a0559613", "read": 1552417757, "write": 235175272},
+    ("k_blend_bwd", HEADLINE, (1, 2, 0)): {"sources": "f4bcba27555d1b28", "read": 2652921741, "write": 729509792},
+    ("k_blend_fwd", HEADLINE, (1, 2, 0)): {"sources": "1eea37c3c85d2bd7", "read": 1924680201, "write": 234854864},
 }
 
 
