@@ -14,7 +14,7 @@ namespace cgs {
 
 // launchers defined in the other translation units
 hipError_t launch_preprocess(const BatchDesc*, int, int, int64_t, float4*, uint32_t*, uint2*, uint32_t*, uint32_t*,
-                             uint32_t*, uint32_t*, uint32_t*, hipStream_t);
+                             uint32_t*, uint32_t*, uint32_t*, const ZeroSpans&, hipStream_t);
 hipError_t launch_capacity(DevCounters*, int64_t, int64_t*, hipStream_t);
 hipError_t launch_emit(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const uint2*, const uint32_t*,
                        const DevCounters*, void*, bool, uint32_t*, hipStream_t);
@@ -59,7 +59,7 @@ struct WsPlan {
     size_t offs, rect_d, cnt_d;
     size_t inst_key[2], inst_val[2];
     size_t tile_range, tile_cut, qbits, tperm_key[2], tperm_val[2];
-    size_t radix_ws, radix_ws_rows, scan_bsum, scan_bsum2;
+    size_t radix_ws, radix_ws_tile, radix_ws_tlen, radix_ws_rows, scan_bsum, scan_bsum2;
     size_t chunk_tot, krange, chunk_base, ginst, rec_grad, rec_flag, isl_flag, gtheta, rpart, psort_key[2], psort_val[2], row_start;
     size_t total;
     int64_t scan_blocks_max;
@@ -274,6 +274,10 @@ cgs_status plan_batch(const cgs_batch* b, Host* h) {
     const int64_t nmax = std::max(std::max(R, cap), std::max(G, T));   // every sort and scan below
     p.radix_ws = take(radix_ws_bytes(nmax));
     p.radix_ws_rows = take(radix_ws_bytes(std::max<int64_t>(G, 1)));   // the row sort runs beside the forward's sorts
+    // the tile sort and the tile-length sort have their own, so that the
+    // preprocess can zero all three sorts' counters up front
+    p.radix_ws_tile = take(radix_ws_bytes(std::max<int64_t>(cap, 1)));
+    p.radix_ws_tlen = take(radix_ws_bytes(std::max<int64_t>(T, 1)));
     p.scan_blocks_max = (int64_t)scan_bsum_count(nmax);
     p.scan_bsum = take(8 * (size_t)p.scan_blocks_max);
     p.scan_bsum2 = take(8 * (size_t)p.scan_blocks_max);
@@ -483,9 +487,19 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     CGS_TRY(mark(h, 0, st));
     h.d.tile_perm = at<const uint32_t>(ws, p.tperm_val[h.tperm_buf]);
     CGS_TRY(upload_desc(h, ws, st));
+    // the preprocess zeroes the counters of the depth sort, the instance
+    // offset scan, the tile sort and the tile-length sort (no fill launches)
+    void* sws_tile = at<char>(ws, p.radix_ws_tile);
+    void* sws_tlen = at<char>(ws, p.radix_ws_tlen);
+    ZeroSpans zero{};
+    zero.p[0] = sort_counters(sws, h.d.n_rec, &zero.n[0]);
+    zero.p[1] = scan_states(bsum, h.d.n_rec, &zero.n[1]);
+    zero.p[2] = sort_counters(sws_tile, h.d.capacity, &zero.n[2]);
+    zero.p[3] = sort_counters(sws_tlen, h.d.n_tiles, &zero.n[3]);
     CGS_TRY(launch_preprocess(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, at<float4>(ws, p.rec), at<uint32_t>(ws, p.depth_key),
                               at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.ntiles), at<uint32_t>(ws, p.prect),
-                              at<uint32_t>(ws, p.chunk_tot), at<uint32_t>(ws, p.krange), at<uint32_t>(ws, p.rec_flag), st));
+                              at<uint32_t>(ws, p.chunk_tot), at<uint32_t>(ws, p.krange), at<uint32_t>(ws, p.rec_flag),
+                              zero, st));
     CGS_TRY(mark(h, 1, st));
     // backward gradient slots: each 64-record chunk owns a contiguous range
     // (chunks in record order); its base, needed only by the backward, is
@@ -522,12 +536,13 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     }
     const int db = h.d.pack_rect
                        ? radix_sort_depth(at<uint32_t>(ws, p.depth_key), at<uint32_t>(ws, p.krange), h.d.n_rec_waves,
-                                          dk, dv, h.d.n_rec, sws, st, &e, rg)
+                                          dk, dv, h.d.n_rec, sws, st, &e, rg, true)
                        : radix_sort_pairs(at<uint32_t>(ws, p.depth_key), nullptr, dk, dv, h.d.n_rec, nullptr, 31, sws,
-                                          st, &e, &rg);
+                                          st, &e, &rg, true);
     CGS_TRY(e);
     // instance offsets in depth order, capacity check, emission
-    CGS_TRY(scan_u32(at<uint32_t>(ws, p.cnt_d), nullptr, h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st));
+    CGS_TRY(scan_u32(at<uint32_t>(ws, p.cnt_d), nullptr, h.d.n_rec, at<uint32_t>(ws, p.offs), &cnt->n_inst, bsum, st,
+                     true));
     CGS_TRY(launch_capacity(cnt, h.d.capacity, d_info, st));
     uint32_t* ik[2] = {at<uint32_t>(ws, p.inst_key[0]), at<uint32_t>(ws, p.inst_key[1])};
     uint32_t* iv[2] = {at<uint32_t>(ws, p.inst_val[0]), at<uint32_t>(ws, p.inst_val[1])};
@@ -538,13 +553,15 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
     int ib;
     if (key16) {
         uint16_t* ik16[2] = {reinterpret_cast<uint16_t*>(ik[0]), reinterpret_cast<uint16_t*>(ik[1])};
-        ib = radix_sort_pairs16(ik16[1], iv[1], ik16, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
+        ib = radix_sort_pairs16(ik16[1], iv[1], ik16, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws_tile, st, &e,
+                                true);
         CGS_TRY(e);
         if (ib != h.inst_buf) return CGS_EHIP;
         CGS_TRY(tile_ranges16(ik16[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range),
                               st));
     } else {
-        ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws, st, &e);
+        ib = radix_sort_pairs(ik[1], iv[1], ik, iv, h.d.capacity, &cnt->n_inst_ok, h.tile_bits, sws_tile, st, &e,
+                              nullptr, true);
         CGS_TRY(e);
         if (ib != h.inst_buf) return CGS_EHIP;
         CGS_TRY(tile_ranges(ik[ib], &cnt->n_inst_ok, h.d.capacity, h.d.n_tiles, at<uint32_t>(ws, p.tile_range), st));
@@ -553,7 +570,8 @@ cgs_status cgs_render_forward(const cgs_batch* batch, float* image, float* T_fin
         uint32_t* tk[2] = {at<uint32_t>(ws, p.tperm_key[0]), at<uint32_t>(ws, p.tperm_key[1])};
         uint32_t* tv[2] = {at<uint32_t>(ws, p.tperm_val[0]), at<uint32_t>(ws, p.tperm_val[1])};
         CGS_TRY(tile_len_keys(at<uint32_t>(ws, p.tile_range), h.d.n_tiles, tk[1], st));
-        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, kTileLenKeyBits, sws, st, &e);
+        const int tb = radix_sort_pairs(tk[1], nullptr, tk, tv, h.d.n_tiles, nullptr, kTileLenKeyBits, sws_tlen, st, &e,
+                                        nullptr, true);
         CGS_TRY(e);
         if (tb != h.tperm_buf) return CGS_EHIP;
     }

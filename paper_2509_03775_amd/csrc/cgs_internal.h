@@ -303,8 +303,21 @@ hipError_t fill_u32(void* dst, uint32_t value, size_t count, hipStream_t st);
 
 // Exclusive scan of n u32 values read through `perm` (NULL = identity):
 // out[j] = sum_{i<j} in[perm[i]]; *total = sum of all (u64).
+// zeroed: the scan's tile states (scan_states) were zeroed beforehand.
 hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out,
-                    unsigned long long* total, unsigned long long* bsum, hipStream_t st);
+                    unsigned long long* total, unsigned long long* bsum, hipStream_t st, bool zeroed = false);
+
+// Up to four spans of u32 words a kernel zeroes on its way, so that the sorts
+// and scans after it need no fill launches of their own (unused spans: n 0).
+struct ZeroSpans {
+    uint32_t* p[4];
+    uint32_t n[4];
+};
+// The words a radix sort over n_max items in `ws` (digit counts, tickets,
+// depth range), or a one-pass scan of n items in `bsum` (tile states), zeroes
+// before it starts; a caller that zeroes them beforehand passes zeroed = true.
+uint32_t* sort_counters(void* ws, int64_t n_max, uint32_t* count);
+uint32_t* scan_states(unsigned long long* bsum, int64_t n, uint32_t* count);
 
 // Stable LSD radix sort of (key, value) u32 pairs on bits [0, nbits), at
 // most 32 bits.  The first pass reads kin/vin (vin NULL: value = position),
@@ -330,14 +343,15 @@ struct SortGather {
 size_t radix_ws_bytes(int64_t n_max);
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
                      const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
-                     const SortGather* last = nullptr);
+                     const SortGather* last = nullptr, bool zeroed = false);
 // The records' depth sort with the packed-rectangle payload (g.pay_in,
 // g.pay_buf): 9-bit digits over the keys relative to the live depth range
 // (from krange: n_part pairs (max ~key, max key) over live keys),
 // only the passes the range needs; results in kbuf/vbuf[1], g.rect_out and
 // g.cnt_out.  Returns 1.
 int radix_sort_depth(const uint32_t* kin, const uint32_t* krange, int64_t n_part, uint32_t* kbuf[2], uint32_t* vbuf[2],
-                     int64_t n, void* ws, hipStream_t st, hipError_t* err, const SortGather& g);
+                     int64_t n, void* ws, hipStream_t st, hipError_t* err, const SortGather& g,
+                     bool zeroed = false);
 // Look-back waits of the radix passes that hit their bound on the current
 // device since the library was loaded (synchronous read; 0 expected).
 uint32_t sort_stalls();
@@ -357,6 +371,7 @@ hipError_t tile_ranges(const uint32_t* sorted_tile, const unsigned long long* n_
 hipError_t tile_ranges16(const uint16_t* sorted_tile, const unsigned long long* n_dev, int64_t n_max,
                          int64_t n_tiles, uint32_t* ranges, hipStream_t st);
 int radix_sort_pairs16(const uint16_t* kin, const uint32_t* vin, uint16_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
-                       const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err);
+                       const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
+                       bool zeroed = false);
 
 }  // namespace cgs

@@ -16,8 +16,16 @@ __global__ __launch_bounds__(256) void k_preprocess(const BatchDesc* __restrict_
                                                     float4* __restrict__ rec, uint32_t* __restrict__ depth_key,
                                                     uint2* __restrict__ tile_rect, uint32_t* __restrict__ ntiles,
                                                     uint32_t* __restrict__ prect, uint32_t* __restrict__ chunk_tot,
-                                                    uint32_t* __restrict__ krange, uint32_t* __restrict__ rec_flag) {
+                                                    uint32_t* __restrict__ krange, uint32_t* __restrict__ rec_flag,
+                                                    ZeroSpans zero) {
     constexpr int NCO = (SHD + 1) * (SHD + 1);
+    {   // the counters the sorts and scans of the binning start from
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)zero.n[s]; i += stride)
+                zero.p[s][i] = 0u;
+    }
     const int64_t wv = wave_id(4);
     if (wv >= desc->n_gauss_waves) return;
     const SceneDesc& sd = desc->scenes[find_scene_by_wave(desc, wv)];
@@ -410,10 +418,16 @@ __global__ __launch_bounds__(WPB * 64) void k_blend_fwd(const BatchDesc* __restr
 // ------------------------------------------------------------------ launchers
 hipError_t launch_preprocess(const BatchDesc* d_desc, int dtype, int shd, int64_t n_gauss_waves, float4* rec,
                              uint32_t* dk, uint2* tr, uint32_t* nt, uint32_t* prect, uint32_t* chunk_tot,
-                             uint32_t* krange, uint32_t* rec_flag, hipStream_t st) {
-    if (n_gauss_waves <= 0) return hipSuccess;
+                             uint32_t* krange, uint32_t* rec_flag, const ZeroSpans& zero, hipStream_t st) {
+    if (n_gauss_waves <= 0) {       // no preprocess launch: zero the spans by fills
+        for (int s = 0; s < 4; ++s) {
+            const hipError_t e = fill_u32(zero.p[s], 0u, zero.n[s], st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
-#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot, krange, rec_flag)
+#define CGS_PRE(DT, SHD) hipLaunchKernelGGL((k_preprocess<DT, SHD>), grid, blk, 0, st, d_desc, rec, dk, tr, nt, prect, chunk_tot, krange, rec_flag, zero)
     if (dtype == CGS_F32) {
         switch (shd) { case 0: CGS_PRE(CGS_F32, 0); break; case 1: CGS_PRE(CGS_F32, 1); break;
                        case 2: CGS_PRE(CGS_F32, 2); break; default: CGS_PRE(CGS_F32, 3); break; }

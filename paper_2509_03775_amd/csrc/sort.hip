@@ -144,16 +144,16 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_down(const uint32_t* in, co
 }
 
 hipError_t scan_onepass(const uint32_t* in, int64_t n, uint32_t* out, unsigned long long* total,
-                        unsigned long long* bsum, hipStream_t st);
+                        unsigned long long* bsum, hipStream_t st, bool zeroed);
 
 hipError_t scan_u32(const uint32_t* in, const uint32_t* perm, int64_t n, uint32_t* out,
-                    unsigned long long* total, unsigned long long* bsum, hipStream_t st) {
+                    unsigned long long* total, unsigned long long* bsum, hipStream_t st, bool zeroed) {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     if (nb == 0) {
         if (total) hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bsum, (int64_t)0, total);
         return hipGetLastError();
     }
-    if (!perm) return scan_onepass(in, n, out, total, bsum, st);
+    if (!perm) return scan_onepass(in, n, out, total, bsum, st, zeroed);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kSortBlock), 0, st, in, perm, n, bsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bsum, nb, total);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kSortBlock), 0, st, in, perm, n, bsum, out);
@@ -379,10 +379,15 @@ __global__ __launch_bounds__(kOsThreads) void k_scan_1p(const uint32_t* in, int6
     }
 }
 
+uint32_t* scan_states(unsigned long long* bsum, int64_t n, uint32_t* count) {
+    *count = (uint32_t)(2 * ((n + kScanTile - 1) / kScanTile + 1));
+    return reinterpret_cast<uint32_t*>(bsum);
+}
+
 hipError_t scan_onepass(const uint32_t* in, int64_t n, uint32_t* out, unsigned long long* total,
-                        unsigned long long* bsum, hipStream_t st) {
+                        unsigned long long* bsum, hipStream_t st, bool zeroed) {
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipError_t e = fill_u32(bsum, 0u, 2 * (size_t)(nb + 1), st);
+    hipError_t e = zeroed ? hipSuccess : fill_u32(bsum, 0u, 2 * (size_t)(nb + 1), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_scan_1p, dim3((unsigned)nb), dim3(kOsThreads), 0, st, in, n, out, total, bsum);
     return hipGetLastError();
@@ -407,6 +412,11 @@ SortWs sort_ws(void* ws, int64_t n_max) {
     s.tickets = s.ghist + 4 * kMaxBins;
     s.range = s.tickets + 4;
     return s;
+}
+
+uint32_t* sort_counters(void* ws, int64_t n_max, uint32_t* count) {
+    *count = (uint32_t)(4 * kMaxBins + 6);
+    return sort_ws(ws, n_max).ghist;
 }
 
 size_t radix_ws_bytes(int64_t n_max) {
@@ -680,7 +690,7 @@ __global__ __launch_bounds__(kOsThreads) void k_os_pass(const KT* keys_in, const
 template <typename KT>
 int radix_sort_impl(const KT* kin, const uint32_t* vin, KT* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
                     const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
-                    const SortGather* last) {
+                    const SortGather* last, bool zeroed) {
     *err = hipSuccess;
     constexpr int IT = os_items<KT>();
     constexpr int64_t TILE = IT * kOsThreads;
@@ -690,7 +700,7 @@ int radix_sort_impl(const KT* kin, const uint32_t* vin, KT* kbuf[2], uint32_t* v
     if (nblocks == 0 || nbits <= 0) return final_buf;
     if (passes > 4) { *err = hipErrorInvalidValue; return final_buf; }
     const SortWs s = sort_ws(ws, n_max);
-    *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
+    if (!zeroed) *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
     if (*err != hipSuccess) return final_buf;
     const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
     hipLaunchKernelGGL((k_os_hist<kRadixBits, false, KT, IT>), dim3(hb), dim3(kOsThreads), 0, st, kin, n_max, n_dev,
@@ -731,26 +741,27 @@ int radix_sort_impl(const KT* kin, const uint32_t* vin, KT* kbuf[2], uint32_t* v
 
 int radix_sort_pairs(const uint32_t* kin, const uint32_t* vin, uint32_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
                      const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
-                     const SortGather* last) {
-    return radix_sort_impl<uint32_t>(kin, vin, kbuf, vbuf, n_max, n_dev, nbits, ws, st, err, last);
+                     const SortGather* last, bool zeroed) {
+    return radix_sort_impl<uint32_t>(kin, vin, kbuf, vbuf, n_max, n_dev, nbits, ws, st, err, last, zeroed);
 }
 
 int radix_sort_pairs16(const uint16_t* kin, const uint32_t* vin, uint16_t* kbuf[2], uint32_t* vbuf[2], int64_t n_max,
-                       const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err) {
+                       const unsigned long long* n_dev, int nbits, void* ws, hipStream_t st, hipError_t* err,
+                       bool zeroed) {
     if (nbits > 16) { *err = hipErrorInvalidValue; return 0; }
-    return radix_sort_impl<uint16_t>(kin, vin, kbuf, vbuf, n_max, n_dev, nbits, ws, st, err, nullptr);
+    return radix_sort_impl<uint16_t>(kin, vin, kbuf, vbuf, n_max, n_dev, nbits, ws, st, err, nullptr, zeroed);
 }
 
 // The depth sort of the records (31-bit keys, +inf for culled records) with
 // the packed-rectangle payload: the result is in kbuf/vbuf[1] and g's
 // rectangle and count arrays whatever the number of passes the range takes.
 int radix_sort_depth(const uint32_t* kin, const uint32_t* krange, int64_t n_part, uint32_t* kbuf[2], uint32_t* vbuf[2],
-                     int64_t n, void* ws, hipStream_t st, hipError_t* err, const SortGather& g) {
+                     int64_t n, void* ws, hipStream_t st, hipError_t* err, const SortGather& g, bool zeroed) {
     *err = hipSuccess;
     const int64_t nblocks = (n + kOsTile - 1) / kOsTile;
     if (nblocks == 0) return 1;
     const SortWs s = sort_ws(ws, n);
-    *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
+    if (!zeroed) *err = fill_u32(s.ghist, 0u, 4 * kMaxBins + 6, st);
     if (*err != hipSuccess) return 1;
     const unsigned hb = (unsigned)std::min<int64_t>(nblocks, kOsHistBlocks);
     const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_part + 255) / 256, 256));
