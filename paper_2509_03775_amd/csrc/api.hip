@@ -30,11 +30,11 @@ hipError_t launch_blend_bwd(const BatchDesc*, int64_t, int, bool, const uint32_t
                             const int32_t*, float*, uint2*, DevCounters*, hipStream_t);
 hipError_t launch_slot_sum(const BatchDesc*, int64_t, const float*, const uint32_t*, const uint32_t*, const uint2*,
                            const uint32_t*, const uint32_t*, const uint2*, const DevCounters*, float*, uint32_t*,
-                           hipStream_t);
+                           uint32_t*, int64_t, hipStream_t);
 hipError_t launch_chain(const BatchDesc*, int, int, int64_t, const float*, const uint32_t*, float*, uint32_t*,
                         const uint32_t*, const uint32_t*, const uint32_t*, float*, hipStream_t);
 hipError_t launch_merge_rows(const BatchDesc*, int64_t, const uint32_t*, const uint32_t*, const float*, const float*,
-                             const uint32_t*, int, hipStream_t);
+                             const uint32_t*, hipStream_t);
 hipError_t launch_row_keys(const BatchDesc*, int, int64_t, uint32_t*, hipStream_t);
 hipError_t launch_reduce(const BatchDesc*, int, const float*, int64_t, int, int, int, const uint32_t*,
                          const uint32_t*, int64_t, int64_t, const uint32_t*, hipStream_t);
@@ -682,8 +682,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
     uint32_t* islf = at<uint32_t>(ws, p.isl_flag);
     CGS_TRY(launch_slot_sum(dd, h.d.n_rec_waves, ginst, at<uint32_t>(ws, p.chunk_base), at<uint32_t>(ws, p.ntiles),
                             at<uint2>(ws, p.tile_rect), at<uint32_t>(ws, p.prect), at<uint32_t>(ws, p.depth_key),
-                            at<uint2>(ws, p.tile_cut), cnt,
-                            rgrad, rflag, st));
+                            at<uint2>(ws, p.tile_cut), cnt, rgrad, rflag, islf, h.d.n_gauss_waves, st));
     if (single) {
         // Single codebook: the chain rule walks the Gaussians in row order and
         // reduces the rows itself, in the order the forward sorted (the
@@ -692,8 +691,7 @@ cgs_status backward_impl(const cgs_batch* batch, const float* grad_image, const 
         CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, rgrad, rflag, gth, islf,
                              pk[pb], pv[pb], rr, at<float>(ws, p.rpart), st));
         CGS_TRY(mark(h, 6, st));
-        CGS_TRY(launch_merge_rows(dd, h.d.sr_rows_total, pv[pb], rr, at<float>(ws, p.rpart), gth, islf,
-                                  h.d.row_width, st));
+        CGS_TRY(launch_merge_rows(dd, h.d.sr_rows_total, pv[pb], rr, at<float>(ws, p.rpart), gth, islf, st));
     } else {
         CGS_TRY(launch_chain(dd, h.d.dtype, h.d.sh_degree, h.d.n_gauss_waves, rgrad, rflag, gth, islf,
                              nullptr, nullptr, nullptr, nullptr, st));

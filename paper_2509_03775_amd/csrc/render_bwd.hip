@@ -267,8 +267,12 @@ __global__ __launch_bounds__(256) void k_slot_sum(const BatchDesc* __restrict__ 
                                                   const uint32_t* __restrict__ depth_key,
                                                   const uint2* __restrict__ tile_cut,
                                                   const DevCounters* __restrict__ cnt, float* __restrict__ rec_grad,
-                                                  uint32_t* __restrict__ rec_flag) {
+                                                  uint32_t* __restrict__ rec_flag, uint32_t* __restrict__ isl_flag,
+                                                  int64_t n_isl) {
     __shared__ uint32_t s_start[4][64], s_so[4][64], s_key[4][64], s_org[4][64], s_w[4][64], s_mark[4][64];
+    // the chain rule's island flag words start from zero
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_isl; i += (int64_t)gridDim.x * blockDim.x)
+        isl_flag[i] = 0u;
     __shared__ float s_v[4][9][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t wv = wave_id(4);
@@ -1077,10 +1081,16 @@ __global__ __launch_bounds__(256) void k_merge_rows(const BatchDesc* __restrict_
     if (r >= desc->sr_rows_total) return;
     const int RW = desc->row_width;
     const int64_t rs = row_range[2 * r], re = row_range[2 * r + 1];
-    if (rs == re) return;                                   // k_reduce_empty
     int64_t lr;
     int sc;
     const RowOut o = row_out(desc, 0, r, &lr, &sc);
+    if (rs == re) {                                         // no Gaussian maps to the row: zero gradient
+        if (lane < RW) {
+            o.ptr[lr * o.stride + o.col0 + lane] = 0.f;
+            if (desc->sgld) sgld_row(desc, sc, lr, lane, 0.f);
+        }
+        return;
+    }
     // the row's positions lie in its scene's range: wavefronts of that scene
     const SceneDesc& sd = desc->scenes[sc];
     const int64_t w0 = sd.wave_off + ((rs - sd.g_off) >> 6), w1 = sd.wave_off + ((re - 1 - sd.g_off) >> 6);
@@ -1398,10 +1408,12 @@ hipError_t launch_blend_bwd(const BatchDesc* d_desc, int64_t n_tiles, int wpb, b
 
 hipError_t launch_slot_sum(const BatchDesc* d_desc, int64_t n_rec_waves, const float* ginst, const uint32_t* eo,
                            const uint32_t* nt, const uint2* tr, const uint32_t* prect, const uint32_t* dk,
-                           const uint2* cut, const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag, hipStream_t st) {
-    if (n_rec_waves > 0)
-        hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
-                           nt, tr, prect, dk, cut, cnt, rec_grad, rec_flag);
+                           const uint2* cut, const DevCounters* cnt, float* rec_grad, uint32_t* rec_flag,
+                           uint32_t* isl_flag, int64_t n_gauss_waves, hipStream_t st) {
+    const int64_t n_isl = 2 * n_gauss_waves + 1;       // zeroed here for the chain rule
+    if (n_rec_waves <= 0) return fill_u32(isl_flag, 0u, (size_t)n_isl, st);
+    hipLaunchKernelGGL(k_slot_sum, dim3((unsigned)((n_rec_waves + 3) / 4)), dim3(256), 0, st, d_desc, ginst, eo,
+                       nt, tr, prect, dk, cut, cnt, rec_grad, rec_flag, isl_flag, n_isl);
     return hipGetLastError();
 }
 
@@ -1413,8 +1425,7 @@ hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_g
                         const uint32_t* skey, const uint32_t* sval, const uint32_t* row_range, float* rpart,
                         hipStream_t st) {
     if (n_gauss_waves <= 0) return hipGetLastError();
-    hipError_t e = fill_u32(isl_flag, 0u, (size_t)(2 * n_gauss_waves + 1), st);
-    if (e != hipSuccess) return e;
+    // isl_flag: zeroed by the record-gradient sums just before
     dim3 grid((unsigned)((n_gauss_waves + 3) / 4)), blk(256);
     dim3 grid64((unsigned)((2 * n_gauss_waves + 255) / 256));
 #define CGS_CH(DT, SHD)                                                                                     \
@@ -1439,14 +1450,10 @@ hipError_t launch_chain(const BatchDesc* d_desc, int dtype, int shd, int64_t n_g
 }
 
 hipError_t launch_merge_rows(const BatchDesc* d_desc, int64_t n_rows, const uint32_t* sval, const uint32_t* row_range,
-                             const float* rpart, const float* gtheta, const uint32_t* isl_flag, int D,
-                             hipStream_t st) {
+                             const float* rpart, const float* gtheta, const uint32_t* isl_flag, hipStream_t st) {
     if (n_rows > 0)
         hipLaunchKernelGGL(k_merge_rows, dim3((unsigned)((n_rows + 3) / 4)), dim3(256), 0, st, d_desc, sval,
                            row_range, rpart, gtheta, isl_flag);
-    if (n_rows * D > 0)
-        hipLaunchKernelGGL(k_reduce_empty, dim3((unsigned)((n_rows * D + 255) / 256)), dim3(256), 0, st, d_desc, 0, 0,
-                           D, 0, n_rows, row_range);
     return hipGetLastError();
 }
 
