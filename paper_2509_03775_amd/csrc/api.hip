@@ -308,11 +308,9 @@ cgs_status hip_status(hipError_t e) { return e == hipSuccess ? CGS_OK : CGS_EHIP
 hipError_t upload_desc(const Host& h, void* ws, hipStream_t st) {
     char* base = static_cast<char*>(ws) + h.p.desc;
     const size_t head = offsetof(BatchDesc, views) + sizeof(ViewDesc) * (size_t)h.d.n_views;
-    hipError_t e = upload_bytes(base, &h.d, head, st);
-    if (e != hipSuccess) return e;
     const size_t so = offsetof(BatchDesc, scenes);
-    return upload_bytes(base + so, reinterpret_cast<const char*>(&h.d) + so, sizeof(SceneDesc) * (size_t)h.d.n_scenes,
-                        st);
+    return upload_two(base, &h.d, head, base + so, reinterpret_cast<const char*>(&h.d) + so,
+                      sizeof(SceneDesc) * (size_t)h.d.n_scenes, st);
 }
 
 hipError_t mark(const Host& h, int i, hipStream_t st) {

@@ -299,6 +299,10 @@ __device__ inline int find_view_by_rec(const BatchDesc* d, int64_t r) {
 // ------------------------------------------------------------- launchers
 // (defined in the .hip files; all enqueue on `st` and never synchronise)
 hipError_t upload_bytes(void* dst, const void* src, size_t n, hipStream_t st);
+// Two byte ranges (whole words each) uploaded by one launch when they fit
+// 2 KB together, else by upload_bytes each.
+hipError_t upload_two(void* dst_a, const void* src_a, size_t na, void* dst_b, const void* src_b, size_t nb,
+                      hipStream_t st);
 hipError_t fill_u32(void* dst, uint32_t value, size_t count, hipStream_t st);
 
 // Exclusive scan of n u32 values read through `perm` (NULL = identity):

@@ -24,6 +24,39 @@ __global__ void k_upload(uint32_t* dst, UploadChunk c, int nwords) {
     if (t < nwords) dst[t] = c.words[t];
 }
 
+// Two destinations in one launch: words [0, na) to a, [na, nw) to b.
+struct UploadPair {
+    uint32_t words[512];
+};
+
+__global__ void k_upload2(uint32_t* a, uint32_t* b, UploadPair c, int na, int nw) {
+    for (int t = threadIdx.x; t < nw; t += blockDim.x) {
+        if (t < na) a[t] = c.words[t];
+        else b[t - na] = c.words[t];
+    }
+}
+
+// Whole words of src (n a multiple of 4) into c.words from position at.
+static void pack_words(UploadPair& c, size_t at, const void* src, size_t n) {
+    __builtin_memcpy(&c.words[at], src, n);
+}
+
+hipError_t upload_two(void* dst_a, const void* src_a, size_t na, void* dst_b, const void* src_b, size_t nb,
+                      hipStream_t st) {
+    const size_t wa = na / 4, wb = nb / 4;
+    if (na % 4 != 0 || nb % 4 != 0 || wa + wb > 512) {
+        hipError_t e = upload_bytes(dst_a, src_a, na, st);
+        return e == hipSuccess ? upload_bytes(dst_b, src_b, nb, st) : e;
+    }
+    if (wa + wb == 0) return hipSuccess;
+    UploadPair c;
+    pack_words(c, 0, src_a, na);
+    pack_words(c, wa, src_b, nb);
+    hipLaunchKernelGGL(k_upload2, dim3(1), dim3(256), 0, st, static_cast<uint32_t*>(dst_a),
+                       static_cast<uint32_t*>(dst_b), c, (int)wa, (int)(wa + wb));
+    return hipGetLastError();
+}
+
 hipError_t upload_bytes(void* dst, const void* src, size_t n, hipStream_t st) {
     const uint32_t* s = static_cast<const uint32_t*>(src);
     uint32_t* d = static_cast<uint32_t*>(dst);
