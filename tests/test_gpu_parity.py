@@ -216,6 +216,49 @@ def test_schedule_invariance(kind):
                 np.testing.assert_array_equal(a, b)
 
 
+def test_fused_scene_split_gradient_layout():
+    """One shared codebook whose gradient is asked for as two blocks (the SR
+    columns and the SH columns in separate arrays): the backward takes the
+    two-codebook path (chain rule in Gaussian order, one row sort and
+    reduction per block) after a forward that already ordered the Gaussians
+    by row for the fused path.  Mean gradients are the same arithmetic in
+    both kernels, so bitwise equal; the blocks equal the fused codebook
+    gradient up to the order of the row sums; a fused-layout backward after
+    it still reads the forward's row order and repeats the first one bit for
+    bit."""
+    wl = small_workload("clusters20k_d3")
+    say("[split gradient layout] clusters20k_d3")
+    r = gpu_renderer(wl)
+    g = torch.from_numpy(np.random.default_rng(8).standard_normal((r.n_pixels, 3)).astype(np.float32) * 1e-5).cuda()
+    r.forward()
+    gm, gcb = r.backward(g)
+    torch.cuda.synchronize()
+    gm0, gcb0 = gm[0].cpu().numpy().copy(), gcb[0].cpu().numpy().copy()
+    s = r.scenes[0]
+    gsr = torch.full((s.k, 8), float("nan"), dtype=torch.float32, device="cuda")
+    gsh = torch.full((s.k, s.r - 8), float("nan"), dtype=torch.float32, device="cuda")
+    d = r._grads[0]
+    saved = (d.sr, d.sr_stride, d.sr_col0, d.sh, d.sh_stride, d.sh_col0)
+    d.sr, d.sr_stride, d.sr_col0 = gsr.data_ptr(), 8, 0
+    d.sh, d.sh_stride, d.sh_col0 = gsh.data_ptr(), s.r - 8, 0
+    try:
+        gm, _ = r.backward(g)
+        torch.cuda.synchronize()
+        gm1 = gm[0].cpu().numpy().copy()
+    finally:
+        d.sr, d.sr_stride, d.sr_col0, d.sh, d.sh_stride, d.sh_col0 = saved
+    np.testing.assert_array_equal(gm1, gm0)
+    split = np.concatenate([gsr.cpu().numpy(), gsh.cpu().numpy()], 1)
+    assert np.isfinite(split).all()
+    e = rel_l2(split, gcb0)
+    say(f"  split vs fused codebook gradient rel L2 {e:.2e}")
+    assert e <= 1e-5
+    gm, gcb = r.backward(g)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(gm[0].cpu().numpy(), gm0)
+    np.testing.assert_array_equal(gcb[0].cpu().numpy(), gcb0)
+
+
 def _bin_inputs(seed, n, tx, ty, V, ties=True):
     rng = np.random.default_rng(seed)
     if ties:
