@@ -1070,7 +1070,8 @@ __global__ __launch_bounds__(256) void k_chain_rows(const BatchDesc* __restrict_
 // The rows k_chain_rows left partial: a row spanning several wavefronts
 // (head or tail partial of each, summed in wavefront order) or holding
 // island Gaussians (their FP64 rows, written to gtheta by k_chain_fp64, added
-// in position order).  One wavefront per row, lanes over columns.
+// in position order); and the rows no Gaussian maps to (a zero gradient, and
+// their SGLD update).  One wavefront per row, lanes over columns.
 __global__ __launch_bounds__(256) void k_merge_rows(const BatchDesc* __restrict__ desc,
                                                     const uint32_t* __restrict__ sval,
                                                     const uint32_t* __restrict__ row_range,
